@@ -1,0 +1,213 @@
+"""Benchmark: bulk build to 95% load, lookups, deletes and re-lookups on one MI355X.
+
+Workload (one step): a FIXED-addressing table of 4,415,057 buckets x 16
+slots (70,640,912 slots) is cleared, then
+  insert   2^26 unique uniform keys (values = lo32(splitmix64(key)))  -> 95% load
+  lookup   2^26 keys, 50% present
+  delete   2^25 of the inserted keys
+  lookup   the same 2^26 keys again (25% present)
+= 3.5 * 2^26 = 234,881,024 operations.  Inputs sit in HBM before timing.
+
+Prints one JSON line.  `value` is whole-step throughput in Mops/s; per-phase
+rates, the roofline of the dominant kernel (the lookup kernel) and the CPU
+oracle on a bounded sample are reported beside it.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mops/s insert/lookup/mixed @95% LF vs plain launch; served p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+BUCKET_BYTES = 128  # 16 slots x 8 B: one line per bucket touch
+N_KEYS = 1 << 26
+LOAD = 0.95
+S = 16
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--keys-log2", type=int, default=26)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-log2", type=int, default=22)
+    return ap.parse_args()
+
+
+def source_digest() -> str:
+    h = hashlib.sha256()
+    for f in ("hive.hip", "hive_device.hpp"):
+        with open(os.path.join(ROOT, "paper_2510_15095_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def cpu_baseline(log2n: int) -> dict:
+    """The CPU oracle (sequential Hive model, single thread) on the same
+    sequence at 2^log2n keys."""
+    import oracle
+    from paper_2510_15095_amd import workload as wl
+    n = 1 << log2n
+    w = wl.bulk_workload(2, n)
+    nb = int(np.ceil(n / (LOAD * S)))
+    o = oracle.O2(S, 8, max(1024, nb * S // 100), oracle.ADDR_FIXED, nb)
+    t0 = time.perf_counter()
+    o.insert(w["ins_keys"], w["ins_vals"])
+    o.lookup(w["query_keys"])
+    o.delete(w["del_keys"])
+    o.lookup(w["query_keys"])
+    dt = time.perf_counter() - t0
+    ops = 3.5 * n
+    return {"value": round(ops / dt / 1e6, 3), "unit": "Mops/s", "cores": 1, "kind": "oracle",
+            "sample": f"same sequence at 2^{log2n} keys ({nb} buckets, 95% load), {dt:.1f} s single-threaded"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2510_15095_amd import hive as H
+    from paper_2510_15095_amd import workload as wl
+
+    n = 1 << args.keys_log2
+    nb = int(np.ceil(n / (LOAD * S)))
+    w = wl.bulk_workload(2, n)
+    dev = torch.device("cuda:0")
+    keys = torch.from_numpy(w["ins_keys"]).to(dev)
+    vals = torch.from_numpy(w["ins_vals"]).to(dev)
+    qk = torch.from_numpy(w["query_keys"]).to(dev)
+    dk = torch.from_numpy(w["del_keys"]).to(dev)
+    vout = torch.empty(n, dtype=torch.uint32, device=dev)
+    fout = torch.empty(n, dtype=torch.uint8, device=dev)
+    dout = torch.empty(dk.numel(), dtype=torch.uint8, device=dev)
+    t = H.Table(nb, slots_per_bucket=S, max_evictions=8, max_batch=n)
+    n_present = int((w["query_idx"] < n).sum())
+    deleted = np.zeros(n, bool)
+    deleted[w["del_idx"]] = True
+    qi = w["query_idx"]
+    n_present2 = int(((qi < n) & ~deleted[np.minimum(qi, n - 1)]).sum())
+    del w
+
+    phases = ("clear", "insert", "lookup", "delete", "lookup2")
+
+    def step(ev):
+        ev[0].record()
+        t.clear()
+        ev[1].record()
+        t.insert(keys, vals, flags=H.HIVE_UNIQUE)
+        ev[2].record()
+        H.hive_lookup_batch(t.h, qk, vout, fout)
+        ev[3].record()
+        H.hive_delete_batch(t.h, dk, dout, H.HIVE_UNIQUE)
+        ev[4].record()
+        H.hive_lookup_batch(t.h, qk, vout, fout)
+        ev[5].record()
+
+    mk = lambda: [torch.cuda.Event(enable_timing=True) for _ in range(6)]  # noqa: E731
+    for _ in range(args.warmup):
+        step(mk())
+    torch.cuda.synchronize()
+    # placement census after a full build (untimed): lookups of present keys
+    # touch one bucket when the key sits in its first candidate, two otherwise
+    t.clear()
+    t.insert(keys, vals, flags=H.HIVE_UNIQUE)
+    first, second, overflow = t.placement()
+    st_build = t.stats()
+    frac_second = second / max(1, first + second + overflow)
+
+    evs = [mk() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for ev in evs:
+        step(ev)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = np.array([[ev[j].elapsed_time(ev[j + 1]) for j in range(5)] for ev in evs])
+    st = t.stats()
+    ops_step = n + n + dk.numel() + n
+    ms_step = float(ms.sum(axis=1).mean())
+
+    # roofline of the lookup kernel: algorithmic bytes per launch =
+    # hits * 128 * (1 + f_second) + misses * 256 (both candidates) + 9 B of I/O
+    # per operation (key in, value and found flag out)
+    def lookup_bytes(hits):
+        misses = n - hits
+        return hits * BUCKET_BYTES * (1 + frac_second) + misses * 2 * BUCKET_BYTES + 9 * n
+    lk_ms = (ms[:, 2].mean() + ms[:, 4].mean()) / 2
+    lk_bytes = (lookup_bytes(n_present) + lookup_bytes(n_present2)) / 2
+    achieved = lk_bytes / (lk_ms * 1e-3) / 1e9
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", "lookup_bulk95_traffic.json")
+    if os.path.exists(tfile):
+        rec = json.load(open(tfile))
+        if rec.get("source_digest") == source_digest():
+            traffic = rec.get("bytes_per_launch")
+
+    phase_mops = {
+        "insert": n / (ms[:, 1].mean() * 1e-3) / 1e6,
+        "lookup": n / (ms[:, 2].mean() * 1e-3) / 1e6,
+        "delete": dk.numel() / (ms[:, 3].mean() * 1e-3) / 1e6,
+        "lookup2": n / (ms[:, 4].mean() * 1e-3) / 1e6,
+    }
+    out = {
+        "metric": METRIC,
+        "value": round(ops_step / (ms_step * 1e-3) / 1e6, 1),
+        "unit": "Mops/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"bulk build to 95% load, plain launch: 2^{args.keys_log2} unique uniform keys into "
+                        f"{nb} x {S}-slot buckets (FIXED), 2^{args.keys_log2} lookups at 50% hits, delete "
+                        f"2^{args.keys_log2 - 1}, re-lookup",
+            "ops_per_step": ops_step,
+            "load_factor": round(n / (nb * S), 6),
+        },
+        "phase_mops": {k: round(v, 1) for k, v in phase_mops.items()},
+        "phase_ms": {p: round(float(ms[:, j].mean()), 4) for j, p in enumerate(phases)},
+        "wall_ms_per_step": round(wall / args.steps * 1e3, 4),
+        "build_stats": {k: st_build[k] for k in ("evictions", "evict_items", "stash_count", "pending_count",
+                                                 "full_chains")},
+        "placement": {"first": first, "second": second, "overflow": overflow},
+        "roofline": {
+            "kernel": "ops_kernel<16, lookup>",
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": round(lk_bytes),
+            "avg_launch_ms": round(float(lk_ms), 4),
+            "one_touch_frac": round(n / (lk_ms * 1e-3) / (HBM_PEAK_GBS * 1e9 / BUCKET_BYTES), 4),
+        },
+        "status": st["status"],
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_sample_log2)
+    t.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

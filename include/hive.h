@@ -1,0 +1,197 @@
+/* hive.h -- C ABI of an MI355X (gfx950) implementation of the Hive hash table
+ * (Polak, Troendle, Jang, "Hive Hash Table: A Warp-Cooperative, Dynamically
+ * Resizable Hash Table for GPUs", arXiv 2510.15095).
+ *
+ * The table maps 32-bit keys to 32-bit values.  Each entry is one 64-bit word,
+ * value in the high half and key in the low half (Section III-A), stored in
+ * buckets of S slots (Section III-B).  Keys 0 and 0xFFFFFFFF are reserved:
+ * operations on them are no-ops that report "absent" and are counted in
+ * hive_stats_t.invalid_keys.
+ *
+ * Conventions for every call below:
+ *   - Pointers named d_* are device memory owned by the caller.  They must
+ *     stay valid until the stream reaches the call.  The table owns all of its
+ *     own memory (buckets, stash, pending list, worklists, scratch).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Batch calls only enqueue work and return; hive_create, hive_stats,
+ *     hive_dump and hive_destroy synchronize the stream.
+ *   - One handle must not be used from two host threads, or from two streams
+ *     that are not ordered with each other, at the same time.  Different
+ *     handles are independent.
+ *   - Argument errors are returned at once (negative status) and nothing is
+ *     enqueued.  Conditions found on the device (a full pending list, reserved
+ *     keys) are latched and returned by the next hive_stats call.
+ *   - A batch call is applied as if its operations ran one at a time in index
+ *     order, provided the caller keeps the contract stated at each call.
+ */
+#ifndef HIVE_H
+#define HIVE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hive_table *hive_t;
+
+typedef enum {
+  HIVE_OK = 0,
+  HIVE_ERR_ARG = -1,      /* invalid argument; nothing was enqueued */
+  HIVE_ERR_OOM = -2,      /* device allocation failed */
+  HIVE_ERR_HIP = -3,      /* a HIP runtime call failed */
+  HIVE_ERR_BUDGET = -4,   /* the bucket arena or a fixed capacity is exhausted */
+  HIVE_ERR_LOST = -5,     /* the pending list overflowed: entries were lost */
+  HIVE_WARN_INVALID_KEYS = 1, /* reserved keys were seen (they were no-ops) */
+  HIVE_WARN_PENDING = 2       /* entries wait in the pending list (data intact) */
+} hive_status;
+
+/* Bucket addressing.  FIXED reduces the mixed hash modulo the bucket count,
+ * as the BitHash listing does (Section III-C); LINEAR uses the linear-hashing
+ * index mask and split pointer (Section IV-C) and allows hive_resize. */
+enum { HIVE_FIXED = 0, HIVE_LINEAR = 1 };
+
+/* Flags for batch calls. */
+enum {
+  HIVE_UNIQUE = 1u /* caller promises no key repeats among the batch's inserts
+                      and none among its deletes: skips the dedupe pass */
+};
+
+/* Op codes for hive_mixed_batch. */
+enum { HIVE_OP_INSERT = 0, HIVE_OP_DELETE = 1, HIVE_OP_LOOKUP = 2 };
+
+typedef struct {
+  uint32_t slots_per_bucket;  /* S: 16 (one 128-byte line) or 64 */
+  uint32_t max_evictions;     /* bound on cuckoo displacements per insert
+                                 (Section III-B "Global Metadata"); default 8 */
+  uint64_t stash_capacity;    /* overflow stash entries (Section IV-A step 4);
+                                 0 = max(1024, 1% of the initial slots) */
+  uint64_t pending_capacity;  /* entries beyond a full stash; 0 = stash_capacity */
+  uint32_t addressing;        /* HIVE_FIXED or HIVE_LINEAR */
+  uint32_t resize_k;          /* K: bucket pairs per split/merge step (Section
+                                 IV-C); default 1024 */
+  uint32_t lf_expand_pct;     /* expand when live > pct% of slots; default 90 */
+  uint32_t lf_contract_pct;   /* contract when live < pct% of slots; default 25 */
+  uint32_t pre_expand;        /* 1: before each insert batch of n inserts, grow
+                                 until live + n fits under lf_expand_pct */
+  uint32_t post_policy;       /* 1: after each batch apply the expand/contract
+                                 rule (LINEAR tables) */
+  uint64_t max_buckets;       /* bucket arena reserved at create (LINEAR:
+                                 growth headroom; 0 = initial buckets) */
+  uint64_t max_batch;         /* scratch preallocated for batches of this many
+                                 operations (0 = grow on demand) */
+} hive_config;
+
+typedef struct {
+  uint64_t live;            /* number of keys stored */
+  uint64_t n_buckets;       /* current bucket count */
+  uint64_t index_mask;      /* LINEAR: 2^m - 1 of the current round */
+  uint64_t split_ptr;       /* LINEAR: buckets of this round already split */
+  uint64_t stash_count;     /* stash ring entries in use (incl. deleted ones) */
+  uint64_t pending_count;   /* pending entries in use (incl. deleted ones) */
+  uint64_t evictions;       /* cuckoo displacements (Section IV-A step 3) */
+  uint64_t stash_inserts;   /* entries that entered the stash */
+  uint64_t pending_inserts; /* entries that entered the pending list */
+  uint64_t full_chains;     /* inserts whose eviction chain ran all rounds */
+  uint64_t invalid_keys;    /* operations on reserved keys */
+  uint64_t evict_items;     /* inserts that needed step 3 (worklist items) */
+  uint64_t bytes_reserved;  /* device bytes owned by the table */
+  uint64_t slots_per_bucket;
+  uint64_t max_buckets;
+  uint64_t error_bits;      /* latched device conditions */
+} hive_stats_t;
+
+/* Fill *cfg with the defaults named above (S = 16, FIXED addressing). */
+hive_status hive_config_default(hive_config *cfg);
+
+/* Create a table with `initial_buckets` empty buckets (Section III-B).
+ * LINEAR tables reserve max(cfg->max_buckets, initial_buckets) buckets of
+ * arena up front, so growth never allocates.  Synchronizes `stream`. */
+hive_status hive_create(const hive_config *cfg, uint64_t initial_buckets, void *stream, hive_t *out);
+
+/* Synchronize the table's last stream and free everything it owns. */
+hive_status hive_destroy(hive_t h);
+
+/* Insert-or-replace n pairs (Section III-D Insert and Replace; the four-step
+ * insert of Section IV-A).  d_keys, d_vals: n uint32 each.  Repeated keys:
+ * the last occurrence wins, unless `flags` has HIVE_UNIQUE (then repeats are
+ * the caller's error and their outcome is unspecified). */
+hive_status hive_insert_batch(hive_t h, const uint32_t *d_keys, const uint32_t *d_vals, uint64_t n,
+                              uint32_t flags, void *stream);
+
+/* Search n keys (Section III-D Search; Section IV-B).  d_vals_out[i] gets
+ * the value or 0xFFFFFFFF, d_found_out[i] 1 or 0.  Either output may be
+ * NULL. */
+hive_status hive_lookup_batch(hive_t h, const uint32_t *d_keys, uint64_t n, uint32_t *d_vals_out,
+                              uint8_t *d_found_out, void *stream);
+
+/* Delete n keys (Section III-D Delete; Algorithm 4).  d_deleted_out[i] (may
+ * be NULL) is 1 when the key was present at that point of the batch; with
+ * repeats, the first occurrence reports the deletion. */
+hive_status hive_delete_batch(hive_t h, const uint32_t *d_keys, uint64_t n, uint32_t flags,
+                              uint8_t *d_deleted_out, void *stream);
+
+/* A batch of mixed operations (the paper's concurrent mix, Section V-C-2).
+ * d_ops[i] is HIVE_OP_INSERT/DELETE/LOOKUP.  Contract: within one call the
+ * keys of inserts, of deletes and of lookups form disjoint sets (a key may
+ * repeat within one type).  Outputs, per operation: lookups write the value
+ * (or 0xFFFFFFFF) and found; deletes write 0xFFFFFFFF and the deleted flag;
+ * inserts write 0xFFFFFFFF and 0.  d_vals may be NULL when there are no
+ * inserts; outputs may be NULL. */
+hive_status hive_mixed_batch(hive_t h, const uint8_t *d_ops, const uint32_t *d_keys, const uint32_t *d_vals,
+                             uint64_t n, uint32_t flags, uint32_t *d_vals_out, uint8_t *d_flags_out,
+                             void *stream);
+
+/* Linear-hashing resize (Section IV-C), LINEAR tables only.
+ * delta > 0: split up to delta buckets, K at a time (Section IV-C-1), then
+ * re-insert the stash and pending entries; delta < 0: merge up to -delta
+ * pairs from the top down, stopping at the first pair whose entries do not
+ * fit (Section IV-C-2); delta == 0: apply the load-factor rule.  The
+ * decisions are taken on the device; the call does not synchronize. */
+hive_status hive_resize(hive_t h, int64_t delta, void *stream);
+
+/* Copy counters and geometry to *out (synchronizes `stream`) and return the
+ * latched device condition, if any: HIVE_ERR_LOST, HIVE_ERR_BUDGET,
+ * HIVE_WARN_PENDING or HIVE_WARN_INVALID_KEYS, else HIVE_OK. */
+hive_status hive_stats(hive_t h, hive_stats_t *out, void *stream);
+
+/* Write every live entry to d_words (packed words) and its place to d_where
+ * (bucket index, -1 for the stash, -2 for the pending list; may be NULL),
+ * in no particular order, at most `capacity` of them; *n_out gets the number
+ * of live entries.  Synchronizes `stream`. */
+hive_status hive_dump(hive_t h, uint64_t *d_words, int64_t *d_where, uint64_t capacity, uint64_t *n_out,
+                      void *stream);
+
+/* Placement census: out[0] = live bucket entries in their first candidate
+ * bucket, out[1] = in their second (different) candidate, out[2] = stash and
+ * pending slots in use (including deleted ones).  With two-choice placement
+ * a successful lookup touches one bucket for out[0] entries and two for
+ * out[1] entries.  Synchronizes `stream`. */
+hive_status hive_placement(hive_t h, uint64_t *out, void *stream);
+
+/* Empty the table and restore its initial geometry (stream-ordered). */
+hive_status hive_clear(hive_t h, void *stream);
+
+/* A short English description of a status code (static storage). */
+const char *hive_status_string(hive_status s);
+
+/* Host-callable copies of the device hash and reduction, for tests: the
+ * full 32-bit BitHash1/BitHash2 mixes (Section III-C) and the bucket a mixed
+ * hash maps to under the table's current geometry (reads the device
+ * geometry; synchronizes the table's last stream). */
+uint32_t hive_bithash1(uint32_t key);
+uint32_t hive_bithash2(uint32_t key);
+hive_status hive_bucket_of(hive_t h, uint32_t mixed_hash, uint64_t *bucket);
+
+/* The remainder a % d by multiply-high with a precomputed magic number
+ * (Lemire, Kaser, Kurz, "Faster remainder by direct computation", 2019), as
+ * the FIXED addressing uses it on the device: exact for all 32-bit a and
+ * 1 <= d < 2^32. */
+uint64_t hive_fastmod_magic(uint32_t d);
+uint32_t hive_fastmod(uint32_t a, uint64_t magic, uint32_t d);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HIVE_H */

@@ -24,7 +24,6 @@ HIP_FLAGS = [
     "-Wall", "-Wno-unused-function",
     # packed fp32 forms are disabled for all HIP code built here
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-fgpu-rdc=false",
 ]
 
 

@@ -1,0 +1,188 @@
+// Device-side building blocks of the Hive table for gfx950 (64-lane waves).
+//
+// Layout in HBM (one table):
+//   buckets  max_buckets * S packed words, 128-byte aligned; bucket b occupies
+//            words [b*S, b*S + S): one 128-byte line for S = 16
+//   hint     one bit per bucket: set when a key with this bucket as a
+//            candidate was sent to the stash or pending list
+//   stash    ring of packed words (Section IV-A step 4); deleted entries
+//            become TOMB
+//   pending  entries that found the stash full
+//   ctl      the control block below
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hive {
+
+// An unoccupied bucket slot: key half 0xFFFFFFFF (a reserved key), so no
+// live entry ever equals it and a 0xFF byte fill empties a bucket.
+constexpr uint64_t EMPTY = ~0ull;
+// A deleted stash or pending entry: key half 0 (the other reserved key).
+constexpr uint64_t TOMB = 0ull;
+constexpr uint32_t NO_VALUE = 0xFFFFFFFFu;
+
+enum : uint32_t { ADDR_FIXED = 0, ADDR_LINEAR = 1 };
+enum : uint32_t { OP_INSERT = 0, OP_DELETE = 1, OP_LOOKUP = 2, OP_MIXED = 3, OP_NONE = 7 };
+
+// Latched device conditions (ctl.error).
+enum : uint32_t {
+  ERR_PENDING_LOST = 1u,   // the pending list overflowed
+  ERR_CAS_RETRY = 2u,      // a replace/delete found its word changed (contract breach)
+  ERR_ARENA_FULL = 4u,     // a split found no arena room
+};
+
+// Control block, one per table, in device memory.  Geometry is read by every
+// kernel at its start, so it may change between launches without host sync.
+struct alignas(128) Ctl {
+  // geometry (Section III-B global metadata, Section IV-C control fields)
+  uint64_t n_buckets;
+  uint64_t magic;      // FIXED: fastmod multiplier for n_buckets
+  uint64_t im;         // LINEAR: index mask 2^m - 1
+  uint64_t sp;         // LINEAR: split pointer
+  uint32_t mode;       // ADDR_FIXED / ADDR_LINEAR
+  uint32_t error;      // latched ERR_* bits
+  // logical size and overflow structures
+  uint64_t live;
+  uint64_t stash_count;    // ring slots used (including TOMB)
+  uint64_t pending_count;  // pending slots used (including TOMB; may pass capacity on loss)
+  // per-batch
+  uint64_t wl_count;       // eviction worklist entries
+  uint64_t p3_done;        // blocks of the eviction kernel that finished
+  uint64_t dump_count;
+  // statistics
+  uint64_t evictions;
+  uint64_t stash_inserts;
+  uint64_t pending_inserts;
+  uint64_t full_chains;
+  uint64_t invalid_keys;
+  uint64_t evict_items;
+  // resize bookkeeping (device-side policy)
+  uint64_t resize_todo;    // pairs the current resize step still has to do
+  uint64_t merge_commit;   // pairs of a merge step that passed the feasibility test
+  uint64_t initial_buckets;
+  uint64_t max_buckets;
+  // placement census (hive_placement)
+  uint64_t place_first;
+  uint64_t place_second;
+  uint64_t reserved_[4];
+};
+
+// ---- Section III-C hashes -------------------------------------------------
+// BitHash1 and BitHash2 written as compositions of invertible maps of
+// Z/2^32 (the final "% nBuckets" of the listing belongs to the addressing):
+//   BitHash1: x -> 32767x - 1, then x ^= x>>12, x -> 5x, x ^= x>>4,
+//             x -> 2057x, x ^= x>>16;
+//   BitHash2: x -> 4097x + 0x7ed55d16, x -> x ^ 0xc761c23c ^ (x>>19),
+//             x -> 33x + 0x165667b1, x -> (x + 0xd3a2646c) ^ (x<<9),
+//             x -> 9x + 0xfd7046c5, x -> x ^ 0xb55a4f09 ^ (x>>16).
+__host__ __device__ inline uint32_t bithash1(uint32_t x) {
+  x = x * 32767u - 1u;
+  x ^= x >> 12;
+  x *= 5u;
+  x ^= x >> 4;
+  x *= 2057u;
+  return x ^ (x >> 16);
+}
+
+__host__ __device__ inline uint32_t bithash2(uint32_t x) {
+  x = x * 4097u + 0x7ed55d16u;
+  x = x ^ 0xc761c23cu ^ (x >> 19);
+  x = x * 33u + 0x165667b1u;
+  x = (x + 0xd3a2646cu) ^ (x << 9);
+  x = x * 9u + 0xfd7046c5u;
+  return x ^ 0xb55a4f09u ^ (x >> 16);
+}
+
+// a % d without a divide (gfx950 has no integer divide): Lemire, Kaser and
+// Kurz, "Faster remainder by direct computation" (2019).  magic = 2^64/d
+// rounded up (wrapping to 0 for d = 1, which still yields 0).
+__host__ __device__ inline uint64_t fastmod_magic(uint32_t d) { return ~0ull / d + 1ull; }
+
+__host__ __device__ inline uint32_t fastmod(uint32_t a, uint64_t magic, uint32_t d) {
+  uint64_t low = magic * a;
+#if defined(__HIP_DEVICE_COMPILE__)
+  return (uint32_t)__umul64hi(low, (uint64_t)d);
+#else
+  return (uint32_t)(((unsigned __int128)low * d) >> 64);
+#endif
+}
+
+struct Geo {
+  uint64_t n_buckets;
+  uint64_t magic;
+  uint32_t im, sp;
+  uint32_t mode;
+};
+
+__host__ __device__ inline uint32_t address(const Geo &g, uint32_t h) {
+  if (g.mode == ADDR_FIXED) return fastmod(h, g.magic, (uint32_t)g.n_buckets);
+  uint32_t a = h & g.im;
+  if (a < g.sp) a = h & (2u * g.im + 1u);
+  return a;
+}
+
+__device__ inline Geo read_geo(const Ctl *c) {
+  Geo g;
+  g.n_buckets = c->n_buckets;
+  g.magic = c->magic;
+  g.im = (uint32_t)c->im;
+  g.sp = (uint32_t)c->sp;
+  g.mode = c->mode;
+  return g;
+}
+
+__host__ __device__ inline uint64_t pack(uint32_t key, uint32_t value) { return ((uint64_t)value << 32) | key; }
+__host__ __device__ inline uint32_t key_of(uint64_t w) { return (uint32_t)w; }
+__host__ __device__ inline uint32_t value_of(uint64_t w) { return (uint32_t)(w >> 32); }
+__host__ __device__ inline bool valid_key(uint32_t k) { return k != 0u && k != 0xFFFFFFFFu; }
+
+// ---- wave helpers ---------------------------------------------------------
+__device__ inline uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+// number of set bits of m below this lane
+__device__ inline uint32_t rank_below(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// LDS written by one lane of a wave and read by another lane of the same
+// wave: LDS instructions of a wave complete in order, so a compiler-level
+// fence is all that is needed.
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Device-scope (agent) relaxed atomics on 64-bit words.
+__device__ inline uint64_t cas64(uint64_t *p, uint64_t expected, uint64_t desired) {
+  __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+  return expected;  // the word found (== expected on success)
+}
+
+__device__ inline uint64_t load_fresh(const uint64_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline uint64_t add64(uint64_t *p, uint64_t v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline uint32_t or32(uint32_t *p, uint32_t v) {
+  return __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Mix for the per-batch dedupe set and the eviction victim choice: the
+// "lowbias32" integer hash published by C. Wellons (hash-prospector, 2018).
+// It is not one of the bucket hashes, so it is independent of placement.
+__host__ __device__ inline uint32_t mix32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  return x ^ (x >> 16);
+}
+
+}  // namespace hive

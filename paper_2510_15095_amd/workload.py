@@ -356,11 +356,15 @@ def mixed_batch(seed: int, batch: int, n_ops: int, universe: int,
             return zipf.sample(rng, count)
         return rng.integers(1, universe + 1, size=count, dtype=np.int64)
 
+    if n_del > universe:
+        raise ValueError("the universe is smaller than the number of distinct delete keys")
     ranks = draw(n_ops)
     lib = _native()
     if lib is not None:
         pool_n = max(1024, n_ops)
         while True:
+            if pool_n > 64 * max(n_ops, 1024):
+                raise RuntimeError("mixed batch: key universe too small for per-type disjoint keys")
             pool = draw(pool_n)
             r = ranks.copy()
             used = lib.wl_resolve_mixed(_ptr(ops), n_ops, _ptr(r), _ptr(pool), pool_n)

@@ -1,0 +1,293 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Every integer output is compared bit-exactly: lookup values and found flags,
+delete flags, and the final key->value set.  Physical placement is not part
+of the contract, but every stored entry must sit in one of its two candidate
+buckets as the oracle computes them, and every key must be stored once.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2510_15095_amd import workload as wl
+
+pytestmark = pytest.mark.gpu
+
+M32 = 0xFFFFFFFF
+
+
+def case(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def H():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2510_15095_amd import hive
+    return hive
+
+
+def dev(a, dtype=None):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def host(t):
+    return t.cpu().numpy()
+
+
+def check_placement(table_dump, where, S, n_buckets, addressing=oracle.ADDR_FIXED, max_buckets=None, geo=None):
+    """Every bucket entry sits in a candidate bucket (oracle addressing) and
+    every key appears once."""
+    keys = (table_dump & np.uint64(M32)).astype(np.uint32)
+    assert np.unique(keys).size == keys.size, "a key is stored twice"
+    o2 = oracle.O2(S, 8, 16, addressing, n_buckets, max_buckets=max_buckets)
+    if geo is not None:  # LINEAR: advance the oracle geometry to the same point
+        while o2.stats()["n_buckets"] < geo:
+            o2.split(1)
+    in_bucket = where >= 0
+    c1, c2 = o2.candidates(keys[in_bucket])
+    w = where[in_bucket]
+    bad = (w != c1) & (w != c2)
+    assert not bad.any(), f"{bad.sum()} entries outside their candidate buckets"
+
+
+def run_tiny(H, S, seed=1, n_keys=1 << 16, n_buckets=None):
+    """The tiny configuration: insert all, look up (50% present), delete a
+    random half, look up again; compared with the oracle step by step."""
+    w = wl.bulk_workload(seed, n_keys)
+    n_buckets = n_buckets or (2 * n_keys) // S  # 50% load
+    case(f"tiny S={S} keys={n_keys} buckets={n_buckets}")
+    t = H.Table(n_buckets, slots_per_bucket=S, max_evictions=8, stash_capacity=1024)
+    o = oracle.O2(S, 8, 1024, oracle.ADDR_FIXED, n_buckets)
+    t.insert(dev(w["ins_keys"]), dev(w["ins_vals"]), flags=H.HIVE_UNIQUE)
+    o.insert(w["ins_keys"], w["ins_vals"])
+    qk = dev(w["query_keys"])
+    v, f = t.lookup(qk)
+    ov, of = o.lookup(w["query_keys"])
+    assert np.array_equal(host(f), of) and np.array_equal(host(v), ov)
+    d = t.delete(dev(w["del_keys"]), flags=H.HIVE_UNIQUE)
+    assert np.array_equal(host(d), o.delete(w["del_keys"]))
+    v, f = t.lookup(qk)
+    ov, of = o.lookup(w["query_keys"])
+    assert np.array_equal(host(f), of) and np.array_equal(host(v), ov)
+    st = t.stats()
+    assert st["status"] == H.HIVE_OK and st["live"] == o.stats()["live"]
+    words, where = t.dump(with_where=True)
+    assert np.array_equal(words, o.dump())
+    check_placement(words, where, S, n_buckets)
+    t.close()
+
+
+def test_tiny_config_s16(H):
+    run_tiny(H, 16)
+
+
+@pytest.mark.parametrize("S", [32, 64])
+def test_tiny_config_other_widths(H, S):
+    run_tiny(H, S, seed=11, n_keys=1 << 14)
+
+
+def test_ragged_sizes_and_tiny_batches(H):
+    for n in (1, 2, 63, 64, 65, 255, 257, 1000, 4097):
+        case(f"ragged n={n}")
+        t = H.Table(max(1, (2 * n) // 16 + 1))
+        w = wl.bulk_workload(7 + n, n, n_queries=n + 1, n_deletes=n // 2)
+        t.insert(dev(w["ins_keys"]), dev(w["ins_vals"]))
+        v, f = t.lookup(dev(w["query_keys"]))
+        present = w["query_idx"] < n
+        assert np.array_equal(host(f).astype(bool), present)
+        exp = np.where(present, wl.values_for(w["query_keys"]), np.uint32(M32))
+        assert np.array_equal(host(v), exp)
+        d = t.delete(dev(w["del_keys"]))
+        assert host(d).all()
+        assert t.stats()["live"] == n - n // 2
+        t.close()
+
+
+def test_empty_batch_and_empty_table(H):
+    import torch
+    case("empty")
+    t = H.Table(64)
+    e = torch.empty(0, dtype=torch.uint32, device="cuda")
+    t.insert(e, e)
+    v, f = t.lookup(e)
+    assert v.numel() == 0
+    keys = dev(np.array([1, 2, 3, 0xFFFFFFFE], np.uint32))
+    v, f = t.lookup(keys)
+    assert host(f).tolist() == [0, 0, 0, 0] and host(v).tolist() == [M32] * 4
+    assert host(t.delete(keys)).tolist() == [0, 0, 0, 0]
+    assert t.stats()["live"] == 0
+    t.close()
+
+
+def test_reserved_keys_are_noops(H):
+    case("reserved keys")
+    t = H.Table(64)
+    keys = np.array([0, 5, M32, 6], np.uint32)
+    t.insert(dev(keys), dev(np.array([1, 2, 3, 4], np.uint32)))
+    v, f = t.lookup(dev(keys))
+    assert host(f).tolist() == [0, 1, 0, 1] and host(v).tolist() == [M32, 2, M32, 4]
+    assert host(t.delete(dev(keys))).tolist() == [0, 1, 0, 1]
+    st = t.stats()
+    assert st["invalid_keys"] == 6 and st["status"] == H.HIVE_WARN_INVALID_KEYS and st["live"] == 0
+    t.close()
+
+
+def test_replace_on_reinsert(H):
+    case("replace")
+    n = 5000
+    t = H.Table(n // 8)
+    o = oracle.O1()
+    keys = wl.KeyStream(21).range(0, n)
+    v1 = wl.values_for(keys)
+    t.insert(dev(keys), dev(v1), flags=H.HIVE_UNIQUE)
+    o.insert(keys, v1)
+    v2 = (v1 ^ np.uint32(0x5A5A5A5A)).astype(np.uint32)
+    t.insert(dev(keys[::3]), dev(v2[::3]), flags=H.HIVE_UNIQUE)
+    o.insert(keys[::3], v2[::3])
+    v, f = t.lookup(dev(keys))
+    ov, of = o.lookup(keys)
+    assert np.array_equal(host(v), ov) and host(f).all()
+    assert t.stats()["live"] == n
+    assert np.array_equal(t.dump(), o.dump())
+    t.close()
+
+
+def test_dedupe_last_insert_wins_first_delete_reports(H):
+    case("dedupe")
+    rng = np.random.default_rng(3)
+    base = wl.KeyStream(31).range(0, 3000)
+    keys = base[rng.integers(0, base.size, 20000)]
+    vals = rng.integers(1, 1 << 32, keys.size, dtype=np.uint64).astype(np.uint32)
+    t = H.Table(512)
+    o = oracle.O1()
+    t.insert(dev(keys), dev(vals))
+    o.insert(keys, vals)
+    v, f = t.lookup(dev(base))
+    ov, of = o.lookup(base)
+    assert np.array_equal(host(f), of) and np.array_equal(host(v), ov)
+    dkeys = base[rng.integers(0, base.size, 5000)]
+    d = t.delete(dev(dkeys))
+    assert np.array_equal(host(d), o.delete(dkeys))
+    assert t.stats()["live"] == len(o)
+    assert np.array_equal(t.dump(), o.dump())
+    t.close()
+
+
+@pytest.mark.parametrize("E,stash,lf", [(8, 1024, 0.97), (2, 64, 0.99), (1, 8, 0.995), (0, 4, 0.99)])
+def test_eviction_stash_pending_heavy(H, E, stash, lf):
+    """Small tables near capacity: eviction chains, the stash and the pending
+    list all carry entries, and every operation still matches the oracle."""
+    S, nb = 16, 97
+    n = int(S * nb * lf)
+    case(f"evict-heavy E={E} stash={stash} lf={lf}")
+    ks = wl.KeyStream(40 + E)
+    keys = ks.range(0, n)
+    vals = wl.values_for(keys)
+    t = H.Table(nb, max_evictions=E, stash_capacity=stash, pending_capacity=4096)
+    o = oracle.O1()
+    t.insert(dev(keys), dev(vals), flags=H.HIVE_UNIQUE)
+    o.insert(keys, vals)
+    st = t.stats()
+    assert st["status"] in (H.HIVE_OK, H.HIVE_WARN_PENDING), st
+    assert st["live"] == n and st["stash_count"] <= stash
+    q = ks.range(0, n + 500)
+    v, f = t.lookup(dev(q))
+    ov, of = o.lookup(q)
+    assert np.array_equal(host(f), of) and np.array_equal(host(v), ov)
+    words, where = t.dump(with_where=True)
+    assert np.array_equal(words, o.dump())
+    check_placement(words, where, S, nb)
+    # replace and delete reach entries wherever they sit, stash included
+    v2 = (vals ^ np.uint32(0xABCDEF)).astype(np.uint32)
+    t.insert(dev(keys[::2]), dev(v2[::2]), flags=H.HIVE_UNIQUE)
+    o.insert(keys[::2], v2[::2])
+    dk = keys[1::3]
+    assert np.array_equal(host(t.delete(dev(dk), flags=H.HIVE_UNIQUE)), o.delete(dk))
+    v, f = t.lookup(dev(q))
+    ov, of = o.lookup(q)
+    assert np.array_equal(host(f), of) and np.array_equal(host(v), ov)
+    assert np.array_equal(t.dump(), o.dump())
+    t.close()
+
+
+def test_mixed_batches_zipf(H):
+    """Prefill, then mixed batches (40% insert with repeats, 40% delete, 20%
+    lookup, Zipf keys, per-type disjoint): per-batch outputs and the final
+    set equal the dictionary's."""
+    S, nb = 16, 4096
+    universe = 1 << 16
+    ks = wl.KeyStream(3)
+    pre = ks.keys(wl.DomainPerm(33, universe).sample(int(0.8 * S * nb * 0.9)))
+    t = H.Table(nb, stash_capacity=2048)
+    o = oracle.O1()
+    t.insert(dev(pre), dev(wl.values_for(pre)), flags=H.HIVE_UNIQUE)
+    o.insert(pre, wl.values_for(pre))
+    for b in range(6):
+        case(f"mixed batch {b}")
+        mb = wl.mixed_batch(3, b, 1 << 14, universe, stream=ks, value_salt=b + 1)
+        v, f = t.mixed(dev(mb["ops"]), dev(mb["keys"]), dev(mb["vals"]))
+        ov, of = o.apply(mb["ops"], mb["keys"], mb["vals"])
+        assert np.array_equal(host(f), of), f"flags differ in batch {b}"
+        assert np.array_equal(host(v), ov), f"values differ in batch {b}"
+        assert t.stats()["live"] == len(o)
+    assert np.array_equal(t.dump(), o.dump())
+    t.close()
+
+
+def test_bulk_95pct_reduced(H):
+    """The bulk configuration at 2^20 keys: FIXED table at 95% load, 50%-hit
+    queries, delete half, re-query; exact expected outputs come from the
+    generator (present iff inserted and not deleted, value = value(key))."""
+    run_bulk(H, 1 << 20, seed=2)
+
+
+def run_bulk(H, n_keys, seed):
+    S = 16
+    nb = int(np.ceil(n_keys / (0.95 * S)))
+    case(f"bulk n={n_keys} buckets={nb}")
+    w = wl.bulk_workload(seed, n_keys)
+    t = H.Table(nb)
+    t.insert(dev(w["ins_keys"]), dev(w["ins_vals"]), flags=H.HIVE_UNIQUE)
+    st = t.stats()
+    assert st["live"] == n_keys and st["status"] == H.HIVE_OK, st
+    qk = dev(w["query_keys"])
+    present = w["query_idx"] < n_keys
+    exp_v = np.where(present, wl.values_for(w["query_keys"]), np.uint32(M32))
+    v, f = t.lookup(qk)
+    assert np.array_equal(host(f).astype(bool), present)
+    assert np.array_equal(host(v), exp_v)
+    d = t.delete(dev(w["del_keys"]), flags=H.HIVE_UNIQUE)
+    assert host(d).all()
+    deleted = np.zeros(n_keys, bool)
+    deleted[w["del_idx"]] = True
+    still = present.copy()
+    still[present] = ~deleted[w["query_idx"][present]]
+    v, f = t.lookup(qk)
+    assert np.array_equal(host(f).astype(bool), still)
+    assert np.array_equal(host(v), np.where(still, exp_v, np.uint32(M32)))
+    st = t.stats()
+    assert st["live"] == n_keys - w["del_keys"].size
+    words = t.dump()
+    idx = w["stream"].index_of((words & np.uint64(M32)).astype(np.uint32))
+    assert idx.size == st["live"] and np.unique(idx).size == idx.size
+    assert not deleted[idx].any() and (idx < n_keys).all()
+    assert np.array_equal((words >> np.uint64(32)).astype(np.uint32), w["ins_vals"][idx])
+    t.close()
+    return st
+
+
+def test_bulk_95pct_full_size(H):
+    """2^26 keys into 4,415,057 16-slot buckets (95% load): every output is
+    checked against the generator's closed-form expectation."""
+    st = run_bulk(H, 1 << 26, seed=2)
+    print("bulk 2^26 stats:", st)

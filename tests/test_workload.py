@@ -102,7 +102,7 @@ def test_tiny_workload_is_deterministic():
 
 @pytest.mark.parametrize("zipf_s", [0.99, None])
 def test_mixed_batch_counts_and_disjointness(zipf_s):
-    b = wl.mixed_batch(3, 0, 20000, 1 << 12, zipf_s=zipf_s)
+    b = wl.mixed_batch(3, 0, 20000, 1 << 16, zipf_s=zipf_s)
     ops, ranks = b["ops"], b["ranks"]
     assert (ops == wl.OP_INSERT).sum() == 8000 and (ops == wl.OP_DELETE).sum() == 8000
     types_per_rank = {}
