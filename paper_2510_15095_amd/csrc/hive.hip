@@ -41,6 +41,8 @@ namespace hive {
 constexpr int WAVES = 4;  // waves per block
 constexpr int BLOCK = 64 * WAVES;
 constexpr int EVICT_GRID = 1024;  // blocks of the eviction phase (grid-stride)
+constexpr int RESIZE_GRID = 2048; // blocks of a resize pass (grid-stride over pairs)
+constexpr int DRAIN_GRID = 256;
 
 template <int S>
 struct Traits {
@@ -409,6 +411,26 @@ __device__ inline bool claim_lane(uint64_t *bkt, uint64_t kv) {
   return false;
 }
 
+template <int S>
+__device__ inline int count_empty_lane(const uint64_t *bkt) {
+  int n = 0;
+  for (int s = 0; s < S; ++s) n += load_fresh(bkt + s) == EMPTY;
+  return n;
+}
+
+// Step 2 for one item (lane-wise): the candidate with more empty slots
+// first, ties to the first hash, then the other candidate.
+template <int S>
+__device__ inline bool two_choice_claim_lane(uint64_t *buckets, uint32_t c1, uint32_t c2, uint64_t kv) {
+  uint32_t first = c1, second = c2;
+  if (c2 != c1 && count_empty_lane<S>(buckets + (uint64_t)c2 * S) > count_empty_lane<S>(buckets + (uint64_t)c1 * S)) {
+    first = c2;
+    second = c1;
+  }
+  if (claim_lane<S>(buckets + (uint64_t)first * S, kv)) return true;
+  return second != first && claim_lane<S>(buckets + (uint64_t)second * S, kv);
+}
+
 // Put kv into slot s0 (or the next slots) by CAS, displacing the occupant.
 // Returns 1 with *victim set, 2 when the slot turned out empty (claimed), 0
 // when every CAS lost a race.
@@ -467,9 +489,14 @@ __global__ __launch_bounds__(BLOCK) void evict_kernel(EvictArgs a) {
   uint64_t n_evict = 0, n_full = 0;
   for (uint64_t t = (uint64_t)blockIdx.x * BLOCK + threadIdx.x; t < cnt; t += (uint64_t)gridDim.x * BLOCK) {
     uint64_t kv = a.wl[t];
-    uint32_t b = address(geo, bithash1(key_of(kv)));  // chains start at the first candidate
-    bool placed = false;
-    for (uint32_t kick = 1; kick <= a.max_evictions; ++kick) {
+    const uint32_t k1 = address(geo, bithash1(key_of(kv))), k2 = address(geo, bithash2(key_of(kv)));
+    // step 2 once more with fresh loads (items from P1 saw both buckets full,
+    // possibly through a stale cache line; items drained from the stash after
+    // a split have not tried the new geometry), then the chain from the first
+    // candidate
+    bool placed = two_choice_claim_lane<S>(a.buckets, k1, k2, kv);
+    uint32_t b = k1;
+    for (uint32_t kick = 1; kick <= a.max_evictions && !placed; ++kick) {
       uint64_t *bkt = a.buckets + (uint64_t)b * S;
       if (claim_lane<S>(bkt, kv)) {
         placed = true;
@@ -508,6 +535,274 @@ __global__ __launch_bounds__(BLOCK) void evict_kernel(EvictArgs a) {
       __hip_atomic_store(&a.ctl->wl_count, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_store(&a.ctl->p3_done, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+  }
+}
+
+
+// ---------------------------------------------------------------------------
+// Linear-hashing resize (Section IV-C), decided on the device.
+//
+// A resize call is planned by resize_plan_kernel (pairs to split or merge),
+// then runs as segments, one per hashing round: pass 1 splits the segment's
+// pairs, or tests each merge pair for room; pass 2 moves the merge pairs that
+// passed, from the top down to the first that did not.  The last block of
+// each pass updates the geometry and plans the next segment, so the host
+// launches a fixed number of segments and never reads the device.
+// ---------------------------------------------------------------------------
+enum : uint32_t { PLAN_PRE = 0, PLAN_PRE_MIXED = 1, PLAN_POST = 2, PLAN_SPLIT = 3, PLAN_MERGE = 4 };
+
+struct ResizeArgs {
+  uint64_t *buckets;
+  uint32_t *hint;
+  Ctl *ctl;
+  uint32_t S;
+  uint32_t K;
+  uint32_t lf_expand_pct;
+  uint32_t lf_contract_pct;
+};
+
+// Geometry of the next segment.  Splits first finish a round (sp == im+1 is
+// the same addressing as the next round with sp == 0); merges first regress
+// a round when sp == 0 (again the same addressing).
+__device__ inline void plan_next(Ctl *c) {
+  c->seg = 0;
+  if (c->resize_todo == 0) {
+    c->resize_dir = 0;
+    return;
+  }
+  if (c->resize_dir > 0) {
+    if (c->sp == c->im + 1) {
+      c->im = 2 * c->im + 1;
+      c->sp = 0;
+    }
+    const uint64_t room = c->max_buckets - c->n_buckets;
+    if (room == 0) {
+      c->resize_todo = 0;
+      c->resize_dir = 0;
+      return;
+    }
+    c->seg = min(min(c->resize_todo, c->im + 1 - c->sp), room);
+  } else {
+    if (c->n_buckets <= c->initial_buckets) {
+      c->resize_todo = 0;
+      c->resize_dir = 0;
+      return;
+    }
+    if (c->sp == 0) {
+      c->im >>= 1;
+      c->sp = c->im + 1;
+    }
+    c->seg = min(min(c->resize_todo, c->sp), c->n_buckets - c->initial_buckets);
+    c->merge_commit = c->seg;
+  }
+}
+
+// Pairs the load-factor rule asks for, in whole K-pair steps: expansion
+// while (live + extra) * 100 > lf_expand * buckets * S, contraction while
+// live * 100 < lf_contract * buckets * S and the table is above its initial
+// size.
+__device__ inline void plan_policy(Ctl *c, const ResizeArgs &a, uint64_t extra, bool allow_contract) {
+  const uint64_t S = a.S, K = a.K, nb = c->n_buckets, live = c->live;
+  const uint64_t need = live + extra;
+  if (need * 100 > (uint64_t)a.lf_expand_pct * nb * S) {
+    const uint64_t den = (uint64_t)a.lf_expand_pct * S;
+    const uint64_t r = (need * 100 + den - 1) / den;  // fewest buckets that satisfy the rule
+    const uint64_t steps = (r - nb + K - 1) / K;
+    c->resize_dir = 1;
+    c->resize_todo = steps * K;
+  } else if (allow_contract && live * 100 < (uint64_t)a.lf_contract_pct * nb * S && nb > c->initial_buckets) {
+    const uint64_t q = live * 100 / ((uint64_t)a.lf_contract_pct * S);
+    const uint64_t lim = max(q, c->initial_buckets);
+    if (nb > lim) {
+      const uint64_t steps = (nb - lim + K - 1) / K;
+      const uint64_t fin = (nb > steps * K && nb - steps * K > c->initial_buckets) ? nb - steps * K
+                                                                                  : c->initial_buckets;
+      c->resize_dir = -1;
+      c->resize_todo = nb - fin;
+    }
+  }
+}
+
+__global__ __launch_bounds__(BLOCK) void resize_plan_kernel(ResizeArgs a, uint32_t mode, uint64_t amount,
+                                                            const uint8_t *ops) {
+  __shared__ unsigned long long n_ins;
+  if (threadIdx.x == 0) n_ins = 0;
+  __syncthreads();
+  if (mode == PLAN_PRE_MIXED) {
+    unsigned long long mine = 0;
+    for (uint64_t i = threadIdx.x; i < amount; i += BLOCK) mine += ops[i] == OP_INSERT;
+    atomicAdd(&n_ins, mine);
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  Ctl *c = a.ctl;
+  c->resize_dir = 0;
+  c->resize_todo = 0;
+  c->ticket = 0;
+  if (c->mode != ADDR_LINEAR) {
+    c->seg = 0;
+    return;
+  }
+  switch (mode) {
+    case PLAN_PRE: plan_policy(c, a, amount, false); break;
+    case PLAN_PRE_MIXED: plan_policy(c, a, n_ins, false); break;
+    case PLAN_POST: plan_policy(c, a, 0, true); break;
+    case PLAN_SPLIT:
+      c->resize_dir = 1;
+      c->resize_todo = amount;
+      break;
+    default:
+      c->resize_dir = -1;
+      c->resize_todo = amount;
+      break;
+  }
+  plan_next(c);
+}
+
+// Ticket for "the last block of this launch": every block has finished its
+// reads of the control block and its writes to the table.
+__device__ inline bool last_block(uint64_t *ticket) {
+  __shared__ bool last;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    last = add64(ticket, 1) == gridDim.x - 1;
+  }
+  __syncthreads();
+  return last;
+}
+
+__device__ inline uint32_t nth_set_bit(uint64_t m, uint32_t r) {
+  for (uint32_t i = 0; i < r; ++i) m &= m - 1;
+  return (uint32_t)__builtin_ctzll(m);
+}
+
+// Pass 1: split the segment's pairs (Section IV-C-1), or test merge pairs.
+template <int S>
+__global__ __launch_bounds__(BLOCK) void resize_pass1_kernel(ResizeArgs a) {
+  using T = Traits<S>;
+  Ctl *c = a.ctl;
+  const uint64_t seg = c->seg;
+  if (seg == 0) return;  // same value in every block: nobody takes a ticket
+  const int64_t dir = c->resize_dir;
+  const uint64_t im = c->im, sp = c->sp;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int g = lane / S, sl = lane % S;
+  const uint64_t groups = (uint64_t)gridDim.x * WAVES * T::G;
+  for (uint64_t j = ((uint64_t)blockIdx.x * WAVES + wv) * T::G + g; j < seg; j += groups) {
+    if (dir > 0) {
+      // pair (src, src + 2^m): an entry stays when one of its candidate
+      // hashes still addresses src under the next round's mask, otherwise
+      // it moves; movers are compacted into the partner's first slots
+      const uint64_t src = sp + j, dst = src + im + 1, next = 2 * im + 1;
+      const uint64_t w = a.buckets[src * S + sl];
+      bool move = false;
+      if (w != EMPTY) {
+        const uint32_t h1 = bithash1(key_of(w)), h2 = bithash2(key_of(w));
+        const bool stay = ((h1 & im) == src && (h1 & next) == src) || ((h2 & im) == src && (h2 & next) == src);
+        move = !stay;
+      }
+      const uint64_t mm = (ballot(move) >> (g * S)) & T::FULL;
+      if (move) {
+        const uint32_t rank = __builtin_popcountll(mm & ((1ull << sl) - 1ull));
+        a.buckets[dst * S + rank] = w;
+        a.buckets[src * S + sl] = EMPTY;
+      }
+    } else {
+      // merge pair (lo, lo + 2^m), walked from the top: it fits when hi's
+      // entries fit lo's empty slots (Section IV-C-2)
+      const uint64_t lo = sp - 1 - j, hi = lo + im + 1;
+      const uint64_t wl = a.buckets[lo * S + sl], wh = a.buckets[hi * S + sl];
+      const uint64_t fl = (ballot(wl == EMPTY) >> (g * S)) & T::FULL;
+      const uint64_t lh = (ballot(wh != EMPTY) >> (g * S)) & T::FULL;
+      if (sl == 0 && __builtin_popcountll(lh) > __builtin_popcountll(fl))
+        __hip_atomic_fetch_min(&c->merge_commit, j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+  if (dir > 0 && last_block(&c->ticket)) {
+    c->ticket = 0;
+    c->sp = sp + seg;
+    c->n_buckets += seg;
+    c->resize_todo -= seg;
+    c->split_happened = 1;
+    plan_next(c);
+  }
+}
+
+// Pass 2: move the merge pairs that fit, top down.
+template <int S>
+__global__ __launch_bounds__(BLOCK) void resize_pass2_kernel(ResizeArgs a) {
+  using T = Traits<S>;
+  Ctl *c = a.ctl;
+  const uint64_t seg = c->seg;
+  if (seg == 0 || c->resize_dir > 0) return;
+  const uint64_t commit = c->merge_commit;
+  const uint64_t im = c->im, sp = c->sp;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int g = lane / S, sl = lane % S;
+  const uint64_t groups = (uint64_t)gridDim.x * WAVES * T::G;
+  for (uint64_t j = ((uint64_t)blockIdx.x * WAVES + wv) * T::G + g; j < commit; j += groups) {
+    const uint64_t lo = sp - 1 - j, hi = lo + im + 1;
+    const uint64_t wl = a.buckets[lo * S + sl], wh = a.buckets[hi * S + sl];
+    const uint64_t fl = (ballot(wl == EMPTY) >> (g * S)) & T::FULL;
+    const uint64_t lh = (ballot(wh != EMPTY) >> (g * S)) & T::FULL;
+    if (wh != EMPTY) {
+      // the r-th live entry of hi goes to the r-th empty slot of lo
+      const uint32_t r = __builtin_popcountll(lh & ((1ull << sl) - 1ull));
+      a.buckets[lo * S + nth_set_bit(fl, r)] = wh;
+      a.buckets[hi * S + sl] = EMPTY;
+    }
+    // stash entries with a candidate in hi now address lo
+    if (sl == 0 && ((a.hint[hi >> 5] >> (hi & 31)) & 1u)) set_hint(a.hint, (uint32_t)lo);
+  }
+  if (last_block(&c->ticket)) {
+    c->ticket = 0;
+    c->sp = sp - commit;
+    c->n_buckets -= commit;
+    c->resize_todo -= commit;
+    if (commit < seg) c->resize_todo = 0;  // a pair did not fit: the call stops here
+    plan_next(c);
+  }
+}
+
+// After splits: move every stash and pending entry to the eviction worklist
+// (they are re-placed by the eviction phase under the new geometry) and
+// clear the hint bits (Section III-B "Overflow Stash").
+__global__ __launch_bounds__(BLOCK) void drain_kernel(uint64_t *stash, uint64_t stash_cap, uint64_t *pending,
+                                                      uint64_t pending_cap, uint32_t *hint, uint64_t hint_n,
+                                                      uint64_t *wl, Ctl *c) {
+  if (!c->split_happened) return;
+  const uint64_t n_stash = min(c->stash_count, stash_cap);
+  const uint64_t n_pend = min(c->pending_count, pending_cap);
+  const uint64_t total = n_stash + n_pend;
+  const uint64_t stride = (uint64_t)gridDim.x * BLOCK;
+  const uint64_t tid = (uint64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (total) {
+    for (uint64_t t = tid; t < hint_n; t += stride) hint[t] = 0u;
+  }
+  const uint64_t span = (total + stride - 1) / stride * stride;
+  const int lane = threadIdx.x & 63;
+  for (uint64_t t = tid; t < span; t += stride) {
+    uint64_t w = TOMB;
+    if (t < n_stash)
+      w = stash[t];
+    else if (t < total)
+      w = pending[t - n_stash];
+    const bool live = w != TOMB;
+    const uint64_t m = ballot(live);
+    if (m) {
+      const int leader = __builtin_ctzll(m);
+      uint64_t base = 0;
+      if (lane == leader) base = add64(&c->wl_count, (uint64_t)__popcll(m));
+      base = read_lane64(base, leader);
+      if (live) wl[base + rank_below(m)] = w;
+    }
+  }
+  if (last_block(&c->drain_ticket)) {
+    c->drain_ticket = 0;
+    c->stash_count = 0;
+    c->pending_count = 0;
+    c->split_happened = 0;
   }
 }
 
@@ -750,6 +1045,40 @@ static void launch_evict(hive_table *h, hipStream_t st) {
   }
 }
 
+// Upper bound on the hashing rounds one resize call can cross: from the
+// initial bucket count to the arena size, plus the partial rounds at both
+// ends.
+static int resize_rounds(const hive_table *h) {
+  int r = 2;
+  for (uint64_t x = h->initial_buckets; x < h->max_buckets; x *= 2) ++r;
+  return r;
+}
+
+template <int S>
+static void launch_resize_passes(const ResizeArgs &ra, int rounds, hipStream_t st) {
+  for (int r = 0; r < rounds; ++r) {
+    hipLaunchKernelGGL(resize_pass1_kernel<S>, dim3(RESIZE_GRID), dim3(BLOCK), 0, st, ra);
+    hipLaunchKernelGGL(resize_pass2_kernel<S>, dim3(RESIZE_GRID), dim3(BLOCK), 0, st, ra);
+  }
+}
+
+static hive_status resize_sequence(hive_table *h, uint32_t mode, uint64_t amount, const uint8_t *d_ops,
+                                   hipStream_t st) {
+  ResizeArgs ra{h->d_buckets, h->d_hint, h->d_ctl, h->S, h->cfg.resize_k, h->cfg.lf_expand_pct,
+                h->cfg.lf_contract_pct};
+  hipLaunchKernelGGL(resize_plan_kernel, dim3(1), dim3(BLOCK), 0, st, ra, mode, amount, d_ops);
+  const int rounds = resize_rounds(h);
+  switch (h->S) {
+    case 16: launch_resize_passes<16>(ra, rounds, st); break;
+    case 32: launch_resize_passes<32>(ra, rounds, st); break;
+    default: launch_resize_passes<64>(ra, rounds, st); break;
+  }
+  hipLaunchKernelGGL(drain_kernel, dim3(DRAIN_GRID), dim3(BLOCK), 0, st, h->d_stash, h->stash_cap, h->d_pending,
+                     h->pending_cap, h->d_hint, hint_words(h->max_buckets), h->d_wl, h->d_ctl);
+  launch_evict(h, st);
+  return launch_check();
+}
+
 static hive_status run_batch(hive_t h, uint32_t mode, const uint8_t *d_ops, const uint32_t *d_keys,
                              const uint32_t *d_vals, uint64_t n, uint32_t flags, uint32_t *d_vals_out,
                              uint8_t *d_flags_out, void *stream) {
@@ -789,6 +1118,11 @@ static hive_status run_batch(hive_t h, uint32_t mode, const uint8_t *d_ops, cons
     a.dd = h->d_dd;
     a.dd_mask = cap - 1;
   }
+  const bool linear = h->cfg.addressing == HIVE_LINEAR;
+  if (linear && h->cfg.pre_expand && (mode == OP_INSERT || mode == OP_MIXED)) {
+    // grow before the batch so that live + (inserts of the batch) fits
+    if ((s = resize_sequence(h, mode == OP_MIXED ? PLAN_PRE_MIXED : PLAN_PRE, n, d_ops, st)) != HIVE_OK) return s;
+  }
   switch (h->S) {
     case 16: launch_ops_mode<16>(mode, a, st); break;
     case 32: launch_ops_mode<32>(mode, a, st); break;
@@ -798,6 +1132,9 @@ static hive_status run_batch(hive_t h, uint32_t mode, const uint8_t *d_ops, cons
   if (mode == OP_INSERT || mode == OP_MIXED) {
     launch_evict(h, st);
     if ((s = launch_check()) != HIVE_OK) return s;
+  }
+  if (linear && h->cfg.post_policy && mode != OP_LOOKUP) {
+    if ((s = resize_sequence(h, PLAN_POST, 0, nullptr, st)) != HIVE_OK) return s;
   }
   return HIVE_OK;
 }
@@ -859,7 +1196,9 @@ hive_status hive_create(const hive_config *cfg_in, uint64_t initial_buckets, voi
   }
   hipStream_t st = (hipStream_t)stream;
   h->last = st;
-  if (cfg.max_batch && (s = ensure_scratch(h, cfg.max_batch, true, st)) != HIVE_OK) {
+  // the worklist must hold a full stash + pending drain (after a split)
+  const uint64_t min_wl = h->stash_cap + h->pending_cap;
+  if ((s = ensure_scratch(h, std::max<uint64_t>(cfg.max_batch, min_wl), cfg.max_batch > 0, st)) != HIVE_OK) {
     free_table(h);
     return s;
   }
@@ -902,9 +1241,11 @@ hive_status hive_mixed_batch(hive_t h, const uint8_t *d_ops, const uint32_t *d_k
 hive_status hive_resize(hive_t h, int64_t delta, void *stream) {
   if (!h) return HIVE_ERR_ARG;
   if (h->cfg.addressing != HIVE_LINEAR) return HIVE_ERR_ARG;
-  (void)delta;
-  (void)stream;
-  return HIVE_ERR_ARG;  // linear-hashing resize lands with the split/merge kernels
+  hipStream_t st = (hipStream_t)stream;
+  h->last = st;
+  if (delta > 0) return resize_sequence(h, PLAN_SPLIT, (uint64_t)delta, nullptr, st);
+  if (delta < 0) return resize_sequence(h, PLAN_MERGE, (uint64_t)(-(delta + 1)) + 1, nullptr, st);
+  return resize_sequence(h, PLAN_POST, 0, nullptr, st);
 }
 
 hive_status hive_stats(hive_t h, hive_stats_t *out, void *stream) {

@@ -58,15 +58,19 @@ struct alignas(128) Ctl {
   uint64_t full_chains;
   uint64_t invalid_keys;
   uint64_t evict_items;
-  // resize bookkeeping (device-side policy)
-  uint64_t resize_todo;    // pairs the current resize step still has to do
-  uint64_t merge_commit;   // pairs of a merge step that passed the feasibility test
+  // resize bookkeeping (device-side policy, Section IV-C)
+  int64_t resize_dir;      // +1 split, -1 merge, 0 idle
+  uint64_t resize_todo;    // pairs the current resize call still has to do
+  uint64_t seg;            // pairs of the current round segment
+  uint64_t merge_commit;   // merge segment: pairs from the top that fit
+  uint64_t ticket;         // blocks of a resize pass that finished
+  uint64_t split_happened; // a split ran since the last stash drain
+  uint64_t drain_ticket;
   uint64_t initial_buckets;
   uint64_t max_buckets;
   // placement census (hive_placement)
   uint64_t place_first;
   uint64_t place_second;
-  uint64_t reserved_[4];
 };
 
 // ---- Section III-C hashes -------------------------------------------------

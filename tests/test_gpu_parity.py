@@ -291,3 +291,153 @@ def test_bulk_95pct_full_size(H):
     checked against the generator's closed-form expectation."""
     st = run_bulk(H, 1 << 26, seed=2)
     print("bulk 2^26 stats:", st)
+
+
+def linear_table(H, nb, max_buckets, K, pre=1, post=1, lf_e=90, lf_c=25, stash=256):
+    return H.Table(nb, addressing=H.HIVE_LINEAR, max_buckets=max_buckets, resize_k=K, pre_expand=pre,
+                   post_policy=post, lf_expand_pct=lf_e, lf_contract_pct=lf_c, stash_capacity=stash,
+                   pending_capacity=1024)
+
+
+def geometry(st):
+    return st["n_buckets"], st["index_mask"], st["split_ptr"]
+
+
+def same_geometry(gpu_st, o2):
+    """Equal bucket counts give equal addressing; (im, sp) agree up to the
+    equivalent form sp == im + 1 that a merge regress leaves."""
+    ost = o2.stats()
+    g, o = geometry(gpu_st), (ost["n_buckets"], ost["index_mask"], ost["split_ptr"])
+    norm = lambda t: (t[0], 2 * t[1] + 1, 0) if t[2] == t[1] + 1 else t  # noqa: E731
+    return norm(g) == norm(o)
+
+
+def policy_stable(t, S, lf_e=90, lf_c=25, initial=None):
+    """After a post-batch policy call the table is not over the expand
+    threshold, and it is under the contract threshold only when it is at its
+    initial size or the next merge pair (from the top) does not fit."""
+    st = t.stats()
+    nb, im, sp, live = st["n_buckets"], st["index_mask"], st["split_ptr"], st["live"]
+    assert live * 100 <= lf_e * nb * S
+    if live * 100 >= lf_c * nb * S or nb == initial:
+        return False
+    if sp == 0:
+        im, sp = im >> 1, (im >> 1) + 1
+    lo, hi = sp - 1, sp - 1 + im + 1
+    _, where = t.dump(with_where=True)
+    counts = np.bincount(where[where >= 0], minlength=nb)
+    assert counts[hi] > S - counts[lo], f"merge of ({lo}, {hi}) fits but the policy stopped"
+    return True
+
+
+@pytest.mark.parametrize("K", [1, 7, 64])
+def test_linear_growth_and_contraction_match_oracle(H, K):
+    """Pre-batch expansion and post-batch contraction (Section IV-C): the
+    bucket count, index mask and split pointer after every batch equal the
+    oracle's, and every key stays reachable.  Splits never abort, so growth
+    matches exactly; a merge stops at the first pair whose entries do not fit
+    the low bucket, which depends on the physical layout (not part of the
+    contract), so once the GPU's layout blocks a merge the test checks that
+    the block is real instead of comparing geometry."""
+    S, nb0, mb = 16, 8, 4096
+    t = linear_table(H, nb0, mb, K)
+    o2 = oracle.O2(S, 8, 256, oracle.ADDR_LINEAR, nb0, max_buckets=mb, resize_k=K)
+    o1 = oracle.O1()
+    ks = wl.KeyStream(50 + K)
+    n_batch = 3000
+    for b in range(6):
+        case(f"linear K={K} insert batch {b}")
+        keys = ks.range(b * n_batch, (b + 1) * n_batch)
+        vals = wl.values_for(keys)
+        o2.policy_pre(n_batch)
+        o2.insert(keys, vals)
+        o2.policy_post()
+        o1.insert(keys, vals)
+        t.insert(dev(keys), dev(vals), flags=H.HIVE_UNIQUE)
+        st = t.stats()
+        assert st["status"] == H.HIVE_OK, st
+        assert same_geometry(st, o2), (geometry(st), o2.stats())
+        assert st["live"] == len(o1)
+    allk = ks.range(0, 6 * n_batch + 500)
+    v, f = t.lookup(dev(allk))
+    ov, of = o1.lookup(allk)
+    assert np.array_equal(host(f), of) and np.array_equal(host(v), ov)
+    rng = np.random.default_rng(K)
+    order = rng.permutation(6 * n_batch)
+    diverged = False
+    for b in range(5):
+        case(f"linear K={K} delete batch {b}")
+        dk = allk[order[b * 3400:(b + 1) * 3400]]
+        d = t.delete(dev(dk), flags=H.HIVE_UNIQUE)
+        o2.delete(dk)
+        o2.policy_post()
+        assert np.array_equal(host(d), o1.delete(dk))
+        st = t.stats()
+        blocked = policy_stable(t, S, initial=nb0)
+        if not diverged and not same_geometry(st, o2):
+            assert blocked, (geometry(st), o2.stats())
+            assert st["n_buckets"] > o2.stats()["n_buckets"]
+            diverged = True
+        assert st["live"] == len(o1)
+        v, f = t.lookup(dev(allk))
+        ov, of = o1.lookup(allk)
+        assert np.array_equal(host(f), of) and np.array_equal(host(v), ov)
+    words, where = t.dump(with_where=True)
+    assert np.array_equal(words, o1.dump())
+    check_placement(words, where, S, nb0, oracle.ADDR_LINEAR, mb, geo=t.stats()["n_buckets"])
+    t.close()
+
+
+def test_linear_explicit_split_merge_and_stash_drain(H):
+    """hive_resize(+d) splits d pairs, hive_resize(-d) merges d pairs top
+    down; stash entries survive splits (drained and re-placed) and merges."""
+    S, nb0, mb = 16, 4, 256
+    t = linear_table(H, nb0, mb, 4, pre=0, post=0, stash=512)
+    o1 = oracle.O1()
+    ks = wl.KeyStream(77)
+    keys = ks.range(0, 80)  # 80 keys into 64 slots: the stash must hold some
+    vals = wl.values_for(keys)
+    t.insert(dev(keys), dev(vals), flags=H.HIVE_UNIQUE)
+    o1.insert(keys, vals)
+    st = t.stats()
+    assert st["stash_count"] + st["pending_count"] > 0 and st["live"] == 80
+    for delta, exp_nb in ((5, 9), (40, 49), (-3, 46), (100, 146), (-50, 96)):
+        case(f"explicit resize {delta}")
+        t.resize(delta)
+        st = t.stats()
+        assert st["n_buckets"] == exp_nb, (delta, st)
+        v, f = t.lookup(dev(keys))
+        ov, of = o1.lookup(keys)
+        assert np.array_equal(host(f), of) and np.array_equal(host(v), ov)
+        words, where = t.dump(with_where=True)
+        assert np.array_equal(words, o1.dump())
+        check_placement(words, where, S, nb0, oracle.ADDR_LINEAR, mb, geo=st["n_buckets"])
+    t.close()
+
+
+def test_linear_merge_stops_when_pair_does_not_fit(H):
+    """A full low bucket blocks its merge: the top pairs merge, the call
+    stops at the first pair that does not fit."""
+    S, nb0, mb = 16, 2, 64
+    t = linear_table(H, nb0, mb, 1, pre=0, post=0)
+    t.resize(30)  # 32 buckets
+    assert t.stats()["n_buckets"] == 32
+    o2 = oracle.O2(S, 8, 16, oracle.ADDR_LINEAR, nb0, max_buckets=mb)
+    o2.split(30)
+    # fill bucket 1 completely with keys whose two candidates are both 1, and
+    # put one key in its partner 17 (both candidates 17)
+    ks = wl.KeyStream(91)
+    cand = ks.range(0, 200000)
+    c1, c2 = o2.candidates(cand)
+    in1 = cand[(c1 == 1) & (c2 == 1)][:16]
+    in17 = cand[(c1 == 17) & (c2 == 17)][:1]
+    assert in1.size == 16 and in17.size == 1
+    ins = np.concatenate([in1, in17])
+    t.insert(dev(ins), dev(wl.values_for(ins)), flags=H.HIVE_UNIQUE)
+    # merging 20 pairs from the top: pairs (15,31)..(2,18) fit, (1,17) does not
+    t.resize(-20)
+    st = t.stats()
+    assert st["n_buckets"] == 18, st
+    v, f = t.lookup(dev(ins))
+    assert host(f).all()
+    t.close()
