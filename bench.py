@@ -39,7 +39,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", choices=("bulk", "mixed", "resize"), default="bulk")
     ap.add_argument("--keys-log2", type=int, default=26)
+    ap.add_argument("--batches", type=int, default=64, help="mixed/resize: insert batches")
+    ap.add_argument("--batch-log2", type=int, default=22, help="mixed/resize: operations per batch")
+    ap.add_argument("--resize-k", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-log2", type=int, default=22)
     return ap.parse_args()
@@ -79,6 +83,169 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
+    out = {"bulk": run_bulk, "mixed": run_mixed, "resize": run_resize}[args.workload](args)
+    print(json.dumps(out), flush=True)
+
+
+def base_record(args, value, ms_step, workload, extra_config):
+    return {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "Mops/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": workload, **extra_config},
+    }
+
+
+def _gen_mixed(b, n_ops, universe):
+    from paper_2510_15095_amd import workload as wl
+    mb = wl.mixed_batch(3, b, n_ops, universe)
+    return mb["ops"], mb["keys"], mb["vals"]
+
+
+def run_mixed(args):
+    """Mixed contended workload: a LINEAR table pre-filled with 2^24 keys
+    (uniform sample of a 2^26-key Zipf universe) at 95% load, then `batches`
+    batches of 2^22 operations (40% insert incl. repeats, 40% delete, 20%
+    lookup; Zipf(0.99) keys; per-batch disjoint key sets per type), each one
+    hive_mixed_batch call with dedupe; post-batch load-factor rule at 95%."""
+    import multiprocessing as mp
+
+    import torch
+    from paper_2510_15095_amd import hive as H
+    from paper_2510_15095_amd import workload as wl
+    universe, n_pre = 1 << 26, 1 << 24
+    n_ops, nbat = 1 << args.batch_log2, args.batches
+    nb0 = 1103765
+    ks = wl.KeyStream(3)
+    pre_ranks = wl.DomainPerm(wl.batch_seed(3, 0xBEEF), universe).sample(n_pre)
+    pre_keys = ks.keys(pre_ranks)
+    # generate every batch before the GPU is touched (worker processes are
+    # forked from this one)
+    with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
+        gen = pool.starmap(_gen_mixed, [(b, n_ops, universe) for b in range(nbat)])
+    dev = torch.device("cuda:0")
+    pk = torch.from_numpy(pre_keys).to(dev)
+    pv = torch.from_numpy(wl.values_for(pre_keys)).to(dev)
+    batches = [tuple(torch.from_numpy(a).to(dev) for a in g) for g in gen]
+    del gen
+    vout = torch.empty(n_ops, dtype=torch.uint32, device=dev)
+    fout = torch.empty(n_ops, dtype=torch.uint8, device=dev)
+    t = H.Table(nb0, addressing=H.HIVE_LINEAR, max_buckets=4 * nb0, lf_expand_pct=95, post_policy=1,
+                resize_k=args.resize_k, max_batch=n_ops)
+
+    def prefill():
+        t.clear()
+        t.insert(pk, pv, flags=H.HIVE_UNIQUE)
+        torch.cuda.synchronize()
+
+    def run(evs):
+        for j, (o, k, v) in enumerate(batches):
+            evs[j].record()
+            H.hive_mixed_batch(t.h, o, k, v, vout, fout)
+        evs[-1].record()
+
+    mk = lambda: [torch.cuda.Event(enable_timing=True) for _ in range(nbat + 1)]  # noqa: E731
+    for _ in range(args.warmup):
+        prefill()
+        run(mk())
+    times = []
+    for _ in range(args.steps):
+        prefill()
+        ev = mk()
+        run(ev)
+        torch.cuda.synchronize()
+        times.append([ev[j].elapsed_time(ev[j + 1]) for j in range(nbat)])
+    ms = np.array(times)
+    st = t.stats()
+    ms_step = float(ms.sum(axis=1).mean())
+    rec = base_record(args, nbat * n_ops / (ms_step * 1e-3) / 1e6, ms_step,
+                      f"mixed contended, plain launch: prefill 2^24 of a 2^26-key Zipf universe at 95% load "
+                      f"(LINEAR, {nb0} x 16-slot buckets), {nbat} batches of 2^{args.batch_log2} ops "
+                      f"40/40/20 insert/delete/lookup, Zipf(0.99), per-type disjoint, dedupe on",
+                      {"ops_per_step": nbat * n_ops, "batches": nbat, "resize_k": args.resize_k})
+    rec["batch_ms"] = {"mean": round(float(ms.mean()), 4), "p50": round(float(np.percentile(ms, 50)), 4),
+                       "p99": round(float(np.percentile(ms, 99)), 4)}
+    rec["final_stats"] = {k: st[k] for k in ("live", "n_buckets", "stash_count", "pending_count", "evictions",
+                                             "evict_items", "status")}
+    t.close()
+    return rec
+
+
+def run_resize(args):
+    """Dynamic resize cycle: a LINEAR table of 2^16 buckets (2^20 slots)
+    takes `batches` batches of 2^22 unique uniform inserts with pre-batch
+    expansion at 90% load, then 90% of the keys are deleted in random order
+    in 2^22-op batches with post-batch contraction under 25% load."""
+    import torch
+    from paper_2510_15095_amd import hive as H
+    from paper_2510_15095_amd import workload as wl
+    nbat, nb_ops = args.batches, 1 << args.batch_log2
+    n = nbat * nb_ops
+    n_del = int(n * 0.9)
+    ks = wl.KeyStream(4)
+    dev = torch.device("cuda:0")
+    keys = torch.from_numpy(ks.range(0, n)).to(dev)
+    vals = torch.from_numpy(wl.values_for(keys.cpu().numpy())).to(dev)
+    dkeys = torch.from_numpy(ks.keys(wl.DomainPerm(wl.batch_seed(4, 0xDE1), n).sample(n_del))).to(dev)
+    nb0 = 1 << 16
+    max_b = 1
+    while max_b * 16 * 0.9 < n * 1.05:
+        max_b *= 2
+    t = H.Table(nb0, addressing=H.HIVE_LINEAR, max_buckets=max_b, pre_expand=1, post_policy=1, lf_expand_pct=90,
+                lf_contract_pct=25, resize_k=args.resize_k, max_batch=nb_ops)
+    dout = torch.empty(nb_ops, dtype=torch.uint8, device=dev)
+    n_del_batches = (n_del + nb_ops - 1) // nb_ops
+
+    def run(ev):
+        t.clear()
+        ev[0].record()
+        for b in range(nbat):
+            t.insert(keys[b * nb_ops:(b + 1) * nb_ops], vals[b * nb_ops:(b + 1) * nb_ops], flags=H.HIVE_UNIQUE)
+        ev[1].record()
+        peak = t.stats()["n_buckets"]  # synchronises between the two timed intervals
+        ev[2].record()
+        for b in range(n_del_batches):
+            dk = dkeys[b * nb_ops:min(n_del, (b + 1) * nb_ops)]
+            H.hive_delete_batch(t.h, dk, dout[:dk.numel()], H.HIVE_UNIQUE)
+        ev[3].record()
+        return peak
+
+    mk = lambda: [torch.cuda.Event(enable_timing=True) for _ in range(4)]  # noqa: E731
+    for _ in range(args.warmup):
+        run(mk())
+    res = []
+    peak = 0
+    for _ in range(args.steps):
+        ev = mk()
+        peak = run(ev)
+        torch.cuda.synchronize()
+        res.append((ev[0].elapsed_time(ev[1]), ev[2].elapsed_time(ev[3])))
+    ms = np.array(res)
+    st = t.stats()
+    ms_step = float(ms.sum(axis=1).mean())
+    rec = base_record(args, (n + n_del) / (ms_step * 1e-3) / 1e6, ms_step,
+                      f"dynamic resize cycle: LINEAR from 2^16 x 16-slot buckets, {nbat} batches of 2^{args.batch_log2} "
+                      f"unique uniform inserts with pre-batch expansion at 90%, then delete 90% in random order with "
+                      f"contraction under 25%, K={args.resize_k}",
+                      {"ops_per_step": n + n_del, "resize_k": args.resize_k})
+    rec["phase_mops"] = {"insert_with_growth": round(n / (ms[:, 0].mean() * 1e-3) / 1e6, 1),
+                         "delete_with_contraction": round(n_del / (ms[:, 1].mean() * 1e-3) / 1e6, 1)}
+    rec["peak_buckets"] = peak
+    rec["final_stats"] = {k: st[k] for k in ("live", "n_buckets", "stash_count", "pending_count", "status")}
+    t.close()
+    return rec
+
+
+def run_bulk(args):
     import torch
     from paper_2510_15095_amd import hive as H
     from paper_2510_15095_amd import workload as wl
@@ -206,7 +373,7 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample_log2)
     t.close()
-    print(json.dumps(out), flush=True)
+    return out
 
 
 if __name__ == "__main__":

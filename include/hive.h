@@ -57,8 +57,9 @@ enum {
                       and none among its deletes: skips the dedupe pass */
 };
 
-/* Op codes for hive_mixed_batch. */
-enum { HIVE_OP_INSERT = 0, HIVE_OP_DELETE = 1, HIVE_OP_LOOKUP = 2 };
+/* Op codes for hive_mixed_batch; HIVE_OP_MIXED marks a batch descriptor
+ * whose per-operation codes are in d_ops. */
+enum { HIVE_OP_INSERT = 0, HIVE_OP_DELETE = 1, HIVE_OP_LOOKUP = 2, HIVE_OP_MIXED = 3 };
 
 typedef struct {
   uint32_t slots_per_bucket;  /* S: 16 (one 128-byte line) or 64 */
@@ -174,6 +175,56 @@ hive_status hive_clear(hive_t h, void *stream);
 
 /* A short English description of a status code (static storage). */
 const char *hive_status_string(hive_status s);
+
+/* ---- Persistent executor ------------------------------------------------
+ * One resident grid drains a queue of batches in one launch (a hipGraph
+ * captured once and replayed).  Each batch runs the same phases and gives
+ * the same results as the batch call of its kind (hive_insert_batch,
+ * hive_delete_batch, hive_lookup_batch, hive_mixed_batch, including the
+ * table's pre/post load-factor rules); batches on one table run in
+ * submission order, batches on different tables overlap.  While a table has
+ * batches in an executor, no batch call may run on it. */
+typedef struct hive_drain *hive_drain_t;
+
+typedef struct {
+  uint32_t op_mode;        /* HIVE_OP_INSERT, _DELETE, _LOOKUP, or _MIXED (d_ops) */
+  uint32_t flags;          /* HIVE_UNIQUE */
+  const uint8_t *d_ops;    /* HIVE_OP_MIXED: per-operation codes */
+  const uint32_t *d_keys;
+  const uint32_t *d_vals;  /* inserts */
+  uint32_t *d_vals_out;    /* lookups; may be NULL */
+  uint8_t *d_flags_out;    /* lookups (found), deletes (deleted); may be NULL */
+  uint64_t n;
+} hive_batch_desc;
+
+/* Create an executor for tables of `slots_per_bucket` slots.  It holds a
+ * ring of `ring_capacity` batches and up to `max_tables` tables;
+ * `blocks_per_cu` = resident blocks per compute unit (0 = as many as fit);
+ * `idle_limit` = idle polls after which a resident block gives up (0 = the
+ * default, tens of seconds), a watchdog in case the host never stops it. */
+hive_status hive_drain_create(uint32_t slots_per_bucket, uint32_t blocks_per_cu, uint64_t ring_capacity,
+                              uint32_t max_tables, uint64_t idle_limit, hive_drain_t *out);
+
+/* Append a batch (host only; no HIP call).  *ticket identifies it.  Returns
+ * HIVE_ERR_BUDGET when the ring is full or a running executor would need
+ * more scratch than the table has (create tables with max_batch). */
+hive_status hive_drain_submit(hive_drain_t d, hive_t table, const hive_batch_desc *b, uint64_t *ticket);
+
+/* Launch the resident grid on `stream`.  resident = 0: it exits once every
+ * batch submitted so far is complete.  resident = 1: it keeps serving
+ * batches submitted later until hive_drain_stop. */
+hive_status hive_drain_launch(hive_drain_t d, int resident, void *stream);
+
+/* *done = 1 once the batch's outputs and table updates are complete and
+ * visible to the host (no HIP call). */
+hive_status hive_drain_poll(hive_drain_t d, uint64_t ticket, int *done);
+
+/* Tell a resident grid to exit when its queue is empty and wait for it on
+ * `stream`.  Returns HIVE_ERR_HIP if a block gave up on its idle watchdog. */
+hive_status hive_drain_stop(hive_drain_t d, void *stream);
+
+/* Stop (if needed), synchronize and free the executor. */
+hive_status hive_drain_destroy(hive_drain_t d);
 
 /* Host-callable copies of the device hash and reduction, for tests: the
  * full 32-bit BitHash1/BitHash2 mixes (Section III-C) and the bucket a mixed

@@ -28,6 +28,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -43,6 +44,9 @@ constexpr int BLOCK = 64 * WAVES;
 constexpr int EVICT_GRID = 1024;  // blocks of the eviction phase (grid-stride)
 constexpr int RESIZE_GRID = 2048; // blocks of a resize pass (grid-stride over pairs)
 constexpr int DRAIN_GRID = 256;
+#ifndef OPS_WAVES_PER_EU
+#define OPS_WAVES_PER_EU 4  // occupancy target of the probe kernel (waves per SIMD)
+#endif
 
 template <int S>
 struct Traits {
@@ -54,12 +58,12 @@ struct Traits {
   static constexpr uint64_t FULL = (S == 64) ? ~0ull : ((1ull << S) - 1ull);
 };
 
-__device__ inline int ctz_mask(uint32_t m) { return __builtin_ctz(m); }
-__device__ inline int ctz_mask(uint64_t m) { return __builtin_ctzll(m); }
-__device__ inline int popc_mask(uint32_t m) { return __builtin_popcount(m); }
-__device__ inline int popc_mask(uint64_t m) { return __builtin_popcountll(m); }
+__device__ __forceinline__ int ctz_mask(uint32_t m) { return __builtin_ctz(m); }
+__device__ __forceinline__ int ctz_mask(uint64_t m) { return __builtin_ctzll(m); }
+__device__ __forceinline__ int popc_mask(uint32_t m) { return __builtin_popcount(m); }
+__device__ __forceinline__ int popc_mask(uint64_t m) { return __builtin_popcountll(m); }
 
-__device__ inline uint64_t read_lane64(uint64_t x, int lane) {
+__device__ __forceinline__ uint64_t read_lane64(uint64_t x, int lane) {
   uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, lane);
   uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), lane);
   return ((uint64_t)hi << 32) | lo;
@@ -98,10 +102,8 @@ __global__ __launch_bounds__(BLOCK) void fill_u32_kernel(uint32_t *p, uint64_t n
   for (uint64_t t = (uint64_t)blockIdx.x * BLOCK + threadIdx.x; t < n; t += (uint64_t)gridDim.x * BLOCK) p[t] = v;
 }
 
-__global__ __launch_bounds__(BLOCK) void dedupe_build_kernel(uint64_t *dd, uint64_t mask, uint32_t mode,
-                                                             const uint8_t *ops, const uint32_t *keys, uint64_t n) {
-  const uint64_t i = (uint64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (i >= n) return;
+__device__ __forceinline__ void dedupe_insert(uint64_t *dd, uint64_t mask, uint32_t mode, const uint8_t *ops,
+                                              const uint32_t *keys, uint64_t i) {
   const uint32_t op = (mode == OP_MIXED) ? ops[i] : mode;
   const uint32_t k = keys[i];
   if (op > OP_DELETE || !valid_key(k)) return;
@@ -124,7 +126,13 @@ __global__ __launch_bounds__(BLOCK) void dedupe_build_kernel(uint64_t *dd, uint6
   }
 }
 
-__device__ inline bool dedupe_winner(const uint64_t *dd, uint64_t mask, uint32_t k, uint32_t i) {
+__global__ __launch_bounds__(BLOCK) void dedupe_build_kernel(uint64_t *dd, uint64_t mask, uint32_t mode,
+                                                             const uint8_t *ops, const uint32_t *keys, uint64_t n) {
+  const uint64_t i = (uint64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (i < n) dedupe_insert(dd, mask, mode, ops, keys, i);
+}
+
+__device__ __forceinline__ bool dedupe_winner(const uint64_t *dd, uint64_t mask, uint32_t k, uint32_t i) {
   uint64_t s = mix32(k) & mask;
   for (uint64_t probe = 0; probe <= mask; ++probe) {
     const uint64_t cur = dd[s];
@@ -139,56 +147,110 @@ __device__ inline bool dedupe_winner(const uint64_t *dd, uint64_t mask, uint32_t
 // P1 helpers
 // ---------------------------------------------------------------------------
 
-// One probe round of match-and-elect: for each of `count` operations (ops
-// list[t], or t when list is null) the 16-lane group loads bucket bkt[o] and
-// publishes, through LDS, the match mask, the empty-slot mask and the word of
-// the lowest matching slot.
+// One probe round of match-and-elect.  Operations t < count of the round
+// have their key and bucket in keys[t], bkts[t] and their owning lane in
+// list[t] (t itself when list is null).  Each 16-lane group loads one bucket
+// per wave-wide load and publishes, through LDS and indexed by the owning
+// lane, the match mask, the empty-slot mask and the word of the lowest
+// matching slot.  All operands are read from LDS first and all loads of a
+// chunk are issued before any is consumed; idle group slots of the last
+// chunk re-load the round's last bucket and their result is ignored, so the
+// loads carry no control flow.
 template <int S>
-__device__ inline void probe_round(const uint64_t *__restrict__ buckets, const uint32_t *key, const uint32_t *bkt,
-                                   const uint8_t *list, int count, typename Traits<S>::Mask *m_out,
-                                   typename Traits<S>::Mask *e_out, uint64_t *w_out, int g, int sl) {
+__device__ __forceinline__ void probe_round(const uint64_t *__restrict__ buckets, const uint32_t *keys,
+                                            const uint32_t *bkts, const uint8_t *list, int count,
+                                            typename Traits<S>::Mask *m_out, typename Traits<S>::Mask *e_out,
+                                            uint64_t *w_out, int g, int sl) {
   using T = Traits<S>;
   using Mask = typename T::Mask;
   for (int base = 0; base < count; base += T::OPS_PER_CHUNK) {
     uint64_t w[T::CH];
 #pragma unroll
     for (int j = 0; j < T::CH; ++j) {
-      w[j] = EMPTY;
-      const int t = base + j * T::G + g;
-      if (base + j * T::G < count && t < count) {
-        const int o = list ? list[t] : t;
-        if (key[o] != 0u) w[j] = buckets[(uint64_t)bkt[o] * S + sl];
-      }
+      const int t = min(base + j * T::G + g, count - 1);
+      w[j] = buckets[(uint64_t)bkts[t] * S + sl];
     }
 #pragma unroll
     for (int j = 0; j < T::CH; ++j) {
-      if (base + j * T::G < count) {
-        const int t = base + j * T::G + g;
-        const bool mine = t < count;
-        const int o = mine ? (list ? list[t] : t) : 0;
-        const uint32_t ko = mine ? key[o] : 0u;
-        const uint64_t mm = ballot(ko != 0u && key_of(w[j]) == ko);
-        const uint64_t ee = ballot(w[j] == EMPTY);
-        const Mask gm = (Mask)((mm >> (g * S)) & T::FULL);
-        const Mask ge = (Mask)((ee >> (g * S)) & T::FULL);
-        if (mine) {
-          if (sl == 0) {
-            m_out[o] = gm;
-            e_out[o] = ge;
-          }
-          if (gm != 0 && sl == ctz_mask(gm)) w_out[o] = w[j];
+      const int t = base + j * T::G + g;
+      const bool mine = t < count;
+      const uint32_t ko = keys[min(t, count - 1)];
+      const uint64_t mm = ballot(mine && ko != 0u && key_of(w[j]) == ko);
+      const uint64_t ee = ballot(w[j] == EMPTY);
+      const Mask gm = (Mask)((mm >> (g * S)) & T::FULL);
+      const Mask ge = (Mask)((ee >> (g * S)) & T::FULL);
+      if (mine) {
+        const int o = list ? list[t] : t;
+        if (sl == 0) {
+          m_out[o] = gm;
+          e_out[o] = ge;
         }
+        if (gm != 0 && sl == ctz_mask(gm)) w_out[o] = w[j];
       }
     }
   }
 }
 
-__device__ inline bool hinted(const uint32_t *hint, uint32_t c1, uint32_t c2) {
+// Both probe rounds of an insert batch at once (S = 16): 16 loads for the
+// first candidates of the wave's 64 operations and up to 16 for the second
+// candidates are in flight together.
+template <int S>
+__device__ __forceinline__ void probe_round_pair(const uint64_t *__restrict__ buckets, const uint32_t *keys1,
+                                                 const uint32_t *bkts1, typename Traits<S>::Mask *m1_out,
+                                                 typename Traits<S>::Mask *e1_out, uint64_t *w1_out,
+                                                 const uint32_t *keys2, const uint32_t *bkts2, const uint8_t *list2,
+                                                 int count2, typename Traits<S>::Mask *m2_out,
+                                                 typename Traits<S>::Mask *e2_out, uint64_t *w2_out, int g, int sl) {
+  using T = Traits<S>;
+  using Mask = typename T::Mask;
+  static_assert(S == 16, "the fused round covers one chunk per candidate");
+  const int last2 = count2 > 0 ? count2 - 1 : 0;
+  uint64_t wa[T::CH], wb[T::CH];
+#pragma unroll
+  for (int j = 0; j < T::CH; ++j) wa[j] = buckets[(uint64_t)bkts1[j * T::G + g] * S + sl];
+#pragma unroll
+  for (int j = 0; j < T::CH; ++j) {
+    const uint32_t b = count2 > 0 ? bkts2[min(j * T::G + g, last2)] : bkts1[j * T::G + g];
+    wb[j] = buckets[(uint64_t)b * S + sl];
+  }
+#pragma unroll
+  for (int j = 0; j < T::CH; ++j) {
+    const int t = j * T::G + g;
+    const uint32_t ko = keys1[t];
+    const uint64_t mm = ballot(ko != 0u && key_of(wa[j]) == ko);
+    const uint64_t ee = ballot(wa[j] == EMPTY);
+    const Mask gm = (Mask)((mm >> (g * S)) & T::FULL);
+    if (sl == 0) {
+      m1_out[t] = gm;
+      e1_out[t] = (Mask)((ee >> (g * S)) & T::FULL);
+    }
+    if (gm != 0 && sl == ctz_mask(gm)) w1_out[t] = wa[j];
+  }
+#pragma unroll
+  for (int j = 0; j < T::CH; ++j) {
+    const int t = j * T::G + g;
+    const bool mine = t < count2;
+    const uint32_t ko = mine ? keys2[t] : 0u;
+    const uint64_t mm = ballot(mine && ko != 0u && key_of(wb[j]) == ko);
+    const uint64_t ee = ballot(wb[j] == EMPTY);
+    const Mask gm = (Mask)((mm >> (g * S)) & T::FULL);
+    if (mine) {
+      const int o = list2[t];
+      if (sl == 0) {
+        m2_out[o] = gm;
+        e2_out[o] = (Mask)((ee >> (g * S)) & T::FULL);
+      }
+      if (gm != 0 && sl == ctz_mask(gm)) w2_out[o] = wb[j];
+    }
+  }
+}
+
+__device__ __forceinline__ bool hinted(const uint32_t *hint, uint32_t c1, uint32_t c2) {
   return ((hint[c1 >> 5] >> (c1 & 31)) & 1u) | ((hint[c2 >> 5] >> (c2 & 31)) & 1u);
 }
 
 // Lane-wise search of the stash ring and the pending list.
-__device__ inline uint64_t *overflow_find(uint64_t *stash, uint64_t n_stash, uint64_t *pending, uint64_t n_pend,
+__device__ __forceinline__ uint64_t *overflow_find(uint64_t *stash, uint64_t n_stash, uint64_t *pending, uint64_t n_pend,
                                           uint32_t k, uint64_t *word, bool fresh) {
   for (uint64_t p = 0; p < n_stash; ++p) {
     const uint64_t x = fresh ? load_fresh(stash + p) : stash[p];
@@ -207,46 +269,58 @@ __device__ inline uint64_t *overflow_find(uint64_t *stash, uint64_t n_stash, uin
   return nullptr;
 }
 
-// Lane-wise search of the two candidate buckets with fresh (L2) loads.
-template <int S>
-__device__ inline uint64_t *bucket_find_fresh(uint64_t *buckets, uint32_t c1, uint32_t c2, uint32_t k,
-                                              uint64_t *word) {
-  for (int j = 0; j < 2; ++j) {
-    const uint32_t b = j ? c2 : c1;
-    if (j && c2 == c1) break;
-    for (int s = 0; s < S; ++s) {
-      const uint64_t x = load_fresh(buckets + (uint64_t)b * S + s);
-      if (key_of(x) == k) {
-        *word = x;
-        return buckets + (uint64_t)b * S + s;
-      }
-    }
-  }
-  return nullptr;
-}
-
 // ---------------------------------------------------------------------------
 // P1: hash, probe, and replace / lookup / delete / claim.
 // ---------------------------------------------------------------------------
+// LDS of one block of the probe phase (per wave: 64 operations).
+template <int S>
+struct OpsShared {
+  using Mask = typename Traits<S>::Mask;
+  uint32_t key[WAVES][64];
+  uint32_t b1[WAVES][64];
+  uint32_t k2[WAVES][64];  // round 2, compacted: key, bucket, owner
+  uint32_t b2[WAVES][64];
+  uint8_t list[WAVES][64];
+  Mask m[2][WAVES][64];
+  Mask e[2][WAVES][64];
+  uint64_t w[2][WAVES][64];
+};
+
+// The table state a probe tile needs, read once per launch (or per chunk of
+// the persistent executor).
+struct OpsView {
+  Geo geo;
+  uint64_t n_stash, n_pend;
+};
+
+__device__ __forceinline__ OpsView read_view(const Ctl *c, uint64_t stash_cap, uint64_t pending_cap) {
+  OpsView v;
+  v.geo = read_geo(c);
+  v.n_stash = min(ld_ctl(&c->stash_count), stash_cap);
+  v.n_pend = min(ld_ctl(&c->pending_count), pending_cap);
+  return v;
+}
+
+// P1 for one tile of WAVES x 64 operations [tile * 256, tile * 256 + 256).
 template <int S, uint32_t MODE>
-__global__ __launch_bounds__(BLOCK) void ops_kernel(OpsArgs a) {
+__device__ __forceinline__ void ops_tile(const OpsArgs &a, const OpsView &view, uint64_t tile, OpsShared<S> &sh) {
   using T = Traits<S>;
   using Mask = typename T::Mask;
-  __shared__ uint32_t s_key[WAVES][64];
-  __shared__ uint32_t s_b1[WAVES][64];
-  __shared__ uint32_t s_b2[WAVES][64];
-  __shared__ uint8_t s_list[WAVES][64];
-  __shared__ Mask s_m[2][WAVES][64];
-  __shared__ Mask s_e[2][WAVES][64];
-  __shared__ uint64_t s_w[2][WAVES][64];
+  auto &s_key = sh.key;
+  auto &s_b1 = sh.b1;
+  auto &s_k2 = sh.k2;
+  auto &s_b2 = sh.b2;
+  auto &s_list = sh.list;
+  auto &s_m = sh.m;
+  auto &s_e = sh.e;
+  auto &s_w = sh.w;
 
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = lane / S, sl = lane % S;
-  const uint64_t i = ((uint64_t)blockIdx.x * WAVES + wv) * 64 + lane;
+  const uint64_t i = (tile * WAVES + wv) * 64 + lane;
   const bool active = i < a.n;
-  const Geo geo = read_geo(a.ctl);
-  const uint64_t n_stash = min(a.ctl->stash_count, a.stash_cap);
-  const uint64_t n_pend = min(a.ctl->pending_count, a.pending_cap);
+  const Geo &geo = view.geo;
+  const uint64_t n_stash = view.n_stash, n_pend = view.n_pend;
   const bool overflow_used = (n_stash | n_pend) != 0;
 
   uint32_t op = OP_NONE, k = 0, v = 0;
@@ -265,23 +339,53 @@ __global__ __launch_bounds__(BLOCK) void ops_kernel(OpsArgs a) {
   }
   s_key[wv][lane] = work ? k : 0u;
   s_b1[wv][lane] = c1;
-  s_b2[wv][lane] = c2;
   wave_lds_sync();
 
-  // round 1: first candidate of every operation
-  probe_round<S>(a.buckets, s_key[wv], s_b1[wv], nullptr, 64, s_m[0][wv], s_e[0][wv], s_w[0][wv], g, sl);
-  wave_lds_sync();
-  const Mask m1 = s_m[0][wv][lane], e1 = s_e[0][wv][lane];
-  const bool need2 = work && m1 == 0 && c2 != c1;
-  const uint64_t need2_mask = ballot(need2);
-  const int n2 = __popcll(need2_mask);
-  if (need2) s_list[wv][rank_below(need2_mask)] = (uint8_t)lane;
-  wave_lds_sync();
-  // round 2: second candidate of the operations that missed in the first
-  if (n2 > 0)
-    probe_round<S>(a.buckets, s_key[wv], s_b2[wv], s_list[wv], n2, s_m[1][wv], s_e[1][wv], s_w[1][wv], g, sl);
-  wave_lds_sync();
-  const Mask m2 = need2 ? s_m[1][wv][lane] : (Mask)0;
+  // Inserts of new keys need both candidates (absence check and two-choice
+  // placement), so insert batches probe both in one round; lookups and
+  // deletes probe the second candidate only after a miss in the first.
+  constexpr bool kFused = (MODE == OP_INSERT) && (S == 16);
+  Mask m1;
+  bool need2;
+  if constexpr (kFused) {
+    need2 = work && c2 != c1;
+    const uint64_t need2_mask = ballot(need2);
+    const int n2 = __popcll(need2_mask);
+    if (need2) {
+      const uint32_t r = rank_below(need2_mask);
+      s_k2[wv][r] = k;
+      s_b2[wv][r] = c2;
+      s_list[wv][r] = (uint8_t)lane;
+    }
+    wave_lds_sync();
+    probe_round_pair<S>(a.buckets, s_key[wv], s_b1[wv], s_m[0][wv], s_e[0][wv], s_w[0][wv], s_k2[wv], s_b2[wv],
+                        s_list[wv], n2, s_m[1][wv], s_e[1][wv], s_w[1][wv], g, sl);
+    wave_lds_sync();
+    m1 = s_m[0][wv][lane];
+  } else {
+    // round 1: first candidate of every operation
+    probe_round<S>(a.buckets, s_key[wv], s_b1[wv], nullptr, 64, s_m[0][wv], s_e[0][wv], s_w[0][wv], g, sl);
+    wave_lds_sync();
+    m1 = s_m[0][wv][lane];
+    need2 = work && m1 == 0 && c2 != c1;
+    const uint64_t need2_mask = ballot(need2);
+    const int n2 = __popcll(need2_mask);
+    if (need2) {
+      const uint32_t r = rank_below(need2_mask);
+      s_k2[wv][r] = k;
+      s_b2[wv][r] = c2;
+      s_list[wv][r] = (uint8_t)lane;
+    }
+    wave_lds_sync();
+    // round 2: second candidate of the operations that missed in the first
+    if (n2 > 0)
+      probe_round<S>(a.buckets, s_k2[wv], s_b2[wv], s_list[wv], n2, s_m[1][wv], s_e[1][wv], s_w[1][wv], g, sl);
+    wave_lds_sync();
+  }
+  const Mask e1 = s_e[0][wv][lane];
+  // with the fused round a match in the first candidate makes the second's
+  // result irrelevant; otherwise the second round ran only without one
+  const Mask m2 = (need2 && m1 == 0) ? s_m[1][wv][lane] : (Mask)0;
   const Mask e2 = need2 ? s_e[1][wv][lane] : (Mask)0;
 
   uint32_t out_v = NO_VALUE;
@@ -308,24 +412,30 @@ __global__ __launch_bounds__(BLOCK) void ops_kernel(OpsArgs a) {
         out_v = value_of(word);
         out_f = 1;
       }
+    } else if (slot && in_bucket) {
+      // replace (Algorithm 1) or delete (Algorithm 4).  The paper publishes
+      // both with one CAS from the word seen; here the word of key k can
+      // change only through this operation (no entry moves in this phase,
+      // claims only fill EMPTY slots, and a batch gives each key one such
+      // operation), so that CAS cannot fail and one 64-bit store does the
+      // same: the whole entry is replaced at once and nothing waits for an
+      // atomic's return.
+      *slot = (op == OP_INSERT) ? kv : EMPTY;
+      if (op == OP_DELETE) {
+        out_f = 1;
+        dl = -1;
+      }
     } else if (slot) {
-      // replace (Algorithm 1) or delete (Algorithm 4): one CAS from the word
-      // seen.  Only operations on this key may change its word, and the
-      // batch contract gives each key one such operation, so the CAS fails
-      // only when that contract is broken; then search again with fresh
-      // loads.
+      // stash or pending entry: the same single-word update, by CAS (rare)
+      const uint64_t desired = (op == OP_INSERT) ? kv : TOMB;
       bool done = false;
       for (int attempt = 0; attempt < 4 && slot; ++attempt) {
-        // a deleted bucket slot becomes EMPTY, a deleted stash/pending entry TOMB
-        const uint64_t desired = (op == OP_INSERT) ? kv : (in_bucket ? EMPTY : TOMB);
         if (cas64(slot, word, desired) == word) {
           done = true;
           break;
         }
         atomicOr(&a.ctl->error, ERR_CAS_RETRY);
-        slot = bucket_find_fresh<S>(a.buckets, c1, c2, k, &word);
-        in_bucket = slot != nullptr;
-        if (!slot) slot = overflow_find(a.stash, n_stash, a.pending, n_pend, k, &word, true);
+        slot = overflow_find(a.stash, n_stash, a.pending, n_pend, k, &word, true);
       }
       if (op == OP_DELETE && done) {
         out_f = 1;
@@ -386,6 +496,14 @@ __global__ __launch_bounds__(BLOCK) void ops_kernel(OpsArgs a) {
   }
 }
 
+template <int S, uint32_t MODE>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(OPS_WAVES_PER_EU))) void ops_kernel(
+    OpsArgs a) {
+  __shared__ OpsShared<S> sh;
+  const OpsView view = read_view(a.ctl, a.stash_cap, a.pending_cap);
+  ops_tile<S, MODE>(a, view, blockIdx.x, sh);
+}
+
 // ---------------------------------------------------------------------------
 // P3: bounded cuckoo eviction (Algorithm 3) and the stash (Section IV-A step 4)
 // ---------------------------------------------------------------------------
@@ -401,60 +519,9 @@ struct EvictArgs {
   uint32_t max_evictions;
 };
 
-// Claim any empty slot of a bucket with one CAS (lowest slot first).
-template <int S>
-__device__ inline bool claim_lane(uint64_t *bkt, uint64_t kv) {
-  for (int s = 0; s < S; ++s) {
-    const uint64_t w = load_fresh(bkt + s);
-    if (w == EMPTY && cas64(bkt + s, EMPTY, kv) == EMPTY) return true;
-  }
-  return false;
-}
+__device__ __forceinline__ void set_hint(uint32_t *hint, uint32_t b) { or32(&hint[b >> 5], 1u << (b & 31)); }
 
-template <int S>
-__device__ inline int count_empty_lane(const uint64_t *bkt) {
-  int n = 0;
-  for (int s = 0; s < S; ++s) n += load_fresh(bkt + s) == EMPTY;
-  return n;
-}
-
-// Step 2 for one item (lane-wise): the candidate with more empty slots
-// first, ties to the first hash, then the other candidate.
-template <int S>
-__device__ inline bool two_choice_claim_lane(uint64_t *buckets, uint32_t c1, uint32_t c2, uint64_t kv) {
-  uint32_t first = c1, second = c2;
-  if (c2 != c1 && count_empty_lane<S>(buckets + (uint64_t)c2 * S) > count_empty_lane<S>(buckets + (uint64_t)c1 * S)) {
-    first = c2;
-    second = c1;
-  }
-  if (claim_lane<S>(buckets + (uint64_t)first * S, kv)) return true;
-  return second != first && claim_lane<S>(buckets + (uint64_t)second * S, kv);
-}
-
-// Put kv into slot s0 (or the next slots) by CAS, displacing the occupant.
-// Returns 1 with *victim set, 2 when the slot turned out empty (claimed), 0
-// when every CAS lost a race.
-template <int S>
-__device__ inline int displace_lane(uint64_t *bkt, uint64_t kv, int s0, uint64_t *victim) {
-  for (int t = 0; t < S; ++t) {
-    const int s = (s0 + t) & (S - 1);
-    uint64_t cur = load_fresh(bkt + s);
-    for (int attempt = 0; attempt < 4; ++attempt) {
-      const uint64_t found = cas64(bkt + s, cur, kv);
-      if (found == cur) {
-        if (cur == EMPTY) return 2;
-        *victim = cur;
-        return 1;
-      }
-      cur = found;
-    }
-  }
-  return 0;
-}
-
-__device__ inline void set_hint(uint32_t *hint, uint32_t b) { or32(&hint[b >> 5], 1u << (b & 31)); }
-
-__device__ inline void overflow_push(const EvictArgs &a, const Geo &geo, uint64_t kv) {
+__device__ __forceinline__ void overflow_push(const EvictArgs &a, const Geo &geo, uint64_t kv) {
   bool stashed = false;
   uint64_t c = load_fresh(&a.ctl->stash_count);
   while (c < a.stash_cap) {
@@ -482,50 +549,120 @@ __device__ inline void overflow_push(const EvictArgs &a, const Geo &geo, uint64_
   set_hint(a.hint, address(geo, bithash2(k)));
 }
 
+// Value of lane `src` of the wave, for a 64-bit word.
+__device__ __forceinline__ uint64_t shfl64(uint64_t x, int src) {
+  const int lo = __builtin_amdgcn_ds_bpermute(src << 2, (int)(uint32_t)x);
+  const int hi = __builtin_amdgcn_ds_bpermute(src << 2, (int)(uint32_t)(x >> 32));
+  return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+// Claim-then-commit by one 16-lane group (WABC): `free_mask` holds the
+// group's view of the bucket's EMPTY slots; the lowest one is claimed with
+// one CAS by its lane, and a failed CAS (the view was stale) drops that slot
+// and tries the next.  Returns true when the entry was committed.
+template <int S>
+__device__ __forceinline__ bool group_claim(uint64_t *bkt, typename Traits<S>::Mask free_mask, uint64_t kv, int g,
+                                            int sl) {
+  using T = Traits<S>;
+  using Mask = typename T::Mask;
+  while (free_mask) {
+    const int s = ctz_mask(free_mask);
+    bool won = false;
+    if (sl == s) won = cas64(bkt + s, EMPTY, kv) == EMPTY;
+    if ((Mask)((ballot(won) >> (g * S)) & T::FULL)) return true;
+    free_mask &= (Mask)(free_mask - 1);
+  }
+  return false;
+}
+
+// P3: items whose two buckets were full in P1 (or stash entries re-placed
+// after a split), one 16-lane group per item.  Step 2 is tried again with a
+// fresh view of both buckets (two-choice), then the bounded cuckoo chain of
+// Algorithm 3: each round claims a free slot of the current bucket or
+// displaces a victim by CAS and carries the victim to its alternate bucket.
+// An item still in hand after max_evictions displacements goes to the stash
+// ring, or to the pending list when the ring is full.
+template <int S>
+__device__ __forceinline__ void evict_item(const EvictArgs &a, const Geo &geo, uint64_t t, int g, int sl,
+                                           uint64_t &n_evict, uint64_t &n_full) {
+  using T = Traits<S>;
+  using Mask = typename T::Mask;
+  uint64_t kv = a.wl[t];
+  const uint32_t c1 = address(geo, bithash1(key_of(kv))), c2 = address(geo, bithash2(key_of(kv)));
+  // step 2 with fresh loads (fresh: other items of this phase change buckets)
+  const uint64_t w1 = load_fresh(a.buckets + (uint64_t)c1 * S + sl);
+  const uint64_t w2 = load_fresh(a.buckets + (uint64_t)c2 * S + sl);
+  const Mask f1 = (Mask)((ballot(w1 == EMPTY) >> (g * S)) & T::FULL);
+  const Mask f2 = (c2 != c1) ? (Mask)((ballot(w2 == EMPTY) >> (g * S)) & T::FULL) : (Mask)0;
+  bool placed;
+  if (popc_mask(f2) > popc_mask(f1))
+    placed = group_claim<S>(a.buckets + (uint64_t)c2 * S, f2, kv, g, sl) ||
+             group_claim<S>(a.buckets + (uint64_t)c1 * S, f1, kv, g, sl);
+  else
+    placed = group_claim<S>(a.buckets + (uint64_t)c1 * S, f1, kv, g, sl) ||
+             group_claim<S>(a.buckets + (uint64_t)c2 * S, f2, kv, g, sl);
+  uint32_t b = c1;  // chains start at the first candidate
+  for (uint32_t kick = 1; kick <= a.max_evictions && !placed; ++kick) {
+    uint64_t *bkt = a.buckets + (uint64_t)b * S;
+    const uint64_t w = load_fresh(bkt + sl);
+    const Mask fm = (Mask)((ballot(w == EMPTY) >> (g * S)) & T::FULL);
+    if (group_claim<S>(bkt, fm, kv, g, sl)) {
+      placed = true;
+      break;
+    }
+    // victim: a pseudo-random slot (the paper's "first occupied" slot is
+    // slot 0 of every full bucket, which lets two chains trade the same
+    // pair of entries back and forth)
+    const int s0 = (int)(mix32(key_of(kv) ^ (kick * 0x9E3779B9u)) & (S - 1));
+    uint64_t found = 0;
+    bool won = false;
+    if (sl == s0) {
+      found = cas64(bkt + s0, w, kv);
+      won = found == w;
+    }
+    const bool ok = (ballot(won) >> (g * S)) & T::FULL;
+    const uint64_t victim = shfl64(w, g * S + s0);
+    if (!ok) continue;  // the slot changed under us: count the round, keep the item
+    if (victim == EMPTY) {
+      placed = true;  // the slot was empty after all: the CAS claimed it
+      break;
+    }
+    ++n_evict;
+    kv = victim;
+    const uint32_t v1 = address(geo, bithash1(key_of(kv)));
+    const uint32_t v2 = address(geo, bithash2(key_of(kv)));
+    b = (b == v1) ? v2 : v1;  // AltBucket: the victim's other candidate
+  }
+  if (!placed && sl == 0) {
+    ++n_full;
+    overflow_push(a, geo, kv);
+  }
+}
+
+__device__ __forceinline__ void evict_counters(const EvictArgs &a, uint64_t n_evict, uint64_t n_full, int sl) {
+  if (n_evict && sl == 0) add64(&a.ctl->evictions, n_evict);
+  if (n_full) add64(&a.ctl->full_chains, n_full);
+}
+
+// P3: items whose two buckets were full in P1 (or stash entries re-placed
+// after a split), one 16-lane group per item.  Step 2 is tried again with a
+// fresh view of both buckets (two-choice), then the bounded cuckoo chain of
+// Algorithm 3: each round claims a free slot of the current bucket or
+// displaces a victim by CAS and carries the victim to its alternate bucket.
+// An item still in hand after max_evictions displacements goes to the stash
+// ring, or to the pending list when the ring is full.
 template <int S>
 __global__ __launch_bounds__(BLOCK) void evict_kernel(EvictArgs a) {
+  using T = Traits<S>;
   const Geo geo = read_geo(a.ctl);
   const uint64_t cnt = a.ctl->wl_count;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int g = lane / S, sl = lane % S;
+  const uint64_t groups = (uint64_t)gridDim.x * WAVES * T::G;
   uint64_t n_evict = 0, n_full = 0;
-  for (uint64_t t = (uint64_t)blockIdx.x * BLOCK + threadIdx.x; t < cnt; t += (uint64_t)gridDim.x * BLOCK) {
-    uint64_t kv = a.wl[t];
-    const uint32_t k1 = address(geo, bithash1(key_of(kv))), k2 = address(geo, bithash2(key_of(kv)));
-    // step 2 once more with fresh loads (items from P1 saw both buckets full,
-    // possibly through a stale cache line; items drained from the stash after
-    // a split have not tried the new geometry), then the chain from the first
-    // candidate
-    bool placed = two_choice_claim_lane<S>(a.buckets, k1, k2, kv);
-    uint32_t b = k1;
-    for (uint32_t kick = 1; kick <= a.max_evictions && !placed; ++kick) {
-      uint64_t *bkt = a.buckets + (uint64_t)b * S;
-      if (claim_lane<S>(bkt, kv)) {
-        placed = true;
-        break;
-      }
-      // victim: a pseudo-random slot (the paper's "first occupied" slot is
-      // always slot 0 of a full bucket, which lets two chains swap the same
-      // pair of entries back and forth)
-      uint64_t victim = 0;
-      const int s0 = (int)(mix32(key_of(kv) ^ (kick * 0x9E3779B9u)) & (S - 1));
-      const int r = displace_lane<S>(bkt, kv, s0, &victim);
-      if (r == 2) {
-        placed = true;
-        break;
-      }
-      if (r == 0) continue;  // every CAS raced: count the round, keep the item
-      ++n_evict;
-      kv = victim;
-      const uint32_t v1 = address(geo, bithash1(key_of(kv)));
-      const uint32_t v2 = address(geo, bithash2(key_of(kv)));
-      b = (b == v1) ? v2 : v1;  // AltBucket: the victim's other candidate
-    }
-    if (!placed) {
-      ++n_full;
-      overflow_push(a, geo, kv);
-    }
-  }
-  if (n_evict) add64(&a.ctl->evictions, n_evict);
-  if (n_full) add64(&a.ctl->full_chains, n_full);
+  for (uint64_t t = ((uint64_t)blockIdx.x * WAVES + wv) * T::G + g; t < cnt; t += groups)
+    evict_item<S>(a, geo, t, g, sl, n_evict, n_full);
+  evict_counters(a, n_evict, n_full, sl);
   __syncthreads();
   if (threadIdx.x == 0) {
     if (blockIdx.x == 0 && cnt) add64(&a.ctl->evict_items, cnt);
@@ -537,7 +674,6 @@ __global__ __launch_bounds__(BLOCK) void evict_kernel(EvictArgs a) {
     }
   }
 }
-
 
 // ---------------------------------------------------------------------------
 // Linear-hashing resize (Section IV-C), decided on the device.
@@ -564,7 +700,7 @@ struct ResizeArgs {
 // Geometry of the next segment.  Splits first finish a round (sp == im+1 is
 // the same addressing as the next round with sp == 0); merges first regress
 // a round when sp == 0 (again the same addressing).
-__device__ inline void plan_next(Ctl *c) {
+__device__ __forceinline__ void plan_next(volatile Ctl *c) {
   c->seg = 0;
   if (c->resize_todo == 0) {
     c->resize_dir = 0;
@@ -601,7 +737,8 @@ __device__ inline void plan_next(Ctl *c) {
 // while (live + extra) * 100 > lf_expand * buckets * S, contraction while
 // live * 100 < lf_contract * buckets * S and the table is above its initial
 // size.
-__device__ inline void plan_policy(Ctl *c, const ResizeArgs &a, uint64_t extra, bool allow_contract) {
+__device__ __forceinline__ void plan_policy(volatile Ctl *c, const ResizeArgs &a, uint64_t extra,
+                                            bool allow_contract) {
   const uint64_t S = a.S, K = a.K, nb = c->n_buckets, live = c->live;
   const uint64_t need = live + extra;
   if (need * 100 > (uint64_t)a.lf_expand_pct * nb * S) {
@@ -623,19 +760,10 @@ __device__ inline void plan_policy(Ctl *c, const ResizeArgs &a, uint64_t extra, 
   }
 }
 
-__global__ __launch_bounds__(BLOCK) void resize_plan_kernel(ResizeArgs a, uint32_t mode, uint64_t amount,
-                                                            const uint8_t *ops) {
-  __shared__ unsigned long long n_ins;
-  if (threadIdx.x == 0) n_ins = 0;
-  __syncthreads();
-  if (mode == PLAN_PRE_MIXED) {
-    unsigned long long mine = 0;
-    for (uint64_t i = threadIdx.x; i < amount; i += BLOCK) mine += ops[i] == OP_INSERT;
-    atomicAdd(&n_ins, mine);
-    __syncthreads();
-  }
-  if (threadIdx.x != 0) return;
-  Ctl *c = a.ctl;
+// Start a resize call (one thread): the pairs the call asks for, then the
+// first segment.  `amount` is the insert count (PRE), or the pair count
+// (SPLIT, MERGE).
+__device__ __forceinline__ void plan_start(volatile Ctl *c, const ResizeArgs &a, uint32_t mode, uint64_t amount) {
   c->resize_dir = 0;
   c->resize_todo = 0;
   c->ticket = 0;
@@ -644,8 +772,8 @@ __global__ __launch_bounds__(BLOCK) void resize_plan_kernel(ResizeArgs a, uint32
     return;
   }
   switch (mode) {
-    case PLAN_PRE: plan_policy(c, a, amount, false); break;
-    case PLAN_PRE_MIXED: plan_policy(c, a, n_ins, false); break;
+    case PLAN_PRE:
+    case PLAN_PRE_MIXED: plan_policy(c, a, amount, false); break;
     case PLAN_POST: plan_policy(c, a, 0, true); break;
     case PLAN_SPLIT:
       c->resize_dir = 1;
@@ -659,9 +787,23 @@ __global__ __launch_bounds__(BLOCK) void resize_plan_kernel(ResizeArgs a, uint32
   plan_next(c);
 }
 
+__global__ __launch_bounds__(BLOCK) void resize_plan_kernel(ResizeArgs a, uint32_t mode, uint64_t amount,
+                                                            const uint8_t *ops) {
+  __shared__ unsigned long long n_ins;
+  if (threadIdx.x == 0) n_ins = 0;
+  __syncthreads();
+  if (mode == PLAN_PRE_MIXED) {
+    unsigned long long mine = 0;
+    for (uint64_t i = threadIdx.x; i < amount; i += BLOCK) mine += ops[i] == OP_INSERT;
+    atomicAdd(&n_ins, mine);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) plan_start(a.ctl, a, mode, mode == PLAN_PRE_MIXED ? n_ins : amount);
+}
+
 // Ticket for "the last block of this launch": every block has finished its
 // reads of the control block and its writes to the table.
-__device__ inline bool last_block(uint64_t *ticket) {
+__device__ __forceinline__ bool last_block(uint64_t *ticket) {
   __shared__ bool last;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -672,12 +814,86 @@ __device__ inline bool last_block(uint64_t *ticket) {
   return last;
 }
 
-__device__ inline uint32_t nth_set_bit(uint64_t m, uint32_t r) {
+__device__ __forceinline__ uint32_t nth_set_bit(uint64_t m, uint32_t r) {
   for (uint32_t i = 0; i < r; ++i) m &= m - 1;
   return (uint32_t)__builtin_ctzll(m);
 }
 
-// Pass 1: split the segment's pairs (Section IV-C-1), or test merge pairs.
+// One split pair (Section IV-C-1): pair j of the segment is (src, src + 2^m)
+// with src = sp + j.  An entry stays when one of its candidate hashes still
+// addresses src under the next round's mask, otherwise it moves; movers are
+// compacted into the partner's first slots (the partner is EMPTY).
+template <int S>
+__device__ __forceinline__ void split_pair(const ResizeArgs &a, uint64_t im, uint64_t sp, uint64_t j, int g, int sl) {
+  using T = Traits<S>;
+  const uint64_t src = sp + j, dst = src + im + 1, next = 2 * im + 1;
+  const uint64_t w = a.buckets[src * S + sl];
+  bool move = false;
+  if (w != EMPTY) {
+    const uint32_t h1 = bithash1(key_of(w)), h2 = bithash2(key_of(w));
+    const bool stay = ((h1 & im) == src && (h1 & next) == src) || ((h2 & im) == src && (h2 & next) == src);
+    move = !stay;
+  }
+  const uint64_t mm = (ballot(move) >> (g * S)) & T::FULL;
+  if (move) {
+    const uint32_t rank = __builtin_popcountll(mm & ((1ull << sl) - 1ull));
+    a.buckets[dst * S + rank] = w;
+    a.buckets[src * S + sl] = EMPTY;
+  }
+}
+
+// Merge pair j of the segment, walked from the top: (lo, lo + 2^m) with
+// lo = sp - 1 - j.  It fits when hi's entries fit lo's EMPTY slots
+// (Section IV-C-2); the first pair that does not fit bounds the commit.
+template <int S>
+__device__ __forceinline__ void merge_test_pair(const ResizeArgs &a, Ctl *c, uint64_t im, uint64_t sp, uint64_t j,
+                                                int g, int sl) {
+  using T = Traits<S>;
+  const uint64_t lo = sp - 1 - j, hi = lo + im + 1;
+  const uint64_t wl = a.buckets[lo * S + sl], wh = a.buckets[hi * S + sl];
+  const uint64_t fl = (ballot(wl == EMPTY) >> (g * S)) & T::FULL;
+  const uint64_t lh = (ballot(wh != EMPTY) >> (g * S)) & T::FULL;
+  if (sl == 0 && __builtin_popcountll(lh) > __builtin_popcountll(fl))
+    __hip_atomic_fetch_min(&c->merge_commit, j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Move a merge pair that fits: the r-th live entry of hi goes to the r-th
+// EMPTY slot of lo; stash entries with a candidate in hi now address lo.
+template <int S>
+__device__ __forceinline__ void merge_move_pair(const ResizeArgs &a, uint64_t im, uint64_t sp, uint64_t j, int g,
+                                                int sl) {
+  using T = Traits<S>;
+  const uint64_t lo = sp - 1 - j, hi = lo + im + 1;
+  const uint64_t wl = a.buckets[lo * S + sl], wh = a.buckets[hi * S + sl];
+  const uint64_t fl = (ballot(wl == EMPTY) >> (g * S)) & T::FULL;
+  const uint64_t lh = (ballot(wh != EMPTY) >> (g * S)) & T::FULL;
+  if (wh != EMPTY) {
+    const uint32_t r = __builtin_popcountll(lh & ((1ull << sl) - 1ull));
+    a.buckets[lo * S + nth_set_bit(fl, r)] = wh;
+    a.buckets[hi * S + sl] = EMPTY;
+  }
+  if (sl == 0 && ((a.hint[hi >> 5] >> (hi & 31)) & 1u)) set_hint(a.hint, (uint32_t)lo);
+}
+
+// Geometry after a finished segment (run by one thread once every pair of
+// the segment is done), then the plan of the next segment.
+__device__ __forceinline__ void split_segment_done(volatile Ctl *c, uint64_t sp, uint64_t seg) {
+  c->sp = sp + seg;
+  c->n_buckets += seg;
+  c->resize_todo -= seg;
+  c->split_happened = 1;
+  plan_next(c);
+}
+
+__device__ __forceinline__ void merge_segment_done(volatile Ctl *c, uint64_t sp, uint64_t seg, uint64_t commit) {
+  c->sp = sp - commit;
+  c->n_buckets -= commit;
+  c->resize_todo -= commit;
+  if (commit < seg) c->resize_todo = 0;  // a pair did not fit: the call stops here
+  plan_next(c);
+}
+
+// Pass 1: split the segment's pairs, or test merge pairs.
 template <int S>
 __global__ __launch_bounds__(BLOCK) void resize_pass1_kernel(ResizeArgs a) {
   using T = Traits<S>;
@@ -690,42 +906,14 @@ __global__ __launch_bounds__(BLOCK) void resize_pass1_kernel(ResizeArgs a) {
   const int g = lane / S, sl = lane % S;
   const uint64_t groups = (uint64_t)gridDim.x * WAVES * T::G;
   for (uint64_t j = ((uint64_t)blockIdx.x * WAVES + wv) * T::G + g; j < seg; j += groups) {
-    if (dir > 0) {
-      // pair (src, src + 2^m): an entry stays when one of its candidate
-      // hashes still addresses src under the next round's mask, otherwise
-      // it moves; movers are compacted into the partner's first slots
-      const uint64_t src = sp + j, dst = src + im + 1, next = 2 * im + 1;
-      const uint64_t w = a.buckets[src * S + sl];
-      bool move = false;
-      if (w != EMPTY) {
-        const uint32_t h1 = bithash1(key_of(w)), h2 = bithash2(key_of(w));
-        const bool stay = ((h1 & im) == src && (h1 & next) == src) || ((h2 & im) == src && (h2 & next) == src);
-        move = !stay;
-      }
-      const uint64_t mm = (ballot(move) >> (g * S)) & T::FULL;
-      if (move) {
-        const uint32_t rank = __builtin_popcountll(mm & ((1ull << sl) - 1ull));
-        a.buckets[dst * S + rank] = w;
-        a.buckets[src * S + sl] = EMPTY;
-      }
-    } else {
-      // merge pair (lo, lo + 2^m), walked from the top: it fits when hi's
-      // entries fit lo's empty slots (Section IV-C-2)
-      const uint64_t lo = sp - 1 - j, hi = lo + im + 1;
-      const uint64_t wl = a.buckets[lo * S + sl], wh = a.buckets[hi * S + sl];
-      const uint64_t fl = (ballot(wl == EMPTY) >> (g * S)) & T::FULL;
-      const uint64_t lh = (ballot(wh != EMPTY) >> (g * S)) & T::FULL;
-      if (sl == 0 && __builtin_popcountll(lh) > __builtin_popcountll(fl))
-        __hip_atomic_fetch_min(&c->merge_commit, j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    if (dir > 0)
+      split_pair<S>(a, im, sp, j, g, sl);
+    else
+      merge_test_pair<S>(a, c, im, sp, j, g, sl);
   }
   if (dir > 0 && last_block(&c->ticket)) {
     c->ticket = 0;
-    c->sp = sp + seg;
-    c->n_buckets += seg;
-    c->resize_todo -= seg;
-    c->split_happened = 1;
-    plan_next(c);
+    split_segment_done(c, sp, seg);
   }
 }
 
@@ -741,33 +929,43 @@ __global__ __launch_bounds__(BLOCK) void resize_pass2_kernel(ResizeArgs a) {
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = lane / S, sl = lane % S;
   const uint64_t groups = (uint64_t)gridDim.x * WAVES * T::G;
-  for (uint64_t j = ((uint64_t)blockIdx.x * WAVES + wv) * T::G + g; j < commit; j += groups) {
-    const uint64_t lo = sp - 1 - j, hi = lo + im + 1;
-    const uint64_t wl = a.buckets[lo * S + sl], wh = a.buckets[hi * S + sl];
-    const uint64_t fl = (ballot(wl == EMPTY) >> (g * S)) & T::FULL;
-    const uint64_t lh = (ballot(wh != EMPTY) >> (g * S)) & T::FULL;
-    if (wh != EMPTY) {
-      // the r-th live entry of hi goes to the r-th empty slot of lo
-      const uint32_t r = __builtin_popcountll(lh & ((1ull << sl) - 1ull));
-      a.buckets[lo * S + nth_set_bit(fl, r)] = wh;
-      a.buckets[hi * S + sl] = EMPTY;
-    }
-    // stash entries with a candidate in hi now address lo
-    if (sl == 0 && ((a.hint[hi >> 5] >> (hi & 31)) & 1u)) set_hint(a.hint, (uint32_t)lo);
-  }
+  for (uint64_t j = ((uint64_t)blockIdx.x * WAVES + wv) * T::G + g; j < commit; j += groups)
+    merge_move_pair<S>(a, im, sp, j, g, sl);
   if (last_block(&c->ticket)) {
     c->ticket = 0;
-    c->sp = sp - commit;
-    c->n_buckets -= commit;
-    c->resize_todo -= commit;
-    if (commit < seg) c->resize_todo = 0;  // a pair did not fit: the call stops here
-    plan_next(c);
+    merge_segment_done(c, sp, seg, commit);
   }
 }
 
-// After splits: move every stash and pending entry to the eviction worklist
-// (they are re-placed by the eviction phase under the new geometry) and
-// clear the hint bits (Section III-B "Overflow Stash").
+// After splits: every stash and pending entry moves to the eviction worklist
+// (the eviction phase re-places it under the new geometry) and the hint bits
+// are cleared (Section III-B "Overflow Stash").  One wave-aggregated append
+// per wave and item range; `t` indexes stash entries then pending entries.
+__device__ __forceinline__ void drain_collect(uint64_t t, uint64_t n_stash, uint64_t total, const uint64_t *stash,
+                                              const uint64_t *pending, uint64_t *wl, Ctl *c) {
+  uint64_t w = TOMB;
+  if (t < n_stash)
+    w = stash[t];
+  else if (t < total)
+    w = pending[t - n_stash];
+  const bool live = w != TOMB;
+  const uint64_t m = ballot(live);
+  if (m) {
+    const int lane = threadIdx.x & 63;
+    const int leader = __builtin_ctzll(m);
+    uint64_t base = 0;
+    if (lane == leader) base = add64(&c->wl_count, (uint64_t)__popcll(m));
+    base = read_lane64(base, leader);
+    if (live) wl[base + rank_below(m)] = w;
+  }
+}
+
+__device__ __forceinline__ void drain_done(volatile Ctl *c) {
+  c->stash_count = 0;
+  c->pending_count = 0;
+  c->split_happened = 0;
+}
+
 __global__ __launch_bounds__(BLOCK) void drain_kernel(uint64_t *stash, uint64_t stash_cap, uint64_t *pending,
                                                       uint64_t pending_cap, uint32_t *hint, uint64_t hint_n,
                                                       uint64_t *wl, Ctl *c) {
@@ -781,28 +979,10 @@ __global__ __launch_bounds__(BLOCK) void drain_kernel(uint64_t *stash, uint64_t 
     for (uint64_t t = tid; t < hint_n; t += stride) hint[t] = 0u;
   }
   const uint64_t span = (total + stride - 1) / stride * stride;
-  const int lane = threadIdx.x & 63;
-  for (uint64_t t = tid; t < span; t += stride) {
-    uint64_t w = TOMB;
-    if (t < n_stash)
-      w = stash[t];
-    else if (t < total)
-      w = pending[t - n_stash];
-    const bool live = w != TOMB;
-    const uint64_t m = ballot(live);
-    if (m) {
-      const int leader = __builtin_ctzll(m);
-      uint64_t base = 0;
-      if (lane == leader) base = add64(&c->wl_count, (uint64_t)__popcll(m));
-      base = read_lane64(base, leader);
-      if (live) wl[base + rank_below(m)] = w;
-    }
-  }
+  for (uint64_t t = tid; t < span; t += stride) drain_collect(t, n_stash, total, stash, pending, wl, c);
   if (last_block(&c->drain_ticket)) {
     c->drain_ticket = 0;
-    c->stash_count = 0;
-    c->pending_count = 0;
-    c->split_happened = 0;
+    drain_done(c);
   }
 }
 
@@ -876,6 +1056,440 @@ __global__ void ctl_zero_placement_kernel(Ctl *ctl) {
 __global__ void ctl_reset_kernel(Ctl *ctl, Ctl init) { *ctl = init; }
 __global__ void ctl_zero_dump_kernel(Ctl *ctl) { ctl->dump_count = 0; }
 
+
+// ---------------------------------------------------------------------------
+// Persistent executor: one resident grid drains a queue of batches.
+//
+// The host appends batch descriptors to a ring in pinned host memory and
+// advances a host-side tail.  Blocks of the resident grid ingest new
+// descriptors into a device ring, and each batch then runs as a sequence of
+// data-parallel phases (dedupe fill, dedupe, insert count, resize segments,
+// stash drain, re-placement, probe tiles, eviction) split into chunks that
+// any block may claim.  One 64-bit word per batch packs the phase, its chunk
+// count and the number of chunks claimed, so a claim is one atomic add; the
+// block that completes the last chunk of a phase runs the phase's scalar
+// epilogue (geometry updates, plans) and publishes the next phase.  Batches
+// on one table run in submission order (a per-table sequence number);
+// batches on different tables overlap.  Completion is written to host-mapped
+// memory.  Every block leaves the loop once the host has set the stop flag
+// and every ingested batch is complete.
+// ---------------------------------------------------------------------------
+enum : uint32_t {
+  PH_START = 0, PH_FILL = 1, PH_DEDUPE = 2, PH_COUNT = 3, PH_SEG_A = 4, PH_SEG_B = 5, PH_DRAIN = 6,
+  PH_REPLACE = 7, PH_OPS = 8, PH_EVICT = 9, PH_DONE = 10
+};
+constexpr uint64_t FILL_PER_CHUNK = BLOCK * 16;   // words per fill chunk
+constexpr uint64_t COUNT_PER_CHUNK = BLOCK * 16;  // operations per count chunk
+constexpr uint64_t EVICT_PER_GROUP = 4;           // eviction items per group per chunk
+constexpr uint64_t M28 = (1ull << 28) - 1;
+constexpr uint32_t DRAIN_WINDOW = 64;             // batches scanned for work
+
+struct TableDesc {
+  uint64_t *buckets;
+  uint32_t *hint;
+  uint64_t *stash;
+  uint64_t *pending;
+  Ctl *ctl;
+  uint64_t *wl;
+  uint64_t *dd;
+  uint64_t stash_cap, pending_cap, hint_words;
+  uint32_t S, max_evictions, K, lf_expand_pct, lf_contract_pct, pre_expand, post_policy, addressing;
+};
+
+struct ReqDesc {  // written by the host
+  TableDesc t;
+  const uint8_t *ops;
+  const uint32_t *keys;
+  const uint32_t *vals;
+  uint32_t *vals_out;
+  uint8_t *flags_out;
+  uint64_t n;
+  uint32_t mode, flags;
+  uint64_t seq, table_slot, ticket, dd_size;
+};
+static_assert(sizeof(ReqDesc) % 8 == 0, "descriptor copied as 64-bit words");
+
+struct ReqState {
+  ReqDesc d;
+  uint64_t state;  // phase:8 | chunks:28 | claimed:28
+  uint64_t done;   // chunks of the current phase completed
+  uint64_t aux;    // inserts counted for the pre-batch plan
+  uint64_t seg_sp, seg_n, seg_im;
+  int64_t seg_dir;
+  uint64_t items;  // eviction items of the current eviction phase
+  uint32_t resume; // phase that follows the current resize call
+  uint32_t pad_;
+};
+
+struct DrainQueue {
+  ReqState *req;              // device ring
+  const ReqDesc *host_ring;   // pinned host ring
+  const uint64_t *host_tail;  // pinned: descriptors written by the host
+  const uint32_t *host_stop;  // pinned: set when no more work will come
+  uint64_t *host_done;        // pinned: per ring slot, ticket + 1 once complete
+  uint64_t *table_next;       // per table slot: sequence number allowed to run
+  uint64_t cap;
+  uint64_t idle_limit;        // idle polls before a block gives up (watchdog)
+  uint64_t ingested;
+  uint64_t head;
+  uint64_t completed;
+  uint32_t ingest_lock;
+  uint32_t error;             // 1: a block hit the idle watchdog
+};
+
+__device__ __forceinline__ uint64_t make_state(uint32_t ph, uint64_t nch) {
+  return ((uint64_t)ph << 56) | ((nch & M28) << 28);
+}
+
+__device__ __forceinline__ uint64_t ld_sys(const uint64_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+__device__ __forceinline__ ResizeArgs resize_args(const ReqDesc &d) {
+  return ResizeArgs{d.t.buckets, d.t.hint, d.t.ctl, d.t.S, d.t.K, d.t.lf_expand_pct, d.t.lf_contract_pct};
+}
+
+__device__ __forceinline__ EvictArgs evict_args(const ReqDesc &d) {
+  return EvictArgs{d.t.buckets, d.t.hint, d.t.stash, d.t.pending, d.t.ctl, d.t.wl, d.t.stash_cap, d.t.pending_cap,
+                   d.t.max_evictions};
+}
+
+__device__ __forceinline__ bool has_inserts(const ReqDesc &d) { return d.mode == OP_INSERT || d.mode == OP_MIXED; }
+
+__device__ __forceinline__ uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+
+// After a resize step: the next segment, the stash drain after splits, or
+// the phase the resize call returns to.
+__device__ __forceinline__ uint32_t seg_entry(volatile ReqState *r, const ReqDesc &d) {
+  volatile Ctl *c = d.t.ctl;
+  if (c->seg > 0) {
+    r->seg_sp = c->sp;
+    r->seg_n = c->seg;
+    r->seg_im = c->im;
+    r->seg_dir = c->resize_dir;
+    return PH_SEG_A;
+  }
+  if (c->split_happened) return PH_DRAIN;
+  return r->resume;
+}
+
+// Successor of a finished phase; scalar work between phases happens here.
+__device__ __forceinline__ uint32_t successor(volatile ReqState *r, const ReqDesc &d, uint32_t ph) {
+  volatile Ctl *c = d.t.ctl;
+  const bool linear = d.t.addressing == ADDR_LINEAR;
+  switch (ph) {
+    case PH_START: return PH_FILL;
+    case PH_FILL: return PH_DEDUPE;
+    case PH_DEDUPE: return PH_COUNT;
+    case PH_COUNT:
+      if (linear && d.t.pre_expand && has_inserts(d)) {
+        plan_start(c, resize_args(d), PLAN_PRE, d.mode == OP_MIXED ? r->aux : d.n);
+        r->resume = PH_OPS;
+        return seg_entry(r, d);
+      }
+      return PH_OPS;
+    case PH_SEG_A: return r->seg_dir < 0 ? PH_SEG_B : seg_entry(r, d);
+    case PH_SEG_B: return seg_entry(r, d);
+    case PH_DRAIN: return PH_REPLACE;
+    case PH_REPLACE: return r->resume;
+    case PH_OPS: return PH_EVICT;
+    case PH_EVICT:
+      if (linear && d.t.post_policy && d.mode != OP_LOOKUP) {
+        plan_start(c, resize_args(d), PLAN_POST, 0);
+        r->resume = PH_DONE;
+        return seg_entry(r, d);
+      }
+      return PH_DONE;
+    default: return PH_DONE;
+  }
+}
+
+// Chunks of a phase about to start (0: nothing to do).
+__device__ __forceinline__ uint64_t enter(volatile ReqState *r, const ReqDesc &d, uint32_t ph) {
+  volatile Ctl *c = d.t.ctl;
+  const uint64_t gpb = (uint64_t)WAVES * (64 / d.t.S);  // groups per block
+  switch (ph) {
+    case PH_FILL: return d.dd_size ? ceil_div(d.dd_size, FILL_PER_CHUNK) : 0;
+    case PH_DEDUPE: return d.dd_size ? ceil_div(d.n, BLOCK) : 0;
+    case PH_COUNT:
+      r->aux = 0;
+      return (d.t.addressing == ADDR_LINEAR && d.t.pre_expand && d.mode == OP_MIXED) ? ceil_div(d.n, COUNT_PER_CHUNK)
+                                                                                     : 0;
+    case PH_SEG_A: return ceil_div(r->seg_n, gpb);
+    case PH_SEG_B: return ceil_div(c->merge_commit, gpb);
+    case PH_DRAIN: {
+      const uint64_t total = min(c->stash_count, d.t.stash_cap) + min(c->pending_count, d.t.pending_cap);
+      return total ? max(ceil_div(total, BLOCK), ceil_div(d.t.hint_words, FILL_PER_CHUNK)) : 0;
+    }
+    case PH_REPLACE:
+    case PH_EVICT:
+      r->items = c->wl_count;
+      return ceil_div(r->items, gpb * EVICT_PER_GROUP);
+    case PH_OPS: return ceil_div(d.n, BLOCK);
+    default: return 0;
+  }
+}
+
+// Scalar work at the end of a phase (also for phases with no chunks).
+__device__ __forceinline__ void epilogue(volatile ReqState *r, const ReqDesc &d, uint32_t ph) {
+  volatile Ctl *c = d.t.ctl;
+  switch (ph) {
+    case PH_SEG_A:
+      if (r->seg_dir > 0) split_segment_done(c, r->seg_sp, r->seg_n);
+      break;
+    case PH_SEG_B: merge_segment_done(c, r->seg_sp, r->seg_n, c->merge_commit); break;
+    case PH_DRAIN: drain_done(c); break;
+    case PH_REPLACE:
+    case PH_EVICT:
+      if (r->items) {
+        c->evict_items = c->evict_items + r->items;
+        c->wl_count = 0;
+      }
+      break;
+    default: break;
+  }
+}
+
+// Finish phase `ph` of r and publish the next one (one thread).
+__device__ void advance(DrainQueue *q, ReqState *rs, const ReqDesc &d, uint32_t ph) {
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  volatile ReqState *r = rs;
+  uint64_t nch = 0;
+  epilogue(r, d, ph);
+  for (;;) {
+    ph = successor(r, d, ph);
+    if (ph == PH_DONE) break;
+    nch = enter(r, d, ph);
+    if (nch > 0) break;
+    epilogue(r, d, ph);
+  }
+  r->done = 0;
+  if (ph == PH_DONE) {
+    const uint64_t ticket = d.ticket;
+    __threadfence_system();  // the batch's outputs before its completion flag
+    __hip_atomic_store(&q->table_next[d.table_slot], d.seq + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&rs->state, make_state(PH_DONE, 0), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&q->host_done[ticket % q->cap], ticket + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    add64(&q->completed, 1);
+    return;
+  }
+  __threadfence();
+  __hip_atomic_store(&rs->state, make_state(ph, nch), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Copy new host descriptors into the device ring (one block at a time).
+__device__ void ingest(DrainQueue *q) {
+  if (__hip_atomic_load(&q->ingest_lock, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
+  uint32_t expect = 0;
+  if (!__hip_atomic_compare_exchange_strong(&q->ingest_lock, &expect, 1u, __ATOMIC_ACQUIRE, __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT))
+    return;
+  const uint64_t tail = ld_sys(q->host_tail);
+  uint64_t i = ld_ctl(&q->ingested);
+  const uint64_t stop = min(tail, i + 16);
+  for (; i < stop; ++i) {
+    const uint64_t *src = (const uint64_t *)(q->host_ring + i % q->cap);
+    ReqState *r = q->req + i % q->cap;
+    uint64_t *dst = (uint64_t *)&r->d;
+    for (uint32_t w = 0; w < sizeof(ReqDesc) / 8; ++w) dst[w] = ld_sys(src + w);
+    volatile ReqState *vr = r;
+    vr->done = 0;
+    vr->aux = 0;
+    vr->items = 0;
+    vr->resume = PH_DONE;
+    __threadfence();
+    // one START chunk: the batch's first real phase is chosen when it runs,
+    // i.e. after every earlier batch on its table has finished
+    __hip_atomic_store(&r->state, make_state(PH_START, 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __hip_atomic_store(&q->ingested, i, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(&q->ingest_lock, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Claim a chunk of runnable work.  Returns 0 (work), 1 (none now), 2 (exit).
+__device__ uint32_t find_work(DrainQueue *q, uint64_t *req, uint32_t *phase, uint64_t *chunk, uint64_t *nch) {
+  ingest(q);
+  const uint64_t ing = ld_ctl(&q->ingested);
+  uint64_t head = ld_ctl(&q->head);
+  // retire completed batches at the head of the ring
+  while (head < ing &&
+         (__hip_atomic_load(&q->req[head % q->cap].state, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >> 56) ==
+             PH_DONE) {
+    uint64_t h = head;
+    __hip_atomic_compare_exchange_strong(&q->head, &h, head + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+    head = ld_ctl(&q->head);
+  }
+  if (head == ing) {
+    const bool stop = __hip_atomic_load(q->host_stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0;
+    if (stop && ld_sys(q->host_tail) == ing) return 2;
+    return 1;
+  }
+  const uint64_t end = min(ing, head + DRAIN_WINDOW);
+  for (uint64_t t = head; t < end; ++t) {
+    ReqState *r = q->req + t % q->cap;
+    const uint64_t st = __hip_atomic_load(&r->state, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t ph = (uint32_t)(st >> 56);
+    if (ph == PH_DONE || (st & M28) >= ((st >> 28) & M28)) continue;
+    const uint64_t slot = ld_ctl(&r->d.table_slot), seq = ld_ctl(&r->d.seq);
+    if (ld_ctl(&q->table_next[slot]) != seq) continue;
+    const uint64_t old = add64(&r->state, 1);
+    const uint64_t n = (old >> 28) & M28, c = old & M28;
+    if ((uint32_t)(old >> 56) == PH_DONE || c >= n) continue;
+    *req = t;
+    *phase = (uint32_t)(old >> 56);
+    *chunk = c;
+    *nch = n;
+    return 0;
+  }
+  return 1;
+}
+
+// Descriptor of the batch a block works on, read coherently into LDS.
+__device__ __forceinline__ void load_desc(ReqDesc *dst, const ReqDesc *src) {
+  const uint64_t *s = (const uint64_t *)src;
+  uint64_t *d = (uint64_t *)dst;
+  for (uint32_t w = threadIdx.x; w < sizeof(ReqDesc) / 8; w += BLOCK) d[w] = ld_ctl(s + w);
+}
+
+template <int S>
+__device__ void run_chunk(ReqState *r, const ReqDesc &d, uint32_t ph, uint64_t c, OpsShared<S> &sh) {
+  using T = Traits<S>;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int g = lane / S, sl = lane % S;
+  const uint64_t gib = (uint64_t)wv * T::G + g;  // group in block
+  const uint64_t gpb = (uint64_t)WAVES * T::G;
+  switch (ph) {
+    case PH_FILL: {
+      const uint64_t b = c * FILL_PER_CHUNK, e = min(b + FILL_PER_CHUNK, d.dd_size);
+      for (uint64_t t = b + threadIdx.x; t < e; t += BLOCK) d.t.dd[t] = EMPTY;
+      break;
+    }
+    case PH_DEDUPE: {
+      const uint64_t i = c * BLOCK + threadIdx.x;
+      if (i < d.n) dedupe_insert(d.t.dd, d.dd_size - 1, d.mode, d.ops, d.keys, i);
+      break;
+    }
+    case PH_COUNT: {
+      __shared__ unsigned long long cnt;
+      if (threadIdx.x == 0) cnt = 0;
+      __syncthreads();
+      unsigned long long mine = 0;
+      const uint64_t b = c * COUNT_PER_CHUNK, e = min(b + COUNT_PER_CHUNK, d.n);
+      for (uint64_t t = b + threadIdx.x; t < e; t += BLOCK) mine += d.ops[t] == OP_INSERT;
+      atomicAdd(&cnt, mine);
+      __syncthreads();
+      if (threadIdx.x == 0 && cnt) add64(&r->aux, cnt);
+      break;
+    }
+    case PH_SEG_A: {
+      const ResizeArgs ra = resize_args(d);
+      const uint64_t j = c * gpb + gib, n = ld_ctl(&r->seg_n);
+      const uint64_t im = ld_ctl(&r->seg_im), sp = ld_ctl(&r->seg_sp);
+      if (j < n) {
+        if ((int64_t)ld_ctl((const uint64_t *)&r->seg_dir) > 0)
+          split_pair<S>(ra, im, sp, j, g, sl);
+        else
+          merge_test_pair<S>(ra, d.t.ctl, im, sp, j, g, sl);
+      }
+      break;
+    }
+    case PH_SEG_B: {
+      const ResizeArgs ra = resize_args(d);
+      const uint64_t j = c * gpb + gib, commit = ld_ctl(&d.t.ctl->merge_commit);
+      if (j < commit) merge_move_pair<S>(ra, ld_ctl(&r->seg_im), ld_ctl(&r->seg_sp), j, g, sl);
+      break;
+    }
+    case PH_DRAIN: {
+      const Ctl *cc = d.t.ctl;
+      const uint64_t n_stash = min(ld_ctl(&cc->stash_count), d.t.stash_cap);
+      const uint64_t total = n_stash + min(ld_ctl(&cc->pending_count), d.t.pending_cap);
+      const uint64_t hb = c * FILL_PER_CHUNK, he = min(hb + FILL_PER_CHUNK, d.t.hint_words);
+      for (uint64_t t = hb + threadIdx.x; t < he; t += BLOCK) d.t.hint[t] = 0u;
+      drain_collect(c * BLOCK + threadIdx.x, n_stash, total, d.t.stash, d.t.pending, d.t.wl, d.t.ctl);
+      break;
+    }
+    case PH_REPLACE:
+    case PH_EVICT: {
+      const EvictArgs ea = evict_args(d);
+      const Geo geo = read_geo(d.t.ctl);
+      const uint64_t items = ld_ctl(&r->items);
+      uint64_t n_evict = 0, n_full = 0;
+      for (uint64_t k = 0; k < EVICT_PER_GROUP; ++k) {
+        const uint64_t t = (c * EVICT_PER_GROUP + k) * gpb + gib;
+        if (t < items) evict_item<S>(ea, geo, t, g, sl, n_evict, n_full);
+      }
+      evict_counters(ea, n_evict, n_full, sl);
+      break;
+    }
+    case PH_OPS: {
+      OpsArgs a{};
+      a.buckets = d.t.buckets;
+      a.hint = d.t.hint;
+      a.stash = d.t.stash;
+      a.pending = d.t.pending;
+      a.ctl = d.t.ctl;
+      a.wl = d.t.wl;
+      a.dd = d.dd_size ? d.t.dd : nullptr;
+      a.dd_mask = d.dd_size ? d.dd_size - 1 : 0;
+      a.ops = d.ops;
+      a.keys = d.keys;
+      a.vals = d.vals;
+      a.vals_out = d.vals_out;
+      a.flags_out = d.flags_out;
+      a.n = d.n;
+      a.stash_cap = d.t.stash_cap;
+      a.pending_cap = d.t.pending_cap;
+      const OpsView view = read_view(d.t.ctl, d.t.stash_cap, d.t.pending_cap);
+      switch (d.mode) {
+        case OP_INSERT: ops_tile<S, OP_INSERT>(a, view, c, sh); break;
+        case OP_DELETE: ops_tile<S, OP_DELETE>(a, view, c, sh); break;
+        case OP_LOOKUP: ops_tile<S, OP_LOOKUP>(a, view, c, sh); break;
+        default: ops_tile<S, OP_MIXED>(a, view, c, sh); break;
+      }
+      break;
+    }
+    default: break;  // PH_START: no data-parallel work
+  }
+}
+
+template <int S>
+__global__ __launch_bounds__(BLOCK) void drain_worker_kernel(DrainQueue *q) {
+  __shared__ OpsShared<S> sh;
+  __shared__ ReqDesc desc;
+  __shared__ uint64_t s_req, s_chunk, s_nch;
+  __shared__ uint32_t s_phase, s_cmd;
+  uint64_t idle = 0;
+  const uint64_t idle_limit = ld_ctl(&q->idle_limit);
+  for (;;) {
+    if (threadIdx.x == 0) s_cmd = find_work(q, &s_req, &s_phase, &s_chunk, &s_nch);
+    __syncthreads();
+    const uint32_t cmd = s_cmd;
+    if (cmd == 2) break;
+    if (cmd == 1) {
+      if (++idle > idle_limit) {
+        if (threadIdx.x == 0) atomicOr(&q->error, 1u);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(4);
+      __syncthreads();
+      continue;
+    }
+    idle = 0;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    ReqState *r = q->req + s_req % q->cap;
+    load_desc(&desc, &r->d);
+    __syncthreads();
+    run_chunk<S>(r, desc, s_phase, s_chunk, sh);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __threadfence();  // this chunk's writes before its completion count
+      if (add64(&r->done, 1) + 1 == s_nch) advance(q, r, desc, s_phase);
+    }
+    __syncthreads();
+  }
+}
+
 }  // namespace hive
 
 // ===========================================================================
@@ -900,6 +1514,30 @@ struct hive_table {
   uint64_t dd_cap = 0;  // power of two
   uint64_t bytes = 0;
   hipStream_t last = nullptr;
+};
+
+struct hive_drain {
+  uint32_t S = 16;
+  uint64_t cap = 0;
+  uint32_t max_tables = 0;
+  unsigned grid = 0;
+  DrainQueue *d_q = nullptr;
+  ReqState *d_req = nullptr;
+  uint64_t *d_table_next = nullptr;
+  ReqDesc *h_ring = nullptr;
+  uint64_t *h_tail = nullptr;
+  uint32_t *h_stop = nullptr;
+  uint64_t *h_done = nullptr;
+  uint64_t submitted = 0;
+  // per registered table: its slot in table_next and its next sequence number
+  hive_table *tables[4096];
+  uint64_t next_seq[4096];
+  uint32_t n_tables = 0;
+  hipStream_t capture = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t running_on = nullptr;
+  bool running = false;
 };
 
 #define HIP_OK(expr)                                                                        \
@@ -1077,6 +1715,50 @@ static hive_status resize_sequence(hive_table *h, uint32_t mode, uint64_t amount
                      h->pending_cap, h->d_hint, hint_words(h->max_buckets), h->d_wl, h->d_ctl);
   launch_evict(h, st);
   return launch_check();
+}
+
+
+// ---------------------------------------------------------------------------
+// Persistent executor (host side)
+// ---------------------------------------------------------------------------
+static void free_drain(hive_drain *d) {
+  if (!d) return;
+  if (d->exec) (void)hipGraphExecDestroy(d->exec);
+  if (d->graph) (void)hipGraphDestroy(d->graph);
+  if (d->capture) (void)hipStreamDestroy(d->capture);
+  (void)hipFree(d->d_q);
+  (void)hipFree(d->d_req);
+  (void)hipFree(d->d_table_next);
+  (void)hipHostFree(d->h_ring);
+  (void)hipHostFree(d->h_tail);
+  (void)hipHostFree(d->h_stop);
+  (void)hipHostFree(d->h_done);
+  delete d;
+}
+
+template <int S>
+static hive_status drain_grid(uint32_t blocks_per_cu, unsigned *grid) {
+  int dev = 0, cus = 0, per_cu = 0;
+  HIP_OK(hipGetDevice(&dev));
+  HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, drain_worker_kernel<S>, BLOCK, 0));
+  if (per_cu < 1) return HIVE_ERR_HIP;
+  const unsigned want = blocks_per_cu ? blocks_per_cu : (unsigned)per_cu;
+  *grid = (unsigned)cus * std::min<unsigned>(want, (unsigned)per_cu);
+  return HIVE_OK;
+}
+
+template <int S>
+static void launch_drain_kernel(hive_drain *d, hipStream_t st) {
+  hipLaunchKernelGGL(drain_worker_kernel<S>, dim3(d->grid), dim3(BLOCK), 0, st, d->d_q);
+}
+
+static void launch_drain_any(hive_drain *d, hipStream_t st) {
+  switch (d->S) {
+    case 16: launch_drain_kernel<16>(d, st); break;
+    case 32: launch_drain_kernel<32>(d, st); break;
+    default: launch_drain_kernel<64>(d, st); break;
+  }
 }
 
 static hive_status run_batch(hive_t h, uint32_t mode, const uint8_t *d_ops, const uint32_t *d_keys,
@@ -1345,6 +2027,190 @@ hive_status hive_bucket_of(hive_t h, uint32_t mixed_hash, uint64_t *bucket) {
   HIP_OK(hipStreamSynchronize(h->last));
   Geo g{c.n_buckets, c.magic, (uint32_t)c.im, (uint32_t)c.sp, c.mode};
   *bucket = address(g, mixed_hash);
+  return HIVE_OK;
+}
+
+
+hive_status hive_drain_create(uint32_t slots_per_bucket, uint32_t blocks_per_cu, uint64_t ring_capacity,
+                              uint32_t max_tables, uint64_t idle_limit, hive_drain_t *out) {
+  if (!out) return HIVE_ERR_ARG;
+  *out = nullptr;
+  if (slots_per_bucket != 16 && slots_per_bucket != 32 && slots_per_bucket != 64) return HIVE_ERR_ARG;
+  if (ring_capacity < 1 || ring_capacity > (1ull << 24)) return HIVE_ERR_ARG;
+  if (max_tables < 1 || max_tables > 4096) return HIVE_ERR_ARG;
+  hive_drain *d = new (std::nothrow) hive_drain();
+  if (!d) return HIVE_ERR_OOM;
+  d->S = slots_per_bucket;
+  d->cap = ring_capacity;
+  d->max_tables = max_tables;
+  hive_status s = HIVE_OK;
+  switch (d->S) {
+    case 16: s = drain_grid<16>(blocks_per_cu, &d->grid); break;
+    case 32: s = drain_grid<32>(blocks_per_cu, &d->grid); break;
+    default: s = drain_grid<64>(blocks_per_cu, &d->grid); break;
+  }
+  if (s != HIVE_OK) {
+    free_drain(d);
+    return s;
+  }
+  uint64_t bytes = 0;
+  if (alloc((void **)&d->d_q, sizeof(DrainQueue), &bytes) != HIVE_OK ||
+      alloc((void **)&d->d_req, sizeof(ReqState) * ring_capacity, &bytes) != HIVE_OK ||
+      alloc((void **)&d->d_table_next, 8ull * max_tables, &bytes) != HIVE_OK) {
+    free_drain(d);
+    return HIVE_ERR_OOM;
+  }
+  const unsigned hflags = hipHostMallocMapped | hipHostMallocCoherent;
+  if (hipHostMalloc((void **)&d->h_ring, sizeof(ReqDesc) * ring_capacity, hflags) != hipSuccess ||
+      hipHostMalloc((void **)&d->h_tail, 64, hflags) != hipSuccess ||
+      hipHostMalloc((void **)&d->h_stop, 64, hflags) != hipSuccess ||
+      hipHostMalloc((void **)&d->h_done, 8 * ring_capacity, hflags) != hipSuccess) {
+    (void)hipGetLastError();
+    free_drain(d);
+    return HIVE_ERR_OOM;
+  }
+  memset(d->h_ring, 0, sizeof(ReqDesc) * ring_capacity);
+  memset(d->h_done, 0, 8 * ring_capacity);
+  *d->h_tail = 0;
+  *d->h_stop = 1;
+  DrainQueue q;
+  memset(&q, 0, sizeof(q));
+  q.req = d->d_req;
+  q.cap = ring_capacity;
+  q.table_next = d->d_table_next;
+  q.idle_limit = idle_limit ? idle_limit : (1ull << 25);
+  void *dp = nullptr;
+  if (hipHostGetDevicePointer(&dp, d->h_ring, 0) != hipSuccess) goto fail;
+  q.host_ring = (const ReqDesc *)dp;
+  if (hipHostGetDevicePointer(&dp, d->h_tail, 0) != hipSuccess) goto fail;
+  q.host_tail = (const uint64_t *)dp;
+  if (hipHostGetDevicePointer(&dp, d->h_stop, 0) != hipSuccess) goto fail;
+  q.host_stop = (const uint32_t *)dp;
+  if (hipHostGetDevicePointer(&dp, d->h_done, 0) != hipSuccess) goto fail;
+  q.host_done = (uint64_t *)dp;
+  if (hipMemcpy(d->d_q, &q, sizeof(q), hipMemcpyHostToDevice) != hipSuccess) goto fail;
+  if (hipMemset(d->d_req, 0, sizeof(ReqState) * ring_capacity) != hipSuccess) goto fail;
+  if (hipMemset(d->d_table_next, 0, 8ull * max_tables) != hipSuccess) goto fail;
+  if (hipStreamCreateWithFlags(&d->capture, hipStreamNonBlocking) != hipSuccess) goto fail;
+  if (hipDeviceSynchronize() != hipSuccess) goto fail;
+  *out = d;
+  return HIVE_OK;
+fail:
+  (void)hipGetLastError();
+  free_drain(d);
+  return HIVE_ERR_HIP;
+}
+
+hive_status hive_drain_submit(hive_drain_t d, hive_t h, const hive_batch_desc *b, uint64_t *ticket) {
+  if (!d || !h || !b || !ticket) return HIVE_ERR_ARG;
+  if (h->S != d->S) return HIVE_ERR_ARG;
+  if (b->op_mode > HIVE_OP_MIXED) return HIVE_ERR_ARG;
+  if (b->n > 0 && !b->d_keys) return HIVE_ERR_ARG;
+  if ((b->op_mode == HIVE_OP_INSERT || b->op_mode == HIVE_OP_MIXED) && b->n > 0 && !b->d_vals) return HIVE_ERR_ARG;
+  if (b->op_mode == HIVE_OP_MIXED && b->n > 0 && !b->d_ops) return HIVE_ERR_ARG;
+  if (b->n >= 0xFFFFFFFFull || (b->flags & ~(uint32_t)HIVE_UNIQUE)) return HIVE_ERR_ARG;
+  const uint64_t t = d->submitted;
+  // the ring slot must be free: the batch `cap` tickets earlier is complete
+  if (t >= d->cap && __atomic_load_n(&d->h_done[t % d->cap], __ATOMIC_ACQUIRE) != t - d->cap + 1)
+    return HIVE_ERR_BUDGET;
+  // table slot (tables registered on first use)
+  uint32_t slot = 0;
+  while (slot < d->n_tables && d->tables[slot] != h) ++slot;
+  if (slot == d->n_tables) {
+    if (d->n_tables >= d->max_tables) return HIVE_ERR_BUDGET;
+    d->tables[slot] = h;
+    d->next_seq[slot] = 0;
+    d->n_tables++;
+  }
+  const bool dedupe = !(b->flags & HIVE_UNIQUE) && b->op_mode != HIVE_OP_LOOKUP;
+  uint64_t dd_size = 0;
+  if (dedupe && b->n > 0) {
+    dd_size = 16;
+    while (dd_size < 2 * b->n) dd_size <<= 1;
+  }
+  // scratch is never reallocated under a running executor
+  if (b->n > h->wl_cap || dd_size > h->dd_cap) {
+    if (d->running) return HIVE_ERR_BUDGET;
+    hive_status s = ensure_scratch(h, b->n, dedupe, h->last);
+    if (s != HIVE_OK) return s;
+  }
+  ReqDesc r;
+  memset(&r, 0, sizeof(r));
+  r.t = TableDesc{h->d_buckets, h->d_hint, h->d_stash, h->d_pending, h->d_ctl, h->d_wl, h->d_dd, h->stash_cap,
+                  h->pending_cap, hint_words(h->max_buckets), h->S, h->cfg.max_evictions, h->cfg.resize_k,
+                  h->cfg.lf_expand_pct, h->cfg.lf_contract_pct, h->cfg.pre_expand, h->cfg.post_policy,
+                  h->cfg.addressing};
+  r.ops = b->d_ops;
+  r.keys = b->d_keys;
+  r.vals = b->d_vals;
+  r.vals_out = b->d_vals_out;
+  r.flags_out = b->d_flags_out;
+  r.n = b->n;
+  r.mode = b->op_mode;
+  r.flags = b->flags;
+  r.seq = d->next_seq[slot]++;
+  r.table_slot = slot;
+  r.ticket = t;
+  r.dd_size = dd_size;
+  memcpy(&d->h_ring[t % d->cap], &r, sizeof(r));
+  __atomic_thread_fence(__ATOMIC_RELEASE);
+  __atomic_store_n(d->h_tail, t + 1, __ATOMIC_RELEASE);
+  d->submitted = t + 1;
+  *ticket = t;
+  return HIVE_OK;
+}
+
+hive_status hive_drain_launch(hive_drain_t d, int resident, void *stream) {
+  if (!d || d->running) return HIVE_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  __atomic_store_n(d->h_stop, resident ? 0u : 1u, __ATOMIC_RELEASE);
+  if (!d->exec) {
+    // the launch is captured once; replays read everything dynamic from the
+    // queue in memory
+    HIP_OK(hipStreamBeginCapture(d->capture, hipStreamCaptureModeRelaxed));
+    launch_drain_any(d, d->capture);
+    hipError_t e = hipGetLastError();
+    hipError_t e2 = hipStreamEndCapture(d->capture, &d->graph);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      fprintf(stderr, "hive: drain graph capture failed: %s / %s\n", hipGetErrorString(e), hipGetErrorString(e2));
+      return HIVE_ERR_HIP;
+    }
+    HIP_OK(hipGraphInstantiate(&d->exec, d->graph, nullptr, nullptr, 0));
+  }
+  HIP_OK(hipGraphLaunch(d->exec, st));
+  d->running = resident != 0;
+  d->running_on = st;
+  return HIVE_OK;
+}
+
+hive_status hive_drain_poll(hive_drain_t d, uint64_t ticket, int *done) {
+  if (!d || !done || ticket >= d->submitted) return HIVE_ERR_ARG;
+  if (d->submitted - ticket > d->cap) {
+    *done = 1;  // its slot has been reused, so it completed long ago
+    return HIVE_OK;
+  }
+  *done = __atomic_load_n(&d->h_done[ticket % d->cap], __ATOMIC_ACQUIRE) == ticket + 1;
+  return HIVE_OK;
+}
+
+hive_status hive_drain_stop(hive_drain_t d, void *stream) {
+  if (!d) return HIVE_ERR_ARG;
+  __atomic_store_n(d->h_stop, 1u, __ATOMIC_RELEASE);
+  d->running = false;
+  HIP_OK(hipStreamSynchronize((hipStream_t)stream));
+  uint32_t err = 0;
+  HIP_OK(hipMemcpy(&err, (char *)d->d_q + offsetof(DrainQueue, error), 4, hipMemcpyDeviceToHost));
+  return err ? HIVE_ERR_HIP : HIVE_OK;
+}
+
+hive_status hive_drain_destroy(hive_drain_t d) {
+  if (!d) return HIVE_ERR_ARG;
+  if (d->running) {
+    __atomic_store_n(d->h_stop, 1u, __ATOMIC_RELEASE);
+    (void)hipStreamSynchronize(d->running_on);
+  }
+  (void)hipDeviceSynchronize();
+  free_drain(d);
   return HIVE_OK;
 }
 

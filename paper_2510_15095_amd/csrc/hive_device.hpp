@@ -81,7 +81,7 @@ struct alignas(128) Ctl {
 //   BitHash2: x -> 4097x + 0x7ed55d16, x -> x ^ 0xc761c23c ^ (x>>19),
 //             x -> 33x + 0x165667b1, x -> (x + 0xd3a2646c) ^ (x<<9),
 //             x -> 9x + 0xfd7046c5, x -> x ^ 0xb55a4f09 ^ (x>>16).
-__host__ __device__ inline uint32_t bithash1(uint32_t x) {
+__host__ __device__ __forceinline__ uint32_t bithash1(uint32_t x) {
   x = x * 32767u - 1u;
   x ^= x >> 12;
   x *= 5u;
@@ -90,7 +90,7 @@ __host__ __device__ inline uint32_t bithash1(uint32_t x) {
   return x ^ (x >> 16);
 }
 
-__host__ __device__ inline uint32_t bithash2(uint32_t x) {
+__host__ __device__ __forceinline__ uint32_t bithash2(uint32_t x) {
   x = x * 4097u + 0x7ed55d16u;
   x = x ^ 0xc761c23cu ^ (x >> 19);
   x = x * 33u + 0x165667b1u;
@@ -102,9 +102,9 @@ __host__ __device__ inline uint32_t bithash2(uint32_t x) {
 // a % d without a divide (gfx950 has no integer divide): Lemire, Kaser and
 // Kurz, "Faster remainder by direct computation" (2019).  magic = 2^64/d
 // rounded up (wrapping to 0 for d = 1, which still yields 0).
-__host__ __device__ inline uint64_t fastmod_magic(uint32_t d) { return ~0ull / d + 1ull; }
+__host__ __device__ __forceinline__ uint64_t fastmod_magic(uint32_t d) { return ~0ull / d + 1ull; }
 
-__host__ __device__ inline uint32_t fastmod(uint32_t a, uint64_t magic, uint32_t d) {
+__host__ __device__ __forceinline__ uint32_t fastmod(uint32_t a, uint64_t magic, uint32_t d) {
   uint64_t low = magic * a;
 #if defined(__HIP_DEVICE_COMPILE__)
   return (uint32_t)__umul64hi(low, (uint64_t)d);
@@ -120,68 +120,79 @@ struct Geo {
   uint32_t mode;
 };
 
-__host__ __device__ inline uint32_t address(const Geo &g, uint32_t h) {
+__host__ __device__ __forceinline__ uint32_t address(const Geo &g, uint32_t h) {
   if (g.mode == ADDR_FIXED) return fastmod(h, g.magic, (uint32_t)g.n_buckets);
   uint32_t a = h & g.im;
   if (a < g.sp) a = h & (2u * g.im + 1u);
   return a;
 }
 
-__device__ inline Geo read_geo(const Ctl *c) {
+// Control-block fields are read with coherent vector loads: a plain uniform
+// load may be served by the scalar cache, which an acquire fence does not
+// invalidate, and the control block changes between the phases of the
+// persistent executor.
+__device__ __forceinline__ uint64_t ld_ctl(const uint64_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t ld_ctl32(const uint32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ Geo read_geo(const Ctl *c) {
   Geo g;
-  g.n_buckets = c->n_buckets;
-  g.magic = c->magic;
-  g.im = (uint32_t)c->im;
-  g.sp = (uint32_t)c->sp;
-  g.mode = c->mode;
+  g.n_buckets = ld_ctl(&c->n_buckets);
+  g.magic = ld_ctl(&c->magic);
+  g.im = (uint32_t)ld_ctl(&c->im);
+  g.sp = (uint32_t)ld_ctl(&c->sp);
+  g.mode = ld_ctl32(&c->mode);
   return g;
 }
 
-__host__ __device__ inline uint64_t pack(uint32_t key, uint32_t value) { return ((uint64_t)value << 32) | key; }
-__host__ __device__ inline uint32_t key_of(uint64_t w) { return (uint32_t)w; }
-__host__ __device__ inline uint32_t value_of(uint64_t w) { return (uint32_t)(w >> 32); }
-__host__ __device__ inline bool valid_key(uint32_t k) { return k != 0u && k != 0xFFFFFFFFu; }
+__host__ __device__ __forceinline__ uint64_t pack(uint32_t key, uint32_t value) { return ((uint64_t)value << 32) | key; }
+__host__ __device__ __forceinline__ uint32_t key_of(uint64_t w) { return (uint32_t)w; }
+__host__ __device__ __forceinline__ uint32_t value_of(uint64_t w) { return (uint32_t)(w >> 32); }
+__host__ __device__ __forceinline__ bool valid_key(uint32_t k) { return k != 0u && k != 0xFFFFFFFFu; }
 
 // ---- wave helpers ---------------------------------------------------------
-__device__ inline uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
 // number of set bits of m below this lane
-__device__ inline uint32_t rank_below(uint64_t m) {
+__device__ __forceinline__ uint32_t rank_below(uint64_t m) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
 // LDS written by one lane of a wave and read by another lane of the same
 // wave: LDS instructions of a wave complete in order, so a compiler-level
 // fence is all that is needed.
-__device__ inline void wave_lds_sync() {
+__device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Device-scope (agent) relaxed atomics on 64-bit words.
-__device__ inline uint64_t cas64(uint64_t *p, uint64_t expected, uint64_t desired) {
+__device__ __forceinline__ uint64_t cas64(uint64_t *p, uint64_t expected, uint64_t desired) {
   __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
   return expected;  // the word found (== expected on success)
 }
 
-__device__ inline uint64_t load_fresh(const uint64_t *p) {
+__device__ __forceinline__ uint64_t load_fresh(const uint64_t *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ inline uint64_t add64(uint64_t *p, uint64_t v) {
+__device__ __forceinline__ uint64_t add64(uint64_t *p, uint64_t v) {
   return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ inline uint32_t or32(uint32_t *p, uint32_t v) {
+__device__ __forceinline__ uint32_t or32(uint32_t *p, uint32_t v) {
   return __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Mix for the per-batch dedupe set and the eviction victim choice: the
 // "lowbias32" integer hash published by C. Wellons (hash-prospector, 2018).
 // It is not one of the bucket hashes, so it is independent of placement.
-__host__ __device__ inline uint32_t mix32(uint32_t x) {
+__host__ __device__ __forceinline__ uint32_t mix32(uint32_t x) {
   x ^= x >> 16;
   x *= 0x7feb352du;
   x ^= x >> 15;

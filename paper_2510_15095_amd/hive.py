@@ -28,7 +28,7 @@ HIVE_WARN_PENDING = 2
 HIVE_FIXED = 0
 HIVE_LINEAR = 1
 HIVE_UNIQUE = 1
-HIVE_OP_INSERT, HIVE_OP_DELETE, HIVE_OP_LOOKUP = 0, 1, 2
+HIVE_OP_INSERT, HIVE_OP_DELETE, HIVE_OP_LOOKUP, HIVE_OP_MIXED = 0, 1, 2, 3
 
 
 class hive_config(ctypes.Structure):
@@ -56,6 +56,19 @@ class hive_stats_t(ctypes.Structure):
 
     def as_dict(self) -> dict:
         return {name: int(getattr(self, name)) for name, _ in self._fields_}
+
+
+class hive_batch_desc(ctypes.Structure):
+    _fields_ = [
+        ("op_mode", ctypes.c_uint32),
+        ("flags", ctypes.c_uint32),
+        ("d_ops", ctypes.c_void_p),
+        ("d_keys", ctypes.c_void_p),
+        ("d_vals", ctypes.c_void_p),
+        ("d_vals_out", ctypes.c_void_p),
+        ("d_flags_out", ctypes.c_void_p),
+        ("n", ctypes.c_uint64),
+    ]
 
 
 class HiveError(RuntimeError):
@@ -89,6 +102,12 @@ def _load():
         "hive_bucket_of": ([p, u32, ctypes.POINTER(u64)], st),
         "hive_fastmod_magic": ([u32], u64),
         "hive_fastmod": ([u32, u64, u32], u32),
+        "hive_drain_create": ([u32, u32, u64, u32, u64, ctypes.POINTER(p)], st),
+        "hive_drain_submit": ([p, p, ctypes.POINTER(hive_batch_desc), ctypes.POINTER(u64)], st),
+        "hive_drain_launch": ([p, st, p], st),
+        "hive_drain_poll": ([p, u64, ctypes.POINTER(st)], st),
+        "hive_drain_stop": ([p, p], st),
+        "hive_drain_destroy": ([p], st),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -241,6 +260,54 @@ def hive_fastmod_magic(d: int) -> int:
 
 def hive_fastmod(a: int, magic: int, d: int) -> int:
     return int(_lib.hive_fastmod(a, magic, d))
+
+
+def hive_drain_create(slots_per_bucket: int = 16, blocks_per_cu: int = 0, ring_capacity: int = 1024,
+                      max_tables: int = 64, idle_limit: int = 0) -> ctypes.c_void_p:
+    d = ctypes.c_void_p()
+    _check(_lib.hive_drain_create(slots_per_bucket, blocks_per_cu, ring_capacity, max_tables, idle_limit,
+                                  ctypes.byref(d)), "hive_drain_create")
+    return d
+
+
+def hive_drain_submit(d, h, op_mode, keys, vals=None, ops=None, vals_out=None, flags_out=None,
+                      flags: int = 0) -> int | None:
+    """Queue one batch; returns its ticket, or None when the ring is full."""
+    import torch
+    n = keys.numel()
+    b = hive_batch_desc()
+    b.op_mode = op_mode
+    b.flags = flags
+    b.d_ops = _dev(ops, torch.uint8, "ops", n, optional=True)
+    b.d_keys = _dev(keys, torch.uint32, "keys")
+    b.d_vals = _dev(vals, torch.uint32, "vals", n, optional=True)
+    b.d_vals_out = _dev(vals_out, torch.uint32, "vals_out", n, optional=True)
+    b.d_flags_out = _dev(flags_out, torch.uint8, "flags_out", n, optional=True)
+    b.n = n
+    t = ctypes.c_uint64()
+    status = _lib.hive_drain_submit(d, h, ctypes.byref(b), ctypes.byref(t))
+    if status == HIVE_ERR_BUDGET:
+        return None
+    _check(status, "hive_drain_submit")
+    return int(t.value)
+
+
+def hive_drain_launch(d, resident: int = 0, stream=None) -> None:
+    _check(_lib.hive_drain_launch(d, resident, _stream_ptr(stream)), "hive_drain_launch")
+
+
+def hive_drain_poll(d, ticket: int) -> bool:
+    done = ctypes.c_int()
+    _check(_lib.hive_drain_poll(d, ticket, ctypes.byref(done)), "hive_drain_poll")
+    return bool(done.value)
+
+
+def hive_drain_stop(d, stream=None) -> None:
+    _check(_lib.hive_drain_stop(d, _stream_ptr(stream)), "hive_drain_stop")
+
+
+def hive_drain_destroy(d) -> None:
+    _check(_lib.hive_drain_destroy(d), "hive_drain_destroy")
 
 
 # ------------------------------------------------------------ convenience

@@ -441,3 +441,149 @@ def test_linear_merge_stops_when_pair_does_not_fit(H):
     v, f = t.lookup(dev(ins))
     assert host(f).all()
     t.close()
+
+
+# ---------------------------------------------------------------- executor
+def _mixed_batches(seed, n_batches, n_ops, universe, ks):
+    return [wl.mixed_batch(seed, b, n_ops, universe, stream=ks, value_salt=b + 1) for b in range(n_batches)]
+
+
+def test_drain_matches_plain_and_oracle_mixed(H):
+    """The persistent executor gives the same per-batch outputs and final
+    contents as one plain launch sequence per batch, and as the dictionary."""
+    import torch
+    universe, nb = 1 << 16, 2048
+    ks = wl.KeyStream(61)
+    pre = ks.keys(wl.DomainPerm(61, universe).sample(int(0.85 * nb * 16)))
+    batches = _mixed_batches(61, 6, 1 << 13, universe, ks)
+    plain = H.Table(nb, stash_capacity=2048, max_batch=1 << 13)
+    drained = H.Table(nb, stash_capacity=2048, max_batch=1 << 13)
+    o = oracle.O1()
+    for t in (plain, drained):
+        t.insert(dev(pre), dev(wl.values_for(pre)), flags=H.HIVE_UNIQUE)
+    o.insert(pre, wl.values_for(pre))
+    d = H.hive_drain_create(16, 0, 64, 8, 1 << 21)
+    outs, tickets, keep = [], [], []
+    for mb in batches:
+        o_, k_, v_ = dev(mb["ops"]), dev(mb["keys"]), dev(mb["vals"])
+        vo = torch.full((k_.numel(),), 7, dtype=torch.uint32, device="cuda")
+        fo = torch.full((k_.numel(),), 9, dtype=torch.uint8, device="cuda")
+        keep += [o_, k_, v_]
+        tickets.append(H.hive_drain_submit(d, drained.h, H.HIVE_OP_MIXED, k_, v_, o_, vo, fo))
+        outs.append((vo, fo))
+    case("drain launch, 6 mixed batches")
+    H.hive_drain_launch(d, 0)
+    torch.cuda.synchronize()
+    assert all(H.hive_drain_poll(d, t) for t in tickets)
+    for b, mb in enumerate(batches):
+        pv, pf = plain.mixed(dev(mb["ops"]), dev(mb["keys"]), dev(mb["vals"]))
+        ov, of = o.apply(mb["ops"], mb["keys"], mb["vals"])
+        assert np.array_equal(host(outs[b][1]), of) and np.array_equal(host(outs[b][0]), ov), f"batch {b}"
+        assert np.array_equal(host(pf), of) and np.array_equal(host(pv), ov)
+    assert np.array_equal(drained.dump(), o.dump()) and np.array_equal(plain.dump(), o.dump())
+    assert drained.stats()["live"] == len(o)
+    H.hive_drain_destroy(d)
+
+
+def test_drain_multi_table_linear_policies(H):
+    """Interleaved batches on three LINEAR tables with pre-batch expansion
+    and post-batch contraction: outputs equal the dictionary's and the
+    geometry equals that of the same sequence run with plain launches."""
+    import torch
+    S, nb0, mb_ = 16, 8, 2048
+    names = range(3)
+    tabs = {i: linear_table(H, nb0, mb_, 4) for i in names}
+    refs = {i: linear_table(H, nb0, mb_, 4) for i in names}
+    o1 = {i: oracle.O1() for i in names}
+    d = H.hive_drain_create(16, 0, 128, 8, 1 << 21)
+    ks = {i: wl.KeyStream(70 + i) for i in names}
+    plan = []
+    for step in range(5):
+        for i in names:
+            plan.append((i, H.HIVE_OP_INSERT, ks[i].range(step * 900, (step + 1) * 900)))
+    for i in names:
+        plan.append((i, H.HIVE_OP_LOOKUP, ks[i].range(0, 5000)))
+    for step in range(4):
+        for i in names:
+            plan.append((i, H.HIVE_OP_DELETE, ks[i].range(step * 1100, (step + 1) * 1100)))
+    for i in names:
+        plan.append((i, H.HIVE_OP_LOOKUP, ks[i].range(0, 5000)))
+    keep, outs = [], []
+    for i, mode, keys in plan:
+        k_ = dev(keys)
+        v_ = dev(wl.values_for(keys)) if mode == H.HIVE_OP_INSERT else None
+        vo = torch.empty(keys.size, dtype=torch.uint32, device="cuda")
+        fo = torch.empty(keys.size, dtype=torch.uint8, device="cuda")
+        keep += [k_, v_]
+        t = H.hive_drain_submit(d, tabs[i].h, mode, k_, v_, None, vo, fo, flags=H.HIVE_UNIQUE)
+        assert t is not None
+        outs.append((vo, fo))
+    case("drain launch, multi-table linear")
+    H.hive_drain_launch(d, 0)
+    torch.cuda.synchronize()
+    for (i, mode, keys), (vo, fo) in zip(plan, outs):
+        t = refs[i]
+        if mode == H.HIVE_OP_INSERT:
+            t.insert(dev(keys), dev(wl.values_for(keys)), flags=H.HIVE_UNIQUE)
+            o1[i].insert(keys, wl.values_for(keys))
+        elif mode == H.HIVE_OP_DELETE:
+            pf = t.delete(dev(keys), flags=H.HIVE_UNIQUE)
+            assert np.array_equal(host(fo), o1[i].delete(keys)) and np.array_equal(host(pf), host(fo))
+        else:
+            t.lookup(dev(keys))
+            ov, of = o1[i].lookup(keys)
+            assert np.array_equal(host(fo), of) and np.array_equal(host(vo), ov)
+    for i in names:
+        g1, g2 = geometry(tabs[i].stats()), geometry(refs[i].stats())
+        assert g1 == g2 or policy_stable(tabs[i], S, initial=nb0), (g1, g2)
+        assert np.array_equal(tabs[i].dump(), o1[i].dump())
+    H.hive_drain_destroy(d)
+
+
+def test_drain_resident_incremental_and_backpressure(H):
+    """A resident grid serves batches submitted while it runs; a full ring
+    refuses submissions until earlier batches complete."""
+    import time
+
+    import torch
+    t = H.Table(1024, max_batch=4096)
+    o = oracle.O1()
+    d = H.hive_drain_create(16, 0, 4, 4, 1 << 22)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()  # the resident grid must not block torch's own stream
+    H.hive_drain_launch(d, 1, side)
+    ks = wl.KeyStream(80)
+    keep = []
+    refused = 0
+    for b in range(12):
+        keys = ks.range(b * 1000, b * 1000 + 1000)
+        vals = wl.values_for(keys)
+        k_, v_ = dev(keys), dev(vals)
+        torch.cuda.current_stream().synchronize()
+        keep += [k_, v_]
+        case(f"resident submit {b}")
+        deadline = time.time() + 30
+        while True:
+            tk = H.hive_drain_submit(d, t.h, H.HIVE_OP_INSERT, k_, v_, flags=H.HIVE_UNIQUE)
+            if tk is not None:
+                break
+            refused += 1
+            assert time.time() < deadline, "ring never drained"
+            time.sleep(0.0005)
+        o.insert(keys, vals)
+        if b % 3 == 2:  # a lookup batch; wait for it before the next submission
+            q = dev(ks.range(0, 13000))
+            vo = torch.empty(13000, dtype=torch.uint32, device="cuda")
+            fo = torch.empty(13000, dtype=torch.uint8, device="cuda")
+            torch.cuda.current_stream().synchronize()
+            keep += [q, vo, fo]
+            while (lt := H.hive_drain_submit(d, t.h, H.HIVE_OP_LOOKUP, q, None, None, vo, fo)) is None:
+                time.sleep(0.0005)
+            while not H.hive_drain_poll(d, lt):
+                assert time.time() < deadline, "lookup batch never completed"
+                time.sleep(0.0002)
+            ov, of = o.lookup(ks.range(0, 13000))
+            assert np.array_equal(host(fo), of) and np.array_equal(host(vo), ov)
+    H.hive_drain_stop(d, side)
+    assert np.array_equal(t.dump(), o.dump())
+    H.hive_drain_destroy(d)
