@@ -170,6 +170,10 @@ hive_status hive_dump(hive_t h, uint64_t *d_words, int64_t *d_where, uint64_t ca
  * out[1] entries.  Synchronizes `stream`. */
 hive_status hive_placement(hive_t h, uint64_t *out, void *stream);
 
+/* Enqueue a copy of the table's key count into *host_dst (pinned host
+ * memory) on `stream`, after the work already on it; no synchronization. */
+hive_status hive_live_async(hive_t h, uint64_t *host_dst, void *stream);
+
 /* Empty the table and restore its initial geometry (stream-ordered). */
 hive_status hive_clear(hive_t h, void *stream);
 
@@ -210,17 +214,26 @@ hive_status hive_drain_create(uint32_t slots_per_bucket, uint32_t blocks_per_cu,
  * more scratch than the table has (create tables with max_batch). */
 hive_status hive_drain_submit(hive_drain_t d, hive_t table, const hive_batch_desc *b, uint64_t *ticket);
 
-/* Launch the resident grid on `stream`.  resident = 0: it exits once every
- * batch submitted so far is complete.  resident = 1: it keeps serving
- * batches submitted later until hive_drain_stop. */
+/* Launch the grid.  resident = 0: on `stream`; it exits once every batch
+ * submitted so far is complete.  resident = 1: on the executor's own
+ * non-blocking stream, after the work already enqueued on `stream`; it keeps
+ * serving batches submitted later until hive_drain_stop, and holds up no
+ * other stream meanwhile (device memory the batches use must be allocated
+ * before the launch). */
 hive_status hive_drain_launch(hive_drain_t d, int resident, void *stream);
 
 /* *done = 1 once the batch's outputs and table updates are complete and
  * visible to the host (no HIP call). */
 hive_status hive_drain_poll(hive_drain_t d, uint64_t ticket, int *done);
 
-/* Tell a resident grid to exit when its queue is empty and wait for it on
- * `stream`.  Returns HIVE_ERR_HIP if a block gave up on its idle watchdog. */
+/* Like hive_drain_poll, and once done *live_after = the table's key count
+ * right after the batch (for admission control without a device sync).
+ * Valid while the ticket's ring slot has not been reused. */
+hive_status hive_drain_result(hive_drain_t d, uint64_t ticket, int *done, uint64_t *live_after);
+
+/* Tell a resident grid to exit when its queue is empty and wait for it
+ * (`stream` is unused).  Returns HIVE_ERR_HIP if a block gave up on its idle
+ * watchdog. */
 hive_status hive_drain_stop(hive_drain_t d, void *stream);
 
 /* Stop (if needed), synchronize and free the executor. */

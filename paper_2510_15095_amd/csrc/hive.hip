@@ -1127,6 +1127,7 @@ struct DrainQueue {
   const uint64_t *host_tail;  // pinned: descriptors written by the host
   const uint32_t *host_stop;  // pinned: set when no more work will come
   uint64_t *host_done;        // pinned: per ring slot, ticket + 1 once complete
+  uint64_t *host_live;        // pinned: per ring slot, the table's live count after the batch
   uint64_t *table_next;       // per table slot: sequence number allowed to run
   uint64_t cap;
   uint64_t idle_limit;        // idle polls before a block gives up (watchdog)
@@ -1135,6 +1136,8 @@ struct DrainQueue {
   uint64_t completed;
   uint32_t ingest_lock;
   uint32_t error;             // 1: a block hit the idle watchdog
+  uint32_t final_seen;        // the host stopped and every submitted batch was ingested
+  uint32_t pad_;
 };
 
 __device__ __forceinline__ uint64_t make_state(uint32_t ph, uint64_t nch) {
@@ -1266,6 +1269,8 @@ __device__ void advance(DrainQueue *q, ReqState *rs, const ReqDesc &d, uint32_t 
   r->done = 0;
   if (ph == PH_DONE) {
     const uint64_t ticket = d.ticket;
+    __hip_atomic_store(&q->host_live[ticket % q->cap], ld_ctl(&d.t.ctl->live), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_SYSTEM);
     __threadfence_system();  // the batch's outputs before its completion flag
     __hip_atomic_store(&q->table_next[d.table_slot], d.seq + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store(&rs->state, make_state(PH_DONE, 0), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
@@ -1277,17 +1282,21 @@ __device__ void advance(DrainQueue *q, ReqState *rs, const ReqDesc &d, uint32_t 
   __hip_atomic_store(&rs->state, make_state(ph, nch), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Copy new host descriptors into the device ring (one block at a time).
+// Copy new host descriptors into the device ring.  Only the block holding
+// the ingest lock reads host memory (the tail, the stop flag, descriptors);
+// every other block polls device memory.  The stop flag is read before the
+// tail, so once it is seen set, the tail read after it is final.
 __device__ void ingest(DrainQueue *q) {
   if (__hip_atomic_load(&q->ingest_lock, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
   uint32_t expect = 0;
   if (!__hip_atomic_compare_exchange_strong(&q->ingest_lock, &expect, 1u, __ATOMIC_ACQUIRE, __ATOMIC_RELAXED,
                                             __HIP_MEMORY_SCOPE_AGENT))
     return;
+  const bool stop = __hip_atomic_load(q->host_stop, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM) != 0;
   const uint64_t tail = ld_sys(q->host_tail);
   uint64_t i = ld_ctl(&q->ingested);
-  const uint64_t stop = min(tail, i + 16);
-  for (; i < stop; ++i) {
+  const uint64_t lim = min(tail, i + 16);
+  for (; i < lim; ++i) {
     const uint64_t *src = (const uint64_t *)(q->host_ring + i % q->cap);
     ReqState *r = q->req + i % q->cap;
     uint64_t *dst = (uint64_t *)&r->d;
@@ -1303,6 +1312,7 @@ __device__ void ingest(DrainQueue *q) {
     __hip_atomic_store(&r->state, make_state(PH_START, 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   }
   __hip_atomic_store(&q->ingested, i, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  if (stop && i == tail) __hip_atomic_store(&q->final_seen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   __hip_atomic_store(&q->ingest_lock, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -1321,8 +1331,9 @@ __device__ uint32_t find_work(DrainQueue *q, uint64_t *req, uint32_t *phase, uin
     head = ld_ctl(&q->head);
   }
   if (head == ing) {
-    const bool stop = __hip_atomic_load(q->host_stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0;
-    if (stop && ld_sys(q->host_tail) == ing) return 2;
+    if (__hip_atomic_load(&q->final_seen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != 0 &&
+        ld_ctl(&q->ingested) == ing)
+      return 2;
     return 1;
   }
   const uint64_t end = min(ing, head + DRAIN_WINDOW);
@@ -1453,6 +1464,8 @@ __device__ void run_chunk(ReqState *r, const ReqDesc &d, uint32_t ph, uint64_t c
   }
 }
 
+__global__ void drain_reset_kernel(DrainQueue *q) { q->final_seen = 0; }
+
 template <int S>
 __global__ __launch_bounds__(BLOCK) void drain_worker_kernel(DrainQueue *q) {
   __shared__ OpsShared<S> sh;
@@ -1471,7 +1484,7 @@ __global__ __launch_bounds__(BLOCK) void drain_worker_kernel(DrainQueue *q) {
         if (threadIdx.x == 0) atomicOr(&q->error, 1u);
         break;
       }
-      __builtin_amdgcn_s_sleep(4);
+      __builtin_amdgcn_s_sleep(32);
       __syncthreads();
       continue;
     }
@@ -1528,6 +1541,7 @@ struct hive_drain {
   uint64_t *h_tail = nullptr;
   uint32_t *h_stop = nullptr;
   uint64_t *h_done = nullptr;
+  uint64_t *h_live = nullptr;
   uint64_t submitted = 0;
   // per registered table: its slot in table_next and its next sequence number
   hive_table *tables[4096];
@@ -1733,6 +1747,7 @@ static void free_drain(hive_drain *d) {
   (void)hipHostFree(d->h_tail);
   (void)hipHostFree(d->h_stop);
   (void)hipHostFree(d->h_done);
+  (void)hipHostFree(d->h_live);
   delete d;
 }
 
@@ -1996,6 +2011,14 @@ hive_status hive_placement(hive_t h, uint64_t *out, void *stream) {
   return HIVE_OK;
 }
 
+hive_status hive_live_async(hive_t h, uint64_t *host_dst, void *stream) {
+  if (!h || !host_dst) return HIVE_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  h->last = st;
+  HIP_OK(hipMemcpyAsync(host_dst, &h->d_ctl->live, 8, hipMemcpyDeviceToHost, st));
+  return HIVE_OK;
+}
+
 hive_status hive_clear(hive_t h, void *stream) {
   if (!h) return HIVE_ERR_ARG;
   hipStream_t st = (hipStream_t)stream;
@@ -2064,13 +2087,15 @@ hive_status hive_drain_create(uint32_t slots_per_bucket, uint32_t blocks_per_cu,
   if (hipHostMalloc((void **)&d->h_ring, sizeof(ReqDesc) * ring_capacity, hflags) != hipSuccess ||
       hipHostMalloc((void **)&d->h_tail, 64, hflags) != hipSuccess ||
       hipHostMalloc((void **)&d->h_stop, 64, hflags) != hipSuccess ||
-      hipHostMalloc((void **)&d->h_done, 8 * ring_capacity, hflags) != hipSuccess) {
+      hipHostMalloc((void **)&d->h_done, 8 * ring_capacity, hflags) != hipSuccess ||
+      hipHostMalloc((void **)&d->h_live, 8 * ring_capacity, hflags) != hipSuccess) {
     (void)hipGetLastError();
     free_drain(d);
     return HIVE_ERR_OOM;
   }
   memset(d->h_ring, 0, sizeof(ReqDesc) * ring_capacity);
   memset(d->h_done, 0, 8 * ring_capacity);
+  memset(d->h_live, 0, 8 * ring_capacity);
   *d->h_tail = 0;
   *d->h_stop = 1;
   DrainQueue q;
@@ -2088,6 +2113,8 @@ hive_status hive_drain_create(uint32_t slots_per_bucket, uint32_t blocks_per_cu,
   q.host_stop = (const uint32_t *)dp;
   if (hipHostGetDevicePointer(&dp, d->h_done, 0) != hipSuccess) goto fail;
   q.host_done = (uint64_t *)dp;
+  if (hipHostGetDevicePointer(&dp, d->h_live, 0) != hipSuccess) goto fail;
+  q.host_live = (uint64_t *)dp;
   if (hipMemcpy(d->d_q, &q, sizeof(q), hipMemcpyHostToDevice) != hipSuccess) goto fail;
   if (hipMemset(d->d_req, 0, sizeof(ReqState) * ring_capacity) != hipSuccess) goto fail;
   if (hipMemset(d->d_table_next, 0, 8ull * max_tables) != hipSuccess) goto fail;
@@ -2162,8 +2189,21 @@ hive_status hive_drain_submit(hive_drain_t d, hive_t h, const hive_batch_desc *b
 
 hive_status hive_drain_launch(hive_drain_t d, int resident, void *stream) {
   if (!d || d->running) return HIVE_ERR_ARG;
-  hipStream_t st = (hipStream_t)stream;
+  hipStream_t user = (hipStream_t)stream;
+  // a resident grid runs on the executor's own non-blocking stream, after the
+  // work already enqueued on `stream`, so it holds up no other stream
+  hipStream_t st = resident ? d->capture : user;
+  if (resident) {
+    hipEvent_t ev;
+    HIP_OK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    HIP_OK(hipEventRecord(ev, user));
+    HIP_OK(hipStreamWaitEvent(st, ev, 0));
+    HIP_OK(hipEventDestroy(ev));
+  }
   __atomic_store_n(d->h_stop, resident ? 0u : 1u, __ATOMIC_RELEASE);
+  // the grid of the previous launch has exited; clear its exit flag
+  hipLaunchKernelGGL(drain_reset_kernel, dim3(1), dim3(1), 0, st, d->d_q);
+  HIP_OK(hipGetLastError());
   if (!d->exec) {
     // the launch is captured once; replays read everything dynamic from the
     // queue in memory
@@ -2193,11 +2233,19 @@ hive_status hive_drain_poll(hive_drain_t d, uint64_t ticket, int *done) {
   return HIVE_OK;
 }
 
+hive_status hive_drain_result(hive_drain_t d, uint64_t ticket, int *done, uint64_t *live_after) {
+  if (!d || !done || !live_after || ticket >= d->submitted || d->submitted - ticket > d->cap) return HIVE_ERR_ARG;
+  *done = __atomic_load_n(&d->h_done[ticket % d->cap], __ATOMIC_ACQUIRE) == ticket + 1;
+  *live_after = *done ? __atomic_load_n(&d->h_live[ticket % d->cap], __ATOMIC_RELAXED) : 0;
+  return HIVE_OK;
+}
+
 hive_status hive_drain_stop(hive_drain_t d, void *stream) {
   if (!d) return HIVE_ERR_ARG;
+  (void)stream;
   __atomic_store_n(d->h_stop, 1u, __ATOMIC_RELEASE);
   d->running = false;
-  HIP_OK(hipStreamSynchronize((hipStream_t)stream));
+  HIP_OK(hipStreamSynchronize(d->running_on));
   uint32_t err = 0;
   HIP_OK(hipMemcpy(&err, (char *)d->d_q + offsetof(DrainQueue, error), 4, hipMemcpyDeviceToHost));
   return err ? HIVE_ERR_HIP : HIVE_OK;

@@ -96,6 +96,7 @@ def _load():
         "hive_dump": ([p, p, p, u64, ctypes.POINTER(u64), p], st),
         "hive_clear": ([p, p], st),
         "hive_placement": ([p, ctypes.POINTER(u64), p], st),
+        "hive_live_async": ([p, p, p], st),
         "hive_status_string": ([st], ctypes.c_char_p),
         "hive_bithash1": ([u32], u32),
         "hive_bithash2": ([u32], u32),
@@ -106,6 +107,7 @@ def _load():
         "hive_drain_submit": ([p, p, ctypes.POINTER(hive_batch_desc), ctypes.POINTER(u64)], st),
         "hive_drain_launch": ([p, st, p], st),
         "hive_drain_poll": ([p, u64, ctypes.POINTER(st)], st),
+        "hive_drain_result": ([p, u64, ctypes.POINTER(st), ctypes.POINTER(u64)], st),
         "hive_drain_stop": ([p, p], st),
         "hive_drain_destroy": ([p], st),
     }
@@ -232,6 +234,11 @@ def hive_placement(h, stream=None) -> tuple[int, int, int]:
     return int(out[0]), int(out[1]), int(out[2])
 
 
+def hive_live_async(h, host_dst_ptr: int, stream=None) -> None:
+    """host_dst_ptr: address of 8 bytes of pinned host memory."""
+    _check(_lib.hive_live_async(h, ctypes.c_void_p(host_dst_ptr), _stream_ptr(stream)), "hive_live_async")
+
+
 def hive_clear(h, stream=None) -> None:
     _check(_lib.hive_clear(h, _stream_ptr(stream)), "hive_clear")
 
@@ -300,6 +307,12 @@ def hive_drain_poll(d, ticket: int) -> bool:
     done = ctypes.c_int()
     _check(_lib.hive_drain_poll(d, ticket, ctypes.byref(done)), "hive_drain_poll")
     return bool(done.value)
+
+
+def hive_drain_result(d, ticket: int) -> tuple[bool, int]:
+    done, live = ctypes.c_int(), ctypes.c_uint64()
+    _check(_lib.hive_drain_result(d, ticket, ctypes.byref(done), ctypes.byref(live)), "hive_drain_result")
+    return bool(done.value), int(live.value)
 
 
 def hive_drain_stop(d, stream=None) -> None:

@@ -587,3 +587,38 @@ def test_drain_resident_incremental_and_backpressure(H):
     H.hive_drain_stop(d, side)
     assert np.array_equal(t.dump(), o.dump())
     H.hive_drain_destroy(d)
+
+
+# ---------------------------------------------------------------- serving
+_SERVED = {}
+
+
+def _served_setup():
+    """Specs and requests are generated before any GPU work of this module's
+    serving tests (the generator forks worker processes)."""
+    if not _SERVED:
+        from paper_2510_15095_amd import serve as sv
+        specs = sv.make_specs(12, 9, log2_min=10, log2_max=14)
+        reqs = sv.make_requests(specs, 300, 9, rate=20000.0, log2_max_size=11, workers=0)
+        _SERVED.update(specs=specs, reqs=reqs)
+    return _SERVED["specs"], _SERVED["reqs"]
+
+
+def test_served_results_same_alone_and_in_the_mix(H):
+    """Each request's outputs are the same whether it runs alone (one at a
+    time, in submission order) or in the mix served by the persistent
+    executor or by plain per-request launches on several streams."""
+    from paper_2510_15095_amd import serve as sv
+    specs, reqs = _served_setup()
+    srv = sv.Server(specs, 2 * sv.footprint_bytes(specs), max_request=1 << 11, ring=64, streams=4)
+    case("served: alone")
+    srv.load()
+    alone = srv.run_alone(reqs)
+    for mode in ("persistent", "plain"):
+        case(f"served: {mode}")
+        srv.load()
+        res = srv.run(reqs, mode, outputs=True, timeout_s=60)
+        for i, ((v1, f1), (v2, f2)) in enumerate(zip(alone, res["results"])):
+            assert np.array_equal(f1, f2) and np.array_equal(v1, v2), f"{mode}: request {i} differs"
+        print(mode, {k: v for k, v in res.items() if k != "results"})
+    srv.close()
