@@ -39,11 +39,19 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=("bulk", "mixed", "resize"), default="bulk")
+    ap.add_argument("--workload", choices=("bulk", "mixed", "resize", "served"), default="bulk")
+    ap.add_argument("--executor", choices=("plain", "persistent"), default="plain",
+                    help="mixed: one launch sequence per batch, or the persistent executor")
+    ap.add_argument("--tables", type=int, default=256, help="served: tables")
+    ap.add_argument("--requests", type=int, default=4000, help="served: requests")
+    ap.add_argument("--request-log2", type=float, default=16, help="served: largest request (log2 ops)")
     ap.add_argument("--keys-log2", type=int, default=26)
     ap.add_argument("--batches", type=int, default=64, help="mixed/resize: insert batches")
     ap.add_argument("--batch-log2", type=int, default=22, help="mixed/resize: operations per batch")
-    ap.add_argument("--resize-k", type=int, default=1024)
+    ap.add_argument("--resize-k", type=int, default=0, help="0: the autotuned value if cached, else 1024")
+    ap.add_argument("--autotune", action="store_true", help="run the autotuner first and use its picks")
+    ap.add_argument("--probe-both", type=int, default=-1,
+                    help="bulk: 1 = lookups/deletes probe both candidates in one round (-1: autotuned, else 0)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-log2", type=int, default=22)
     return ap.parse_args()
@@ -83,7 +91,18 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
-    out = {"bulk": run_bulk, "mixed": run_mixed, "resize": run_resize}[args.workload](args)
+    tuned = {}
+    if args.workload in ("mixed", "resize", "served"):
+        from paper_2510_15095_amd import autotune
+        if args.autotune:
+            autotune.tune(args.workload)
+        tuned = {"resize": autotune.load("resize"), "executor": autotune.load("executor")}
+    if not args.resize_k:
+        args.resize_k = (tuned.get("resize") or {}).get("resize_k", 1024)
+    args.blocks_per_cu = (tuned.get("executor") or {}).get("blocks_per_cu", 0)
+    out = {"bulk": run_bulk, "mixed": run_mixed, "resize": run_resize, "served": run_served}[args.workload](args)
+    if tuned:
+        out["autotuned"] = {k: v for k, v in tuned.items() if v}
     print(json.dumps(out), flush=True)
 
 
@@ -147,7 +166,18 @@ def run_mixed(args):
         t.insert(pk, pv, flags=H.HIVE_UNIQUE)
         torch.cuda.synchronize()
 
+    drain = (H.hive_drain_create(16, args.blocks_per_cu, max(64, nbat), 4, 0) if args.executor == "persistent"
+             else None)
+
     def run(evs):
+        if drain is not None:
+            # every batch is queued, then one launch (a replayed graph) drains them
+            evs[0].record()
+            for (o, k, v) in batches:
+                H.hive_drain_submit(drain, t.h, H.HIVE_OP_MIXED, k, v, o, vout, fout)
+            H.hive_drain_launch(drain, 0)
+            evs[-1].record()
+            return
         for j, (o, k, v) in enumerate(batches):
             evs[j].record()
             H.hive_mixed_batch(t.h, o, k, v, vout, fout)
@@ -163,12 +193,17 @@ def run_mixed(args):
         ev = mk()
         run(ev)
         torch.cuda.synchronize()
-        times.append([ev[j].elapsed_time(ev[j + 1]) for j in range(nbat)])
+        if drain is not None:
+            times.append([ev[0].elapsed_time(ev[-1]) / nbat] * nbat)
+        else:
+            times.append([ev[j].elapsed_time(ev[j + 1]) for j in range(nbat)])
     ms = np.array(times)
+    if drain is not None:
+        H.hive_drain_destroy(drain)
     st = t.stats()
     ms_step = float(ms.sum(axis=1).mean())
     rec = base_record(args, nbat * n_ops / (ms_step * 1e-3) / 1e6, ms_step,
-                      f"mixed contended, plain launch: prefill 2^24 of a 2^26-key Zipf universe at 95% load "
+                      f"mixed contended, {args.executor} executor: prefill 2^24 of a 2^26-key Zipf universe at 95% load "
                       f"(LINEAR, {nb0} x 16-slot buckets), {nbat} batches of 2^{args.batch_log2} ops "
                       f"40/40/20 insert/delete/lookup, Zipf(0.99), per-type disjoint, dedupe on",
                       {"ops_per_step": nbat * n_ops, "batches": nbat, "resize_k": args.resize_k})
@@ -177,6 +212,50 @@ def run_mixed(args):
     rec["final_stats"] = {k: st[k] for k in ("live", "n_buckets", "stash_count", "pending_count", "evictions",
                                              "evict_items", "status")}
     t.close()
+    return rec
+
+
+def run_served(args):
+    """Served multi-table loop: many LINEAR tables (log-uniform sizes,
+    created at 85% load, 25% HBM headroom each), mixed requests (50% lookup,
+    25% insert, 25% delete; uniform or Zipf(0.99) keys; log-uniform sizes)
+    aimed at random tables.  First all requests arrive at once (saturation
+    throughput of each mode), then Poisson arrivals at 70% of the slower
+    mode's saturation rate (p50/p99 latency of each mode)."""
+    import torch
+    from paper_2510_15095_amd import serve as sv
+    specs = sv.make_specs(args.tables, 5, log2_min=12, log2_max=22)
+    reqs = sv.make_requests(specs, args.requests, 5, rate=0, log2_max_size=args.request_log2,
+                            workers=min(16, os.cpu_count() or 1))
+    budget = sv.footprint_bytes(specs)
+    srv = sv.Server(specs, budget, max_request=1 << int(np.ceil(args.request_log2)), ring=1024, streams=8)
+    res = {}
+    for mode in ("plain", "persistent"):
+        srv.load()
+        srv.run(reqs[: min(200, len(reqs))], mode)  # warm-up
+        srv.load()
+        res[mode + "_saturation"] = srv.run(reqs, mode)
+    mean_ops = float(np.mean([r.n for r in reqs]))
+    sat_rate = min(res["plain_saturation"]["mops"], res["persistent_saturation"]["mops"]) * 1e6 / mean_ops
+    rate = 0.7 * sat_rate
+    gaps = np.random.default_rng(55).exponential(1.0 / rate, len(reqs))
+    arrivals = np.cumsum(gaps) - gaps[0]
+    for r, a in zip(reqs, arrivals):
+        r.arrival = float(a)
+    for mode in ("plain", "persistent"):
+        srv.load()
+        res[mode + "_poisson"] = srv.run(reqs, mode)
+    srv.close()
+    torch.cuda.synchronize()
+    p = res["persistent_poisson"]
+    rec = base_record(args, res["persistent_saturation"]["mops"], res["persistent_saturation"]["span_s"] * 1e3,
+                      f"served multi-table loop: {args.tables} LINEAR tables of 2^U(12,22) keys at 85% load "
+                      f"(HBM budget = reservations incl. 25% headroom), {args.requests} mixed requests of "
+                      f"2^U(0,{args.request_log2}) ops, persistent executor vs per-request launches on 8 streams",
+                      {"ops_per_step": p["ops"], "tables": args.tables, "requests": args.requests,
+                       "poisson_rate_req_per_s": round(rate, 1)})
+    rec["served"] = {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                     for k, v in res.items()}
     return rec
 
 
@@ -261,7 +340,10 @@ def run_bulk(args):
     vout = torch.empty(n, dtype=torch.uint32, device=dev)
     fout = torch.empty(n, dtype=torch.uint8, device=dev)
     dout = torch.empty(dk.numel(), dtype=torch.uint8, device=dev)
-    t = H.Table(nb, slots_per_bucket=S, max_evictions=8, max_batch=n)
+    if args.probe_both < 0:
+        from paper_2510_15095_amd import autotune
+        args.probe_both = (autotune.load("probe") or {}).get("probe_both", 0)
+    t = H.Table(nb, slots_per_bucket=S, max_evictions=8, max_batch=n, probe_both=args.probe_both)
     n_present = int((w["query_idx"] < n).sum())
     deleted = np.zeros(n, bool)
     deleted[w["del_idx"]] = True
@@ -344,6 +426,7 @@ def run_bulk(args):
         "dtype": "u32",
         "data": "synthetic",
         "config": {
+            "probe_both": args.probe_both,
             "workload": f"bulk build to 95% load, plain launch: 2^{args.keys_log2} unique uniform keys into "
                         f"{nb} x {S}-slot buckets (FIXED), 2^{args.keys_log2} lookups at 50% hits, delete "
                         f"2^{args.keys_log2 - 1}, re-lookup",

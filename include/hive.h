@@ -81,6 +81,11 @@ typedef struct {
                                  growth headroom; 0 = initial buckets) */
   uint64_t max_batch;         /* scratch preallocated for batches of this many
                                  operations (0 = grow on demand) */
+  uint32_t probe_both;        /* S = 16: 1 = lookups and deletes load both
+                                 candidate buckets in one round (one memory
+                                 round trip fewer, more bytes); inserts always
+                                 do.  0 = second bucket only after a miss */
+  uint32_t reserved_;
 } hive_config;
 
 typedef struct {

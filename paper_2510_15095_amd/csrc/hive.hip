@@ -302,7 +302,10 @@ __device__ __forceinline__ OpsView read_view(const Ctl *c, uint64_t stash_cap, u
 }
 
 // P1 for one tile of WAVES x 64 operations [tile * 256, tile * 256 + 256).
-template <int S, uint32_t MODE>
+// BOTH: probe both candidates in one round for every operation (inserts of
+// new keys always need both; for lookups and deletes it trades bytes for one
+// memory round trip fewer).
+template <int S, uint32_t MODE, bool BOTH>
 __device__ __forceinline__ void ops_tile(const OpsArgs &a, const OpsView &view, uint64_t tile, OpsShared<S> &sh) {
   using T = Traits<S>;
   using Mask = typename T::Mask;
@@ -344,7 +347,7 @@ __device__ __forceinline__ void ops_tile(const OpsArgs &a, const OpsView &view, 
   // Inserts of new keys need both candidates (absence check and two-choice
   // placement), so insert batches probe both in one round; lookups and
   // deletes probe the second candidate only after a miss in the first.
-  constexpr bool kFused = (MODE == OP_INSERT) && (S == 16);
+  constexpr bool kFused = (MODE == OP_INSERT || BOTH) && (S == 16);
   Mask m1;
   bool need2;
   if constexpr (kFused) {
@@ -496,12 +499,12 @@ __device__ __forceinline__ void ops_tile(const OpsArgs &a, const OpsView &view, 
   }
 }
 
-template <int S, uint32_t MODE>
+template <int S, uint32_t MODE, bool BOTH>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(OPS_WAVES_PER_EU))) void ops_kernel(
     OpsArgs a) {
   __shared__ OpsShared<S> sh;
   const OpsView view = read_view(a.ctl, a.stash_cap, a.pending_cap);
-  ops_tile<S, MODE>(a, view, blockIdx.x, sh);
+  ops_tile<S, MODE, BOTH>(a, view, blockIdx.x, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -1094,6 +1097,7 @@ struct TableDesc {
   uint64_t *dd;
   uint64_t stash_cap, pending_cap, hint_words;
   uint32_t S, max_evictions, K, lf_expand_pct, lf_contract_pct, pre_expand, post_policy, addressing;
+  uint32_t probe_both, pad_;
 };
 
 struct ReqDesc {  // written by the host
@@ -1452,11 +1456,20 @@ __device__ void run_chunk(ReqState *r, const ReqDesc &d, uint32_t ph, uint64_t c
       a.stash_cap = d.t.stash_cap;
       a.pending_cap = d.t.pending_cap;
       const OpsView view = read_view(d.t.ctl, d.t.stash_cap, d.t.pending_cap);
-      switch (d.mode) {
-        case OP_INSERT: ops_tile<S, OP_INSERT>(a, view, c, sh); break;
-        case OP_DELETE: ops_tile<S, OP_DELETE>(a, view, c, sh); break;
-        case OP_LOOKUP: ops_tile<S, OP_LOOKUP>(a, view, c, sh); break;
-        default: ops_tile<S, OP_MIXED>(a, view, c, sh); break;
+      if (d.t.probe_both && S == 16) {
+        switch (d.mode) {
+          case OP_INSERT: ops_tile<S, OP_INSERT, true>(a, view, c, sh); break;
+          case OP_DELETE: ops_tile<S, OP_DELETE, true>(a, view, c, sh); break;
+          case OP_LOOKUP: ops_tile<S, OP_LOOKUP, true>(a, view, c, sh); break;
+          default: ops_tile<S, OP_MIXED, true>(a, view, c, sh); break;
+        }
+      } else {
+        switch (d.mode) {
+          case OP_INSERT: ops_tile<S, OP_INSERT, false>(a, view, c, sh); break;
+          case OP_DELETE: ops_tile<S, OP_DELETE, false>(a, view, c, sh); break;
+          case OP_LOOKUP: ops_tile<S, OP_LOOKUP, false>(a, view, c, sh); break;
+          default: ops_tile<S, OP_MIXED, false>(a, view, c, sh); break;
+        }
       }
       break;
     }
@@ -1671,19 +1684,19 @@ static hive_status ensure_scratch(hive_table *h, uint64_t n, bool need_dd, hipSt
   return HIVE_OK;
 }
 
-template <int S, uint32_t MODE>
+template <int S, uint32_t MODE, bool BOTH>
 static void launch_ops(const OpsArgs &a, hipStream_t st) {
   const uint64_t blocks = (a.n + BLOCK - 1) / BLOCK;
-  hipLaunchKernelGGL((ops_kernel<S, MODE>), dim3((unsigned)blocks), dim3(BLOCK), 0, st, a);
+  hipLaunchKernelGGL((ops_kernel<S, MODE, BOTH>), dim3((unsigned)blocks), dim3(BLOCK), 0, st, a);
 }
 
-template <int S>
+template <int S, bool BOTH>
 static void launch_ops_mode(uint32_t mode, const OpsArgs &a, hipStream_t st) {
   switch (mode) {
-    case OP_INSERT: launch_ops<S, OP_INSERT>(a, st); break;
-    case OP_DELETE: launch_ops<S, OP_DELETE>(a, st); break;
-    case OP_LOOKUP: launch_ops<S, OP_LOOKUP>(a, st); break;
-    default: launch_ops<S, OP_MIXED>(a, st); break;
+    case OP_INSERT: launch_ops<S, OP_INSERT, BOTH>(a, st); break;
+    case OP_DELETE: launch_ops<S, OP_DELETE, BOTH>(a, st); break;
+    case OP_LOOKUP: launch_ops<S, OP_LOOKUP, BOTH>(a, st); break;
+    default: launch_ops<S, OP_MIXED, BOTH>(a, st); break;
   }
 }
 
@@ -1821,9 +1834,14 @@ static hive_status run_batch(hive_t h, uint32_t mode, const uint8_t *d_ops, cons
     if ((s = resize_sequence(h, mode == OP_MIXED ? PLAN_PRE_MIXED : PLAN_PRE, n, d_ops, st)) != HIVE_OK) return s;
   }
   switch (h->S) {
-    case 16: launch_ops_mode<16>(mode, a, st); break;
-    case 32: launch_ops_mode<32>(mode, a, st); break;
-    default: launch_ops_mode<64>(mode, a, st); break;
+    case 16:
+      if (h->cfg.probe_both)
+        launch_ops_mode<16, true>(mode, a, st);
+      else
+        launch_ops_mode<16, false>(mode, a, st);
+      break;
+    case 32: launch_ops_mode<32, false>(mode, a, st); break;
+    default: launch_ops_mode<64, false>(mode, a, st); break;
   }
   if ((s = launch_check()) != HIVE_OK) return s;
   if (mode == OP_INSERT || mode == OP_MIXED) {
@@ -2166,7 +2184,7 @@ hive_status hive_drain_submit(hive_drain_t d, hive_t h, const hive_batch_desc *b
   r.t = TableDesc{h->d_buckets, h->d_hint, h->d_stash, h->d_pending, h->d_ctl, h->d_wl, h->d_dd, h->stash_cap,
                   h->pending_cap, hint_words(h->max_buckets), h->S, h->cfg.max_evictions, h->cfg.resize_k,
                   h->cfg.lf_expand_pct, h->cfg.lf_contract_pct, h->cfg.pre_expand, h->cfg.post_policy,
-                  h->cfg.addressing};
+                  h->cfg.addressing, h->cfg.probe_both, 0};
   r.ops = b->d_ops;
   r.keys = b->d_keys;
   r.vals = b->d_vals;

@@ -45,6 +45,8 @@ class hive_config(ctypes.Structure):
         ("post_policy", ctypes.c_uint32),
         ("max_buckets", ctypes.c_uint64),
         ("max_batch", ctypes.c_uint64),
+        ("probe_both", ctypes.c_uint32),
+        ("reserved_", ctypes.c_uint32),
     ]
 
 

@@ -60,13 +60,13 @@ def check_placement(table_dump, where, S, n_buckets, addressing=oracle.ADDR_FIXE
     assert not bad.any(), f"{bad.sum()} entries outside their candidate buckets"
 
 
-def run_tiny(H, S, seed=1, n_keys=1 << 16, n_buckets=None):
+def run_tiny(H, S, seed=1, n_keys=1 << 16, n_buckets=None, probe_both=0):
     """The tiny configuration: insert all, look up (50% present), delete a
     random half, look up again; compared with the oracle step by step."""
     w = wl.bulk_workload(seed, n_keys)
     n_buckets = n_buckets or (2 * n_keys) // S  # 50% load
-    case(f"tiny S={S} keys={n_keys} buckets={n_buckets}")
-    t = H.Table(n_buckets, slots_per_bucket=S, max_evictions=8, stash_capacity=1024)
+    case(f"tiny S={S} keys={n_keys} buckets={n_buckets} probe_both={probe_both}")
+    t = H.Table(n_buckets, slots_per_bucket=S, max_evictions=8, stash_capacity=1024, probe_both=probe_both)
     o = oracle.O2(S, 8, 1024, oracle.ADDR_FIXED, n_buckets)
     t.insert(dev(w["ins_keys"]), dev(w["ins_vals"]), flags=H.HIVE_UNIQUE)
     o.insert(w["ins_keys"], w["ins_vals"])
@@ -87,8 +87,9 @@ def run_tiny(H, S, seed=1, n_keys=1 << 16, n_buckets=None):
     t.close()
 
 
-def test_tiny_config_s16(H):
-    run_tiny(H, 16)
+@pytest.mark.parametrize("probe_both", [0, 1])
+def test_tiny_config_s16(H, probe_both):
+    run_tiny(H, 16, probe_both=probe_both)
 
 
 @pytest.mark.parametrize("S", [32, 64])
@@ -220,7 +221,8 @@ def test_eviction_stash_pending_heavy(H, E, stash, lf):
     t.close()
 
 
-def test_mixed_batches_zipf(H):
+@pytest.mark.parametrize("probe_both", [0, 1])
+def test_mixed_batches_zipf(H, probe_both):
     """Prefill, then mixed batches (40% insert with repeats, 40% delete, 20%
     lookup, Zipf keys, per-type disjoint): per-batch outputs and the final
     set equal the dictionary's."""
@@ -228,7 +230,7 @@ def test_mixed_batches_zipf(H):
     universe = 1 << 16
     ks = wl.KeyStream(3)
     pre = ks.keys(wl.DomainPerm(33, universe).sample(int(0.8 * S * nb * 0.9)))
-    t = H.Table(nb, stash_capacity=2048)
+    t = H.Table(nb, stash_capacity=2048, probe_both=probe_both)
     o = oracle.O1()
     t.insert(dev(pre), dev(wl.values_for(pre)), flags=H.HIVE_UNIQUE)
     o.insert(pre, wl.values_for(pre))
@@ -244,19 +246,20 @@ def test_mixed_batches_zipf(H):
     t.close()
 
 
-def test_bulk_95pct_reduced(H):
+@pytest.mark.parametrize("probe_both", [0, 1])
+def test_bulk_95pct_reduced(H, probe_both):
     """The bulk configuration at 2^20 keys: FIXED table at 95% load, 50%-hit
     queries, delete half, re-query; exact expected outputs come from the
     generator (present iff inserted and not deleted, value = value(key))."""
-    run_bulk(H, 1 << 20, seed=2)
+    run_bulk(H, 1 << 20, seed=2, probe_both=probe_both)
 
 
-def run_bulk(H, n_keys, seed):
+def run_bulk(H, n_keys, seed, probe_both=0):
     S = 16
     nb = int(np.ceil(n_keys / (0.95 * S)))
-    case(f"bulk n={n_keys} buckets={nb}")
+    case(f"bulk n={n_keys} buckets={nb} probe_both={probe_both}")
     w = wl.bulk_workload(seed, n_keys)
-    t = H.Table(nb)
+    t = H.Table(nb, probe_both=probe_both)
     t.insert(dev(w["ins_keys"]), dev(w["ins_vals"]), flags=H.HIVE_UNIQUE)
     st = t.stats()
     assert st["live"] == n_keys and st["status"] == H.HIVE_OK, st
