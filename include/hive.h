@@ -84,7 +84,10 @@ typedef struct {
   uint32_t probe_both;        /* S = 16: 1 = lookups and deletes load both
                                  candidate buckets in one round (one memory
                                  round trip fewer, more bytes); inserts always
-                                 do.  0 = second bucket only after a miss */
+                                 do.  0 = second bucket only after a miss.
+                                 Plain launches only: the persistent
+                                 executor always uses 0.  Results are the
+                                 same either way */
   uint32_t reserved_;
 } hive_config;
 

@@ -159,7 +159,7 @@ def tune_executor_blocks(n_batches: int = 256, batch: int = 1 << 12, reps: int =
     return {"blocks_per_cu": int(best), "scores_mops": {str(k): round(x, 1) for k, x in scores.items()}}
 
 
-def tune(workload: str = "all", reps: int = 3, save: bool = True) -> dict:
+def tune(workload: str = "all", reps: int = 10, save: bool = True) -> dict:
     """Run the tuners a workload needs and cache the winners."""
     t0 = time.time()
     res = {}

@@ -1097,7 +1097,6 @@ struct TableDesc {
   uint64_t *dd;
   uint64_t stash_cap, pending_cap, hint_words;
   uint32_t S, max_evictions, K, lf_expand_pct, lf_contract_pct, pre_expand, post_policy, addressing;
-  uint32_t probe_both, pad_;
 };
 
 struct ReqDesc {  // written by the host
@@ -1456,20 +1455,13 @@ __device__ void run_chunk(ReqState *r, const ReqDesc &d, uint32_t ph, uint64_t c
       a.stash_cap = d.t.stash_cap;
       a.pending_cap = d.t.pending_cap;
       const OpsView view = read_view(d.t.ctl, d.t.stash_cap, d.t.pending_cap);
-      if (d.t.probe_both && S == 16) {
-        switch (d.mode) {
-          case OP_INSERT: ops_tile<S, OP_INSERT, true>(a, view, c, sh); break;
-          case OP_DELETE: ops_tile<S, OP_DELETE, true>(a, view, c, sh); break;
-          case OP_LOOKUP: ops_tile<S, OP_LOOKUP, true>(a, view, c, sh); break;
-          default: ops_tile<S, OP_MIXED, true>(a, view, c, sh); break;
-        }
-      } else {
-        switch (d.mode) {
-          case OP_INSERT: ops_tile<S, OP_INSERT, false>(a, view, c, sh); break;
-          case OP_DELETE: ops_tile<S, OP_DELETE, false>(a, view, c, sh); break;
-          case OP_LOOKUP: ops_tile<S, OP_LOOKUP, false>(a, view, c, sh); break;
-          default: ops_tile<S, OP_MIXED, false>(a, view, c, sh); break;
-        }
+      // one probe variant only (the second candidate after a miss): a
+      // second inlined copy would cost the resident grid occupancy
+      switch (d.mode) {
+        case OP_INSERT: ops_tile<S, OP_INSERT, false>(a, view, c, sh); break;
+        case OP_DELETE: ops_tile<S, OP_DELETE, false>(a, view, c, sh); break;
+        case OP_LOOKUP: ops_tile<S, OP_LOOKUP, false>(a, view, c, sh); break;
+        default: ops_tile<S, OP_MIXED, false>(a, view, c, sh); break;
       }
       break;
     }
@@ -2184,7 +2176,7 @@ hive_status hive_drain_submit(hive_drain_t d, hive_t h, const hive_batch_desc *b
   r.t = TableDesc{h->d_buckets, h->d_hint, h->d_stash, h->d_pending, h->d_ctl, h->d_wl, h->d_dd, h->stash_cap,
                   h->pending_cap, hint_words(h->max_buckets), h->S, h->cfg.max_evictions, h->cfg.resize_k,
                   h->cfg.lf_expand_pct, h->cfg.lf_contract_pct, h->cfg.pre_expand, h->cfg.post_policy,
-                  h->cfg.addressing, h->cfg.probe_both, 0};
+                  h->cfg.addressing};
   r.ops = b->d_ops;
   r.keys = b->d_keys;
   r.vals = b->d_vals;
