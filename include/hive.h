@@ -212,14 +212,19 @@ typedef struct {
 /* Create an executor for tables of `slots_per_bucket` slots.  It holds a
  * ring of `ring_capacity` batches and up to `max_tables` tables;
  * `blocks_per_cu` = resident blocks per compute unit (0 = as many as fit);
- * `idle_limit` = idle polls after which a resident block gives up (0 = the
- * default, tens of seconds), a watchdog in case the host never stops it. */
+ * `idle_timeout_us` = microseconds during which the queue makes no progress
+ * (nothing new ingested, nothing retired) after which a resident block gives
+ * up (0 = the default, 30 s), a watchdog in case the host never stops it. */
 hive_status hive_drain_create(uint32_t slots_per_bucket, uint32_t blocks_per_cu, uint64_t ring_capacity,
-                              uint32_t max_tables, uint64_t idle_limit, hive_drain_t *out);
+                              uint32_t max_tables, uint64_t idle_timeout_us, hive_drain_t *out);
 
 /* Append a batch (host only; no HIP call).  *ticket identifies it.  Returns
- * HIVE_ERR_BUDGET when the ring is full or a running executor would need
- * more scratch than the table has (create tables with max_batch). */
+ * HIVE_ERR_BUDGET when the ring is full or max_tables tables are already
+ * registered (retry after completions), and HIVE_ERR_ARG when the executor
+ * is running and the batch would need more scratch than the table holds:
+ * inserts and mixed batches need a worklist of n entries, batches without
+ * HIVE_UNIQUE a dedupe set (create tables with max_batch to preallocate);
+ * a stopped executor grows the scratch instead. */
 hive_status hive_drain_submit(hive_drain_t d, hive_t table, const hive_batch_desc *b, uint64_t *ticket);
 
 /* Launch the grid.  resident = 0: on `stream`; it exits once every batch

@@ -1133,7 +1133,7 @@ struct DrainQueue {
   uint64_t *host_live;        // pinned: per ring slot, the table's live count after the batch
   uint64_t *table_next;       // per table slot: sequence number allowed to run
   uint64_t cap;
-  uint64_t idle_limit;        // idle polls before a block gives up (watchdog)
+  uint64_t idle_ticks;        // device wall-clock ticks without queue progress before a block gives up
   uint64_t ingested;
   uint64_t head;
   uint64_t completed;
@@ -1477,23 +1477,33 @@ __global__ __launch_bounds__(BLOCK) void drain_worker_kernel(DrainQueue *q) {
   __shared__ ReqDesc desc;
   __shared__ uint64_t s_req, s_chunk, s_nch;
   __shared__ uint32_t s_phase, s_cmd;
-  uint64_t idle = 0;
-  const uint64_t idle_limit = ld_ctl(&q->idle_limit);
+  // watchdog: polls without any progress of the queue as a whole (nothing
+  // newly ingested, nothing retired), so blocks that merely find no chunk
+  // while others work do not give up
+  uint64_t seen_ing = ~0ull, seen_head = ~0ull;
+  uint64_t idle_since = wall_clock64();
+  const uint64_t idle_ticks = ld_ctl(&q->idle_ticks);
   for (;;) {
     if (threadIdx.x == 0) s_cmd = find_work(q, &s_req, &s_phase, &s_chunk, &s_nch);
     __syncthreads();
     const uint32_t cmd = s_cmd;
     if (cmd == 2) break;
     if (cmd == 1) {
-      if (++idle > idle_limit) {
+      const uint64_t ing = ld_ctl(&q->ingested), head = ld_ctl(&q->head);
+      const uint64_t now = wall_clock64();
+      if (ing != seen_ing || head != seen_head) {
+        seen_ing = ing;
+        seen_head = head;
+        idle_since = now;
+      }
+      if (now - idle_since > idle_ticks) {
         if (threadIdx.x == 0) atomicOr(&q->error, 1u);
         break;
       }
-      __builtin_amdgcn_s_sleep(32);
+      __builtin_amdgcn_s_sleep(7);  // about 450 clocks
       __syncthreads();
       continue;
     }
-    idle = 0;
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     ReqState *r = q->req + s_req % q->cap;
     load_desc(&desc, &r->d);
@@ -1793,7 +1803,9 @@ static hive_status run_batch(hive_t h, uint32_t mode, const uint8_t *d_ops, cons
   h->last = st;
   if (n == 0) return HIVE_OK;
   const bool dedupe = !(flags & HIVE_UNIQUE) && mode != OP_LOOKUP;
-  hive_status s = ensure_scratch(h, n, dedupe, st);
+  // only inserts reach the eviction worklist
+  const uint64_t wl_need = (mode == OP_INSERT || mode == OP_MIXED) ? n : 0;
+  hive_status s = ensure_scratch(h, wl_need, dedupe, st);
   if (s != HIVE_OK) return s;
   OpsArgs a{};
   a.buckets = h->d_buckets;
@@ -2065,7 +2077,7 @@ hive_status hive_bucket_of(hive_t h, uint32_t mixed_hash, uint64_t *bucket) {
 
 
 hive_status hive_drain_create(uint32_t slots_per_bucket, uint32_t blocks_per_cu, uint64_t ring_capacity,
-                              uint32_t max_tables, uint64_t idle_limit, hive_drain_t *out) {
+                              uint32_t max_tables, uint64_t idle_timeout_us, hive_drain_t *out) {
   if (!out) return HIVE_ERR_ARG;
   *out = nullptr;
   if (slots_per_bucket != 16 && slots_per_bucket != 32 && slots_per_bucket != 64) return HIVE_ERR_ARG;
@@ -2113,7 +2125,18 @@ hive_status hive_drain_create(uint32_t slots_per_bucket, uint32_t blocks_per_cu,
   q.req = d->d_req;
   q.cap = ring_capacity;
   q.table_next = d->d_table_next;
-  q.idle_limit = idle_limit ? idle_limit : (1ull << 25);
+  {
+    // the watchdog runs on the constant-rate device clock (rate in kHz)
+    int dev = 0, khz = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) !=
+                                                 hipSuccess || khz <= 0) {
+      (void)hipGetLastError();
+      free_drain(d);
+      return HIVE_ERR_HIP;
+    }
+    const uint64_t us = idle_timeout_us ? idle_timeout_us : 30000000ull;
+    q.idle_ticks = us > (~0ull / (uint64_t)khz) ? ~0ull : us * (uint64_t)khz / 1000;
+  }
   void *dp = nullptr;
   if (hipHostGetDevicePointer(&dp, d->h_ring, 0) != hipSuccess) goto fail;
   q.host_ring = (const ReqDesc *)dp;
@@ -2165,10 +2188,12 @@ hive_status hive_drain_submit(hive_drain_t d, hive_t h, const hive_batch_desc *b
     dd_size = 16;
     while (dd_size < 2 * b->n) dd_size <<= 1;
   }
-  // scratch is never reallocated under a running executor
-  if (b->n > h->wl_cap || dd_size > h->dd_cap) {
-    if (d->running) return HIVE_ERR_BUDGET;
-    hive_status s = ensure_scratch(h, b->n, dedupe, h->last);
+  // scratch is never reallocated under a running executor; only inserts
+  // reach the eviction worklist
+  const uint64_t wl_need = (b->op_mode == HIVE_OP_INSERT || b->op_mode == HIVE_OP_MIXED) ? b->n : 0;
+  if (wl_need > h->wl_cap || dd_size > h->dd_cap) {
+    if (d->running) return HIVE_ERR_ARG;
+    hive_status s = ensure_scratch(h, wl_need, dedupe, h->last);
     if (s != HIVE_OK) return s;
   }
   ReqDesc r;

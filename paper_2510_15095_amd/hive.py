@@ -272,9 +272,9 @@ def hive_fastmod(a: int, magic: int, d: int) -> int:
 
 
 def hive_drain_create(slots_per_bucket: int = 16, blocks_per_cu: int = 0, ring_capacity: int = 1024,
-                      max_tables: int = 64, idle_limit: int = 0) -> ctypes.c_void_p:
+                      max_tables: int = 64, idle_timeout_us: int = 0) -> ctypes.c_void_p:
     d = ctypes.c_void_p()
-    _check(_lib.hive_drain_create(slots_per_bucket, blocks_per_cu, ring_capacity, max_tables, idle_limit,
+    _check(_lib.hive_drain_create(slots_per_bucket, blocks_per_cu, ring_capacity, max_tables, idle_timeout_us,
                                   ctypes.byref(d)), "hive_drain_create")
     return d
 

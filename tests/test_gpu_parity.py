@@ -465,7 +465,7 @@ def test_drain_matches_plain_and_oracle_mixed(H):
     for t in (plain, drained):
         t.insert(dev(pre), dev(wl.values_for(pre)), flags=H.HIVE_UNIQUE)
     o.insert(pre, wl.values_for(pre))
-    d = H.hive_drain_create(16, 0, 64, 8, 1 << 21)
+    d = H.hive_drain_create(16, 0, 64, 8, 10_000_000)
     outs, tickets, keep = [], [], []
     for mb in batches:
         o_, k_, v_ = dev(mb["ops"]), dev(mb["keys"]), dev(mb["vals"])
@@ -498,7 +498,7 @@ def test_drain_multi_table_linear_policies(H):
     tabs = {i: linear_table(H, nb0, mb_, 4) for i in names}
     refs = {i: linear_table(H, nb0, mb_, 4) for i in names}
     o1 = {i: oracle.O1() for i in names}
-    d = H.hive_drain_create(16, 0, 128, 8, 1 << 21)
+    d = H.hive_drain_create(16, 0, 128, 8, 10_000_000)
     ks = {i: wl.KeyStream(70 + i) for i in names}
     plan = []
     for step in range(5):
@@ -551,7 +551,7 @@ def test_drain_resident_incremental_and_backpressure(H):
     import torch
     t = H.Table(1024, max_batch=4096)
     o = oracle.O1()
-    d = H.hive_drain_create(16, 0, 4, 4, 1 << 22)
+    d = H.hive_drain_create(16, 0, 4, 4, 10_000_000)
     torch.cuda.synchronize()
     side = torch.cuda.Stream()  # the resident grid must not block torch's own stream
     H.hive_drain_launch(d, 1, side)
@@ -581,12 +581,18 @@ def test_drain_resident_incremental_and_backpressure(H):
             torch.cuda.current_stream().synchronize()
             keep += [q, vo, fo]
             while (lt := H.hive_drain_submit(d, t.h, H.HIVE_OP_LOOKUP, q, None, None, vo, fo)) is None:
+                assert time.time() < deadline, "lookup batch never admitted"
                 time.sleep(0.0005)
             while not H.hive_drain_poll(d, lt):
                 assert time.time() < deadline, "lookup batch never completed"
                 time.sleep(0.0002)
             ov, of = o.lookup(ks.range(0, 13000))
             assert np.array_equal(host(fo), of) and np.array_equal(host(vo), ov)
+    # an insert batch larger than the table's preallocated worklist is
+    # refused on the host while the grid runs (its scratch cannot grow)
+    big = dev(ks.range(20000, 25000))
+    with pytest.raises(H.HiveError):
+        H.hive_drain_submit(d, t.h, H.HIVE_OP_INSERT, big, big, flags=H.HIVE_UNIQUE)
     H.hive_drain_stop(d, side)
     assert np.array_equal(t.dump(), o.dump())
     H.hive_drain_destroy(d)
