@@ -52,6 +52,9 @@ def parse():
     ap.add_argument("--autotune", action="store_true", help="run the autotuner first and use its picks")
     ap.add_argument("--probe-both", type=int, default=-1,
                     help="bulk: 1 = lookups/deletes probe both candidates in one round (-1: autotuned, else 0)")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="bulk: first run one plain device copy of this many MiB (a known-size dispatch that "
+                         "scales HBM byte counters read by a profiler)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-log2", type=int, default=22)
     return ap.parse_args()
@@ -350,6 +353,14 @@ def run_bulk(args):
     qi = w["query_idx"]
     n_present2 = int(((qi < n) & ~deleted[np.minimum(qi, n - 1)]).sum())
     del w
+
+    if args.copy_calibration_mib:
+        src = torch.empty(args.copy_calibration_mib << 18, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     phases = ("clear", "insert", "lookup", "delete", "lookup2")
 

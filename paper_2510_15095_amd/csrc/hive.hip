@@ -152,10 +152,11 @@ __device__ __forceinline__ bool dedupe_winner(const uint64_t *dd, uint64_t mask,
 // list[t] (t itself when list is null).  Each 16-lane group loads one bucket
 // per wave-wide load and publishes, through LDS and indexed by the owning
 // lane, the match mask, the empty-slot mask and the word of the lowest
-// matching slot.  All operands are read from LDS first and all loads of a
-// chunk are issued before any is consumed; idle group slots of the last
-// chunk re-load the round's last bucket and their result is ignored, so the
-// loads carry no control flow.
+// matching slot.  All loads of a chunk are issued before any is consumed.
+// bkts[] holds 64 entries: entries from `count` on repeat the round's last
+// bucket (the caller pads them), so idle group slots re-load a line that is
+// loaded anyway, their result is ignored, and the loads need neither
+// control flow nor clamped indices.
 template <int S>
 __device__ __forceinline__ void probe_round(const uint64_t *__restrict__ buckets, const uint32_t *keys,
                                             const uint32_t *bkts, const uint8_t *list, int count,
@@ -166,15 +167,15 @@ __device__ __forceinline__ void probe_round(const uint64_t *__restrict__ buckets
   for (int base = 0; base < count; base += T::OPS_PER_CHUNK) {
     uint64_t w[T::CH];
 #pragma unroll
-    for (int j = 0; j < T::CH; ++j) {
-      const int t = min(base + j * T::G + g, count - 1);
-      w[j] = buckets[(uint64_t)bkts[t] * S + sl];
-    }
+    for (int j = 0; j < T::CH; ++j) w[j] = buckets[(uint64_t)bkts[base + j * T::G + g] * S + sl];
+    // keep the operands of the consume loop from being read (and held in
+    // registers) while the loads are in flight
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int j = 0; j < T::CH; ++j) {
       const int t = base + j * T::G + g;
       const bool mine = t < count;
-      const uint32_t ko = keys[min(t, count - 1)];
+      const uint32_t ko = keys[t];
       const uint64_t mm = ballot(mine && ko != 0u && key_of(w[j]) == ko);
       const uint64_t ee = ballot(w[j] == EMPTY);
       const Mask gm = (Mask)((mm >> (g * S)) & T::FULL);
@@ -204,15 +205,12 @@ __device__ __forceinline__ void probe_round_pair(const uint64_t *__restrict__ bu
   using T = Traits<S>;
   using Mask = typename T::Mask;
   static_assert(S == 16, "the fused round covers one chunk per candidate");
-  const int last2 = count2 > 0 ? count2 - 1 : 0;
   uint64_t wa[T::CH], wb[T::CH];
 #pragma unroll
   for (int j = 0; j < T::CH; ++j) wa[j] = buckets[(uint64_t)bkts1[j * T::G + g] * S + sl];
 #pragma unroll
-  for (int j = 0; j < T::CH; ++j) {
-    const uint32_t b = count2 > 0 ? bkts2[min(j * T::G + g, last2)] : bkts1[j * T::G + g];
-    wb[j] = buckets[(uint64_t)b * S + sl];
-  }
+  for (int j = 0; j < T::CH; ++j) wb[j] = buckets[(uint64_t)bkts2[j * T::G + g] * S + sl];
+  __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
   for (int j = 0; j < T::CH; ++j) {
     const int t = j * T::G + g;
@@ -267,6 +265,23 @@ __device__ __forceinline__ uint64_t *overflow_find(uint64_t *stash, uint64_t n_s
     }
   }
   return nullptr;
+}
+
+// The second-candidate round's operand list: the operations that need it,
+// compacted in lane order (key, bucket, owning lane), and the rest of the 64
+// entries padded with the last listed bucket (with lane 0's first bucket when
+// the list is empty).
+__device__ __forceinline__ void compact_second(bool need2, uint64_t need2_mask, int n2, uint32_t k, uint32_t c2,
+                                               uint32_t c1, int lane, uint32_t *k2, uint32_t *b2, uint8_t *list) {
+  const uint32_t pad = n2 > 0 ? (uint32_t)__builtin_amdgcn_readlane((int)c2, 63 - __builtin_clzll(need2_mask))
+                              : (uint32_t)__builtin_amdgcn_readlane((int)c1, 0);
+  if (need2) {
+    const uint32_t r = rank_below(need2_mask);
+    k2[r] = k;
+    b2[r] = c2;
+    list[r] = (uint8_t)lane;
+  }
+  if (lane >= n2) b2[lane] = pad;
 }
 
 // ---------------------------------------------------------------------------
@@ -354,12 +369,7 @@ __device__ __forceinline__ void ops_tile(const OpsArgs &a, const OpsView &view, 
     need2 = work && c2 != c1;
     const uint64_t need2_mask = ballot(need2);
     const int n2 = __popcll(need2_mask);
-    if (need2) {
-      const uint32_t r = rank_below(need2_mask);
-      s_k2[wv][r] = k;
-      s_b2[wv][r] = c2;
-      s_list[wv][r] = (uint8_t)lane;
-    }
+    compact_second(need2, need2_mask, n2, k, c2, c1, lane, s_k2[wv], s_b2[wv], s_list[wv]);
     wave_lds_sync();
     probe_round_pair<S>(a.buckets, s_key[wv], s_b1[wv], s_m[0][wv], s_e[0][wv], s_w[0][wv], s_k2[wv], s_b2[wv],
                         s_list[wv], n2, s_m[1][wv], s_e[1][wv], s_w[1][wv], g, sl);
@@ -373,12 +383,7 @@ __device__ __forceinline__ void ops_tile(const OpsArgs &a, const OpsView &view, 
     need2 = work && m1 == 0 && c2 != c1;
     const uint64_t need2_mask = ballot(need2);
     const int n2 = __popcll(need2_mask);
-    if (need2) {
-      const uint32_t r = rank_below(need2_mask);
-      s_k2[wv][r] = k;
-      s_b2[wv][r] = c2;
-      s_list[wv][r] = (uint8_t)lane;
-    }
+    compact_second(need2, need2_mask, n2, k, c2, c1, lane, s_k2[wv], s_b2[wv], s_list[wv]);
     wave_lds_sync();
     // round 2: second candidate of the operations that missed in the first
     if (n2 > 0)
