@@ -28,10 +28,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <thread>
 #include <type_traits>
 
 #include "hive.h"
@@ -69,13 +71,92 @@ __device__ __forceinline__ uint64_t read_lane64(uint64_t x, int lane) {
   return ((uint64_t)hi << 32) | lo;
 }
 
+// Value of lane `src` of the wave, for a 64-bit word.
+__device__ __forceinline__ uint64_t shfl64(uint64_t x, int src) {
+  const int lo = __builtin_amdgcn_ds_bpermute(src << 2, (int)(uint32_t)x);
+  const int hi = __builtin_amdgcn_ds_bpermute(src << 2, (int)(uint32_t)(x >> 32));
+  return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+// Sum over the 64 lanes of a wave (every lane active); every lane gets it.
+__device__ __forceinline__ uint64_t wave_sum64(uint64_t x) {
+  const int lane = threadIdx.x & 63;
+  for (int o = 32; o > 0; o >>= 1) x += shfl64(x, lane ^ o);
+  return x;
+}
+
+// Worklist segments.  The eviction worklist is NSHARD segments of seg_cap
+// entries; tile t (256 operations, or 256 stash entries of a drain) appends
+// to segment t % NSHARD through that shard's wl_count, so appends spread
+// over NSHARD counters.  A segment receives at most 256 entries from each of
+// ceil(tiles / NSHARD) tiles, which bounds seg_cap.
+__device__ __forceinline__ uint64_t wl_append(const Ctl *c, uint64_t tile, uint64_t n) {
+  return add64(&shard_of(c, tile % NSHARD)->wl_count, n);
+}
+
+// Exclusive prefix of the segment fills, pre[0..NSHARD] (pre[NSHARD] is the
+// total); the whole block calls it, wave 0 loads and scans.
+__device__ __forceinline__ void wl_prefix(const Ctl *c, uint64_t *pre) {
+  if (threadIdx.x < NSHARD) {
+    const int lane = threadIdx.x;
+    uint64_t x = ld_ctl(&shard_of(c, lane)->wl_count);
+    for (int o = 1; o < NSHARD; o <<= 1) {
+      const uint64_t y = shfl64(x, lane >= o ? lane - o : lane);
+      if (lane >= o) x += y;
+    }
+    pre[lane + 1] = x;
+    if (lane == 0) pre[0] = 0;
+  }
+  __syncthreads();
+}
+
+// Position in the worklist of item k < pre[NSHARD] (items numbered segment
+// by segment): the last segment whose prefix is <= k holds it.
+__device__ __forceinline__ uint64_t wl_slot(const uint64_t *pre, uint64_t k, uint64_t seg_cap) {
+  int s = 0;
+  for (int step = NSHARD / 2; step > 0; step >>= 1)
+    if (pre[s + step] <= k) s += step;
+  return (uint64_t)s * seg_cap + (k - pre[s]);
+}
+
+// Fold the shards into the totals of Ctl line 1 (one full wave; nothing else
+// may update this table's shards meanwhile).  With wl_done the worklist's
+// items are counted and its segments emptied.  Returns the worklist size.
+__device__ __forceinline__ uint64_t fold_shards_wave(Ctl *c, bool wl_done) {
+  const int lane = threadIdx.x & 63;
+  Shard *sh = shard_of(c, lane);
+  uint64_t v[4] = {ld_ctl(&sh->live), ld_ctl(&sh->evictions), ld_ctl(&sh->full_chains), ld_ctl(&sh->invalid_keys)};
+  const uint64_t wl = ld_ctl(&sh->wl_count);
+  if (v[0]) __hip_atomic_store(&sh->live, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (v[1]) __hip_atomic_store(&sh->evictions, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (v[2]) __hip_atomic_store(&sh->full_chains, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (v[3]) __hip_atomic_store(&sh->invalid_keys, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (wl_done && wl) __hip_atomic_store(&sh->wl_count, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (int f = 0; f < 4; ++f) v[f] = wave_sum64(v[f]);
+  const uint64_t total_wl = wave_sum64(wl);
+  if (lane == 0) {
+    if (v[0]) add64(&c->live, v[0]);
+    if (v[1]) add64(&c->evictions, v[1]);
+    if (v[2]) add64(&c->full_chains, v[2]);
+    if (v[3]) add64(&c->invalid_keys, v[3]);
+    if (wl_done && total_wl) add64(&c->evict_items, total_wl);
+  }
+  return total_wl;
+}
+
+// After a batch or a resize call (one wave of 64 threads).
+__global__ __launch_bounds__(64) void finish_kernel(Ctl *c) {
+  (void)fold_shards_wave(c, true);
+}
+
 struct OpsArgs {
   uint64_t *buckets;
   uint32_t *hint;
   uint64_t *stash;
   uint64_t *pending;
   Ctl *ctl;
-  uint64_t *wl;
+  uint64_t *wl;        // eviction worklist: NSHARD segments of wl_seg_cap entries
+  uint64_t wl_seg_cap;
   const uint64_t *dd;  // dedupe set, or null
   uint64_t dd_mask;
   const uint8_t *ops;
@@ -479,20 +560,22 @@ __device__ __forceinline__ void ops_tile(const OpsArgs &a, const OpsView &view, 
     }
   }
 
-  // eviction worklist: one atomic per wave
+  // eviction worklist: one atomic per wave, on the tile's segment counter
   const uint64_t wl_mask = ballot(to_wl);
   if (wl_mask) {
     const int leader = __builtin_ctzll(wl_mask);
     uint64_t base = 0;
-    if (lane == leader) base = add64(&a.ctl->wl_count, (uint64_t)__popcll(wl_mask));
+    if (lane == leader) base = wl_append(a.ctl, tile, (uint64_t)__popcll(wl_mask));
     base = read_lane64(base, leader);
-    if (to_wl) a.wl[base + rank_below(wl_mask)] = kv;
+    if (to_wl) a.wl[(tile % NSHARD) * a.wl_seg_cap + base + rank_below(wl_mask)] = kv;
   }
+  // key count and reserved keys: one atomic per wave on the wave's shard
   const uint64_t up = ballot(dl > 0), down = ballot(dl < 0), bad = ballot(active && !valid);
   if (lane == 0) {
+    Shard *sh = shard_of(a.ctl, (tile * WAVES + wv) % NSHARD);
     const int64_t d = (int64_t)__popcll(up) - (int64_t)__popcll(down);
-    if (d != 0) add64(&a.ctl->live, (uint64_t)d);
-    if (bad) add64(&a.ctl->invalid_keys, (uint64_t)__popcll(bad));
+    if (d != 0) add64(&sh->live, (uint64_t)d);
+    if (bad) add64(&sh->invalid_keys, (uint64_t)__popcll(bad));
   }
   if (active) {
     if (MODE == OP_LOOKUP || MODE == OP_MIXED) {
@@ -522,6 +605,7 @@ struct EvictArgs {
   uint64_t *pending;
   Ctl *ctl;
   const uint64_t *wl;
+  uint64_t wl_seg_cap;
   uint64_t stash_cap;
   uint64_t pending_cap;
   uint32_t max_evictions;
@@ -557,13 +641,6 @@ __device__ __forceinline__ void overflow_push(const EvictArgs &a, const Geo &geo
   set_hint(a.hint, address(geo, bithash2(k)));
 }
 
-// Value of lane `src` of the wave, for a 64-bit word.
-__device__ __forceinline__ uint64_t shfl64(uint64_t x, int src) {
-  const int lo = __builtin_amdgcn_ds_bpermute(src << 2, (int)(uint32_t)x);
-  const int hi = __builtin_amdgcn_ds_bpermute(src << 2, (int)(uint32_t)(x >> 32));
-  return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
-}
-
 // Claim-then-commit by one 16-lane group (WABC): `free_mask` holds the
 // group's view of the bucket's EMPTY slots; the lowest one is claimed with
 // one CAS by its lane, and a failed CAS (the view was stale) drops that slot
@@ -591,11 +668,11 @@ __device__ __forceinline__ bool group_claim(uint64_t *bkt, typename Traits<S>::M
 // An item still in hand after max_evictions displacements goes to the stash
 // ring, or to the pending list when the ring is full.
 template <int S>
-__device__ __forceinline__ void evict_item(const EvictArgs &a, const Geo &geo, uint64_t t, int g, int sl,
+__device__ __forceinline__ void evict_item(const EvictArgs &a, const Geo &geo, uint64_t pos, int g, int sl,
                                            uint64_t &n_evict, uint64_t &n_full) {
   using T = Traits<S>;
   using Mask = typename T::Mask;
-  uint64_t kv = a.wl[t];
+  uint64_t kv = a.wl[pos];
   const uint32_t c1 = address(geo, bithash1(key_of(kv))), c2 = address(geo, bithash2(key_of(kv)));
   // step 2 with fresh loads (fresh: other items of this phase change buckets)
   const uint64_t w1 = load_fresh(a.buckets + (uint64_t)c1 * S + sl);
@@ -647,9 +724,16 @@ __device__ __forceinline__ void evict_item(const EvictArgs &a, const Geo &geo, u
   }
 }
 
-__device__ __forceinline__ void evict_counters(const EvictArgs &a, uint64_t n_evict, uint64_t n_full, int sl) {
-  if (n_evict && sl == 0) add64(&a.ctl->evictions, n_evict);
-  if (n_full) add64(&a.ctl->full_chains, n_full);
+// Chain statistics of a wave (per group, held by its lane 0) added to the
+// wave's shard.  Every lane of the wave calls it.
+__device__ __forceinline__ void evict_counters(const EvictArgs &a, uint64_t unit, uint64_t n_evict, uint64_t n_full,
+                                               int sl) {
+  const uint64_t e = wave_sum64(sl == 0 ? n_evict : 0), f = wave_sum64(n_full);
+  if ((threadIdx.x & 63) == 0 && (e | f)) {
+    Shard *sh = shard_of(a.ctl, unit % NSHARD);
+    if (e) add64(&sh->evictions, e);
+    if (f) add64(&sh->full_chains, f);
+  }
 }
 
 // P3: items whose two buckets were full in P1 (or stash entries re-placed
@@ -659,28 +743,28 @@ __device__ __forceinline__ void evict_counters(const EvictArgs &a, uint64_t n_ev
 // displaces a victim by CAS and carries the victim to its alternate bucket.
 // An item still in hand after max_evictions displacements goes to the stash
 // ring, or to the pending list when the ring is full.
+// The worklist is emptied afterwards by finish_kernel (it also counts the
+// items), so this kernel takes no ticket.
 template <int S>
 __global__ __launch_bounds__(BLOCK) void evict_kernel(EvictArgs a) {
   using T = Traits<S>;
+  __shared__ uint64_t pre[NSHARD + 1];
+  wl_prefix(a.ctl, pre);
+  const uint64_t cnt = pre[NSHARD];
+  if (cnt == 0) return;  // same in every block
   const Geo geo = read_geo(a.ctl);
-  const uint64_t cnt = a.ctl->wl_count;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = lane / S, sl = lane % S;
   const uint64_t groups = (uint64_t)gridDim.x * WAVES * T::G;
   uint64_t n_evict = 0, n_full = 0;
-  for (uint64_t t = ((uint64_t)blockIdx.x * WAVES + wv) * T::G + g; t < cnt; t += groups)
-    evict_item<S>(a, geo, t, g, sl, n_evict, n_full);
-  evict_counters(a, n_evict, n_full, sl);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    if (blockIdx.x == 0 && cnt) add64(&a.ctl->evict_items, cnt);
-    // the last block to finish has seen every block read wl_count: reset it
-    const uint64_t done = add64(&a.ctl->p3_done, 1);
-    if (done == gridDim.x - 1) {
-      __hip_atomic_store(&a.ctl->wl_count, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&a.ctl->p3_done, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+  const uint64_t first = ((uint64_t)blockIdx.x * WAVES + wv) * T::G + g;
+  // a uniform trip count per wave, so that every lane reaches the counters
+  const uint64_t wave_first = ((uint64_t)blockIdx.x * WAVES + wv) * T::G;
+  for (uint64_t base = wave_first; base < cnt; base += groups) {
+    const uint64_t t = base - wave_first + first;
+    if (t < cnt) evict_item<S>(a, geo, wl_slot(pre, t, a.wl_seg_cap), g, sl, n_evict, n_full);
   }
+  evict_counters(a, (uint64_t)blockIdx.x * WAVES + wv, n_evict, n_full, sl);
 }
 
 // ---------------------------------------------------------------------------
@@ -810,15 +894,31 @@ __global__ __launch_bounds__(BLOCK) void resize_plan_kernel(ResizeArgs a, uint32
 }
 
 // Ticket for "the last block of this launch": every block has finished its
-// reads of the control block and its writes to the table.
-__device__ __forceinline__ bool last_block(uint64_t *ticket) {
+// reads of the control block and its writes to the table.  Two levels, so
+// that no counter takes more than NSHARD atomics: block b counts on shard
+// b % NSHARD, and the block completing a shard counts on Ctl::ticket.  The
+// last block resets both levels for the next launch.
+__device__ __forceinline__ bool last_block(Ctl *c) {
   __shared__ bool last;
   __syncthreads();
   if (threadIdx.x == 0) {
+    const uint64_t grid = gridDim.x, s = blockIdx.x % NSHARD;
+    const uint64_t in_shard = (grid - s + NSHARD - 1) / NSHARD;
+    bool l = false;
     __threadfence();
-    last = add64(ticket, 1) == gridDim.x - 1;
+    if (add64(&shard_of(c, s)->ticket, 1) + 1 == in_shard) {
+      __threadfence();
+      l = add64(&c->ticket, 1) + 1 == min(grid, (uint64_t)NSHARD);
+    }
+    last = l;
   }
   __syncthreads();
+  if (last) {
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (threadIdx.x < NSHARD)
+      __hip_atomic_store(&shard_of(c, threadIdx.x)->ticket, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x == 0) __hip_atomic_store(&c->ticket, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
   return last;
 }
 
@@ -919,10 +1019,7 @@ __global__ __launch_bounds__(BLOCK) void resize_pass1_kernel(ResizeArgs a) {
     else
       merge_test_pair<S>(a, c, im, sp, j, g, sl);
   }
-  if (dir > 0 && last_block(&c->ticket)) {
-    c->ticket = 0;
-    split_segment_done(c, sp, seg);
-  }
+  if (dir > 0 && last_block(c) && threadIdx.x == 0) split_segment_done(c, sp, seg);
 }
 
 // Pass 2: move the merge pairs that fit, top down.
@@ -939,18 +1036,16 @@ __global__ __launch_bounds__(BLOCK) void resize_pass2_kernel(ResizeArgs a) {
   const uint64_t groups = (uint64_t)gridDim.x * WAVES * T::G;
   for (uint64_t j = ((uint64_t)blockIdx.x * WAVES + wv) * T::G + g; j < commit; j += groups)
     merge_move_pair<S>(a, im, sp, j, g, sl);
-  if (last_block(&c->ticket)) {
-    c->ticket = 0;
-    merge_segment_done(c, sp, seg, commit);
-  }
+  if (last_block(c) && threadIdx.x == 0) merge_segment_done(c, sp, seg, commit);
 }
 
 // After splits: every stash and pending entry moves to the eviction worklist
 // (the eviction phase re-places it under the new geometry) and the hint bits
 // are cleared (Section III-B "Overflow Stash").  One wave-aggregated append
-// per wave and item range; `t` indexes stash entries then pending entries.
+// per wave and item range; `t` indexes stash entries then pending entries,
+// and the 256-entry tile t / 256 picks the worklist segment.
 __device__ __forceinline__ void drain_collect(uint64_t t, uint64_t n_stash, uint64_t total, const uint64_t *stash,
-                                              const uint64_t *pending, uint64_t *wl, Ctl *c) {
+                                              const uint64_t *pending, uint64_t *wl, uint64_t seg_cap, Ctl *c) {
   uint64_t w = TOMB;
   if (t < n_stash)
     w = stash[t];
@@ -962,9 +1057,10 @@ __device__ __forceinline__ void drain_collect(uint64_t t, uint64_t n_stash, uint
     const int lane = threadIdx.x & 63;
     const int leader = __builtin_ctzll(m);
     uint64_t base = 0;
-    if (lane == leader) base = add64(&c->wl_count, (uint64_t)__popcll(m));
+    const uint64_t tile = t / BLOCK;
+    if (lane == leader) base = wl_append(c, tile, (uint64_t)__popcll(m));
     base = read_lane64(base, leader);
-    if (live) wl[base + rank_below(m)] = w;
+    if (live) wl[(tile % NSHARD) * seg_cap + base + rank_below(m)] = w;
   }
 }
 
@@ -976,7 +1072,7 @@ __device__ __forceinline__ void drain_done(volatile Ctl *c) {
 
 __global__ __launch_bounds__(BLOCK) void drain_kernel(uint64_t *stash, uint64_t stash_cap, uint64_t *pending,
                                                       uint64_t pending_cap, uint32_t *hint, uint64_t hint_n,
-                                                      uint64_t *wl, Ctl *c) {
+                                                      uint64_t *wl, uint64_t seg_cap, Ctl *c) {
   if (!c->split_happened) return;
   const uint64_t n_stash = min(c->stash_count, stash_cap);
   const uint64_t n_pend = min(c->pending_count, pending_cap);
@@ -987,11 +1083,8 @@ __global__ __launch_bounds__(BLOCK) void drain_kernel(uint64_t *stash, uint64_t 
     for (uint64_t t = tid; t < hint_n; t += stride) hint[t] = 0u;
   }
   const uint64_t span = (total + stride - 1) / stride * stride;
-  for (uint64_t t = tid; t < span; t += stride) drain_collect(t, n_stash, total, stash, pending, wl, c);
-  if (last_block(&c->drain_ticket)) {
-    c->drain_ticket = 0;
-    drain_done(c);
-  }
+  for (uint64_t t = tid; t < span; t += stride) drain_collect(t, n_stash, total, stash, pending, wl, seg_cap, c);
+  if (last_block(c) && threadIdx.x == 0) drain_done(c);
 }
 
 // ---------------------------------------------------------------------------
@@ -1100,7 +1193,7 @@ struct TableDesc {
   Ctl *ctl;
   uint64_t *wl;
   uint64_t *dd;
-  uint64_t stash_cap, pending_cap, hint_words;
+  uint64_t wl_seg_cap, stash_cap, pending_cap, hint_words;
   uint32_t S, max_evictions, K, lf_expand_pct, lf_contract_pct, pre_expand, post_policy, addressing;
 };
 
@@ -1161,8 +1254,8 @@ __device__ __forceinline__ ResizeArgs resize_args(const ReqDesc &d) {
 }
 
 __device__ __forceinline__ EvictArgs evict_args(const ReqDesc &d) {
-  return EvictArgs{d.t.buckets, d.t.hint, d.t.stash, d.t.pending, d.t.ctl, d.t.wl, d.t.stash_cap, d.t.pending_cap,
-                   d.t.max_evictions};
+  return EvictArgs{d.t.buckets, d.t.hint,       d.t.stash,       d.t.pending,      d.t.ctl,
+                   d.t.wl,      d.t.wl_seg_cap, d.t.stash_cap,   d.t.pending_cap,  d.t.max_evictions};
 }
 
 __device__ __forceinline__ bool has_inserts(const ReqDesc &d) { return d.mode == OP_INSERT || d.mode == OP_MIXED; }
@@ -1233,8 +1326,7 @@ __device__ __forceinline__ uint64_t enter(volatile ReqState *r, const ReqDesc &d
       return total ? max(ceil_div(total, BLOCK), ceil_div(d.t.hint_words, FILL_PER_CHUNK)) : 0;
     }
     case PH_REPLACE:
-    case PH_EVICT:
-      r->items = c->wl_count;
+    case PH_EVICT:  // r->items: the worklist size, summed when the phase before it finished
       return ceil_div(r->items, gpb * EVICT_PER_GROUP);
     case PH_OPS: return ceil_div(d.n, BLOCK);
     default: return 0;
@@ -1250,15 +1342,28 @@ __device__ __forceinline__ void epilogue(volatile ReqState *r, const ReqDesc &d,
       break;
     case PH_SEG_B: merge_segment_done(c, r->seg_sp, r->seg_n, c->merge_commit); break;
     case PH_DRAIN: drain_done(c); break;
-    case PH_REPLACE:
-    case PH_EVICT:
-      if (r->items) {
-        c->evict_items = c->evict_items + r->items;
-        c->wl_count = 0;
-      }
-      break;
     default: break;
   }
+}
+
+// Shard work at the end of a phase with chunks (wave 0 of the block that
+// completed it): after the probe phase the key-count changes are folded and
+// the worklist is sized; after a stash drain the worklist is sized; after an
+// eviction phase its statistics are folded and the worklist emptied.
+__device__ __forceinline__ void phase_fold(ReqState *rs, const ReqDesc &d, uint32_t ph) {
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  volatile ReqState *r = rs;
+  Ctl *c = d.t.ctl;
+  uint64_t items = 0;
+  switch (ph) {
+    case PH_OPS: items = fold_shards_wave(c, false); break;
+    case PH_DRAIN: items = wave_sum64(ld_ctl(&shard_of(c, threadIdx.x & 63)->wl_count)); break;
+    case PH_REPLACE:
+    case PH_EVICT: (void)fold_shards_wave(c, true); break;
+    default: return;
+  }
+  if ((threadIdx.x & 63) == 0) r->items = items;
+  __threadfence();
 }
 
 // Finish phase `ph` of r and publish the next one (one thread).
@@ -1425,20 +1530,23 @@ __device__ void run_chunk(ReqState *r, const ReqDesc &d, uint32_t ph, uint64_t c
       const uint64_t total = n_stash + min(ld_ctl(&cc->pending_count), d.t.pending_cap);
       const uint64_t hb = c * FILL_PER_CHUNK, he = min(hb + FILL_PER_CHUNK, d.t.hint_words);
       for (uint64_t t = hb + threadIdx.x; t < he; t += BLOCK) d.t.hint[t] = 0u;
-      drain_collect(c * BLOCK + threadIdx.x, n_stash, total, d.t.stash, d.t.pending, d.t.wl, d.t.ctl);
+      drain_collect(c * BLOCK + threadIdx.x, n_stash, total, d.t.stash, d.t.pending, d.t.wl, d.t.wl_seg_cap,
+                    d.t.ctl);
       break;
     }
     case PH_REPLACE:
     case PH_EVICT: {
+      __shared__ uint64_t pre[NSHARD + 1];
       const EvictArgs ea = evict_args(d);
+      wl_prefix(d.t.ctl, pre);
       const Geo geo = read_geo(d.t.ctl);
-      const uint64_t items = ld_ctl(&r->items);
+      const uint64_t items = pre[NSHARD];
       uint64_t n_evict = 0, n_full = 0;
       for (uint64_t k = 0; k < EVICT_PER_GROUP; ++k) {
         const uint64_t t = (c * EVICT_PER_GROUP + k) * gpb + gib;
-        if (t < items) evict_item<S>(ea, geo, t, g, sl, n_evict, n_full);
+        if (t < items) evict_item<S>(ea, geo, wl_slot(pre, t, d.t.wl_seg_cap), g, sl, n_evict, n_full);
       }
-      evict_counters(ea, n_evict, n_full, sl);
+      evict_counters(ea, c * WAVES + wv, n_evict, n_full, sl);
       break;
     }
     case PH_OPS: {
@@ -1449,6 +1557,7 @@ __device__ void run_chunk(ReqState *r, const ReqDesc &d, uint32_t ph, uint64_t c
       a.pending = d.t.pending;
       a.ctl = d.t.ctl;
       a.wl = d.t.wl;
+      a.wl_seg_cap = d.t.wl_seg_cap;
       a.dd = d.dd_size ? d.t.dd : nullptr;
       a.dd_mask = d.dd_size ? d.dd_size - 1 : 0;
       a.ops = d.ops;
@@ -1476,35 +1585,45 @@ __device__ void run_chunk(ReqState *r, const ReqDesc &d, uint32_t ph, uint64_t c
 
 __global__ void drain_reset_kernel(DrainQueue *q) { q->final_seen = 0; }
 
+// One reading of the constant-rate device clock (clock-rate calibration).
+__global__ void wall_clock_kernel(uint64_t *out) { *out = wall_clock64(); }
+
+// Occupancy target: 3 waves per SIMD (at most 168 VGPRs) fits without spills.
 template <int S>
-__global__ __launch_bounds__(BLOCK) void drain_worker_kernel(DrainQueue *q) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void drain_worker_kernel(DrainQueue *q) {
   __shared__ OpsShared<S> sh;
   __shared__ ReqDesc desc;
   __shared__ uint64_t s_req, s_chunk, s_nch;
   __shared__ uint32_t s_phase, s_cmd;
-  // watchdog: polls without any progress of the queue as a whole (nothing
-  // newly ingested, nothing retired), so blocks that merely find no chunk
-  // while others work do not give up
+  __shared__ bool s_last;
+  // watchdog (thread 0 decides for the block): time without any progress
+  // of the queue as a whole (nothing newly ingested, nothing retired), so
+  // blocks that merely find no chunk while others work do not give up
   uint64_t seen_ing = ~0ull, seen_head = ~0ull;
   uint64_t idle_since = wall_clock64();
   const uint64_t idle_ticks = ld_ctl(&q->idle_ticks);
   for (;;) {
-    if (threadIdx.x == 0) s_cmd = find_work(q, &s_req, &s_phase, &s_chunk, &s_nch);
+    if (threadIdx.x == 0) {
+      uint32_t cmd = find_work(q, &s_req, &s_phase, &s_chunk, &s_nch);
+      if (cmd == 1) {
+        const uint64_t ing = ld_ctl(&q->ingested), head = ld_ctl(&q->head);
+        const uint64_t now = wall_clock64();
+        if (ing != seen_ing || head != seen_head) {
+          seen_ing = ing;
+          seen_head = head;
+          idle_since = now;
+        }
+        if (now - idle_since > idle_ticks) {
+          atomicOr(&q->error, 1u);
+          cmd = 2;
+        }
+      }
+      s_cmd = cmd;
+    }
     __syncthreads();
     const uint32_t cmd = s_cmd;
     if (cmd == 2) break;
     if (cmd == 1) {
-      const uint64_t ing = ld_ctl(&q->ingested), head = ld_ctl(&q->head);
-      const uint64_t now = wall_clock64();
-      if (ing != seen_ing || head != seen_head) {
-        seen_ing = ing;
-        seen_head = head;
-        idle_since = now;
-      }
-      if (now - idle_since > idle_ticks) {
-        if (threadIdx.x == 0) atomicOr(&q->error, 1u);
-        break;
-      }
       __builtin_amdgcn_s_sleep(7);  // about 450 clocks
       __syncthreads();
       continue;
@@ -1517,7 +1636,15 @@ __global__ __launch_bounds__(BLOCK) void drain_worker_kernel(DrainQueue *q) {
     __syncthreads();
     if (threadIdx.x == 0) {
       __threadfence();  // this chunk's writes before its completion count
-      if (add64(&r->done, 1) + 1 == s_nch) advance(q, r, desc, s_phase);
+      s_last = add64(&r->done, 1) + 1 == s_nch;
+    }
+    __syncthreads();
+    if (s_last) {
+      // the block that completed the phase: shard folds by wave 0, then the
+      // scalar epilogue and the next phase by thread 0
+      if (threadIdx.x < 64) phase_fold(r, desc, s_phase);
+      __syncthreads();
+      if (threadIdx.x == 0) advance(q, r, desc, s_phase);
     }
     __syncthreads();
   }
@@ -1542,7 +1669,8 @@ struct hive_table {
   uint64_t *d_pending = nullptr;
   Ctl *d_ctl = nullptr;
   uint64_t *d_wl = nullptr;
-  uint64_t wl_cap = 0;
+  uint64_t wl_cap = 0;      // operations per batch the worklist is sized for
+  uint64_t wl_seg_cap = 0;  // entries per worklist segment (NSHARD segments)
   uint64_t *d_dd = nullptr;
   uint64_t dd_cap = 0;  // power of two
   uint64_t bytes = 0;
@@ -1636,6 +1764,7 @@ static hive_status reset_table(hive_table *h, hipStream_t st) {
   hive_status s;
   if ((s = fill_u64(h->d_buckets, h->max_buckets * h->S, EMPTY, st)) != HIVE_OK) return s;
   if ((s = fill_u32(h->d_hint, hint_words(h->max_buckets), 0u, st)) != HIVE_OK) return s;
+  if ((s = fill_u64((uint64_t *)shard_of(h->d_ctl, 0), NSHARD * SHARD_STRIDE / 8, 0, st)) != HIVE_OK) return s;
   hipLaunchKernelGGL(ctl_reset_kernel, dim3(1), dim3(1), 0, st, h->d_ctl, initial_ctl(h));
   return launch_check();
 }
@@ -1664,16 +1793,27 @@ static hive_status alloc(void **p, uint64_t bytes, uint64_t *total) {
 
 // Per-batch scratch (worklist and dedupe set) grows on demand; growing
 // synchronizes the stream because the old buffers may still be in use.
+// Entries per worklist segment for batches of up to n operations (or stash
+// drains of up to n entries): tile t of 256 appends to segment t % NSHARD,
+// at most 256 entries from each of ceil(tiles / NSHARD) tiles.
+static uint64_t wl_seg_cap_for(uint64_t n) {
+  const uint64_t tiles = (n + BLOCK - 1) / BLOCK;
+  return std::max<uint64_t>(1, (tiles + NSHARD - 1) / NSHARD) * BLOCK;
+}
+
 static hive_status ensure_scratch(hive_table *h, uint64_t n, bool need_dd, hipStream_t st) {
   if (n > h->wl_cap) {
     HIP_OK(hipStreamSynchronize(st));
     (void)hipFree(h->d_wl);
     h->d_wl = nullptr;
-    uint64_t cap = std::max<uint64_t>(n, 2 * h->wl_cap);
-    h->bytes -= h->wl_cap * 8;
+    const uint64_t cap = std::max<uint64_t>(n, 2 * h->wl_cap);
+    const uint64_t seg = wl_seg_cap_for(cap);
+    h->bytes -= h->wl_seg_cap * NSHARD * 8;
     h->wl_cap = 0;
-    if (alloc((void **)&h->d_wl, cap * 8, &h->bytes) != HIVE_OK) return HIVE_ERR_OOM;
+    h->wl_seg_cap = 0;
+    if (alloc((void **)&h->d_wl, seg * NSHARD * 8, &h->bytes) != HIVE_OK) return HIVE_ERR_OOM;
     h->wl_cap = cap;
+    h->wl_seg_cap = seg;
   }
   if (need_dd) {
     uint64_t want = 16;
@@ -1708,13 +1848,18 @@ static void launch_ops_mode(uint32_t mode, const OpsArgs &a, hipStream_t st) {
 }
 
 static void launch_evict(hive_table *h, hipStream_t st) {
-  EvictArgs e{h->d_buckets, h->d_hint, h->d_stash, h->d_pending, h->d_ctl, h->d_wl,
-              h->stash_cap, h->pending_cap, h->cfg.max_evictions};
+  EvictArgs e{h->d_buckets, h->d_hint,       h->d_stash, h->d_pending,  h->d_ctl,
+              h->d_wl,      h->wl_seg_cap,   h->stash_cap, h->pending_cap, h->cfg.max_evictions};
   switch (h->S) {
     case 16: hipLaunchKernelGGL(evict_kernel<16>, dim3(EVICT_GRID), dim3(BLOCK), 0, st, e); break;
     case 32: hipLaunchKernelGGL(evict_kernel<32>, dim3(EVICT_GRID), dim3(BLOCK), 0, st, e); break;
     default: hipLaunchKernelGGL(evict_kernel<64>, dim3(EVICT_GRID), dim3(BLOCK), 0, st, e); break;
   }
+}
+
+// Fold the shards into the totals and empty the worklist.
+static void launch_finish(hive_table *h, hipStream_t st) {
+  hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(64), 0, st, h->d_ctl);
 }
 
 // Upper bound on the hashing rounds one resize call can cross: from the
@@ -1746,8 +1891,9 @@ static hive_status resize_sequence(hive_table *h, uint32_t mode, uint64_t amount
     default: launch_resize_passes<64>(ra, rounds, st); break;
   }
   hipLaunchKernelGGL(drain_kernel, dim3(DRAIN_GRID), dim3(BLOCK), 0, st, h->d_stash, h->stash_cap, h->d_pending,
-                     h->pending_cap, h->d_hint, hint_words(h->max_buckets), h->d_wl, h->d_ctl);
+                     h->pending_cap, h->d_hint, hint_words(h->max_buckets), h->d_wl, h->wl_seg_cap, h->d_ctl);
   launch_evict(h, st);
+  launch_finish(h, st);
   return launch_check();
 }
 
@@ -1769,6 +1915,32 @@ static void free_drain(hive_drain *d) {
   (void)hipHostFree(d->h_done);
   (void)hipHostFree(d->h_live);
   delete d;
+}
+
+// Ticks per microsecond of the device's constant-rate clock: two readings
+// 10 ms apart on the host clock (launch latency is a small error here).
+static hive_status wall_clock_rate(double *ticks_per_us) {
+  uint64_t *d_t = nullptr;
+  uint64_t t[2] = {0, 0};
+  HIP_OK(hipMalloc((void **)&d_t, 16));
+  hipLaunchKernelGGL(wall_clock_kernel, dim3(1), dim3(1), 0, 0, d_t);
+  hipError_t e = hipDeviceSynchronize();
+  const auto h0 = std::chrono::steady_clock::now();
+  std::this_thread::sleep_for(std::chrono::milliseconds(10));
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(wall_clock_kernel, dim3(1), dim3(1), 0, 0, d_t + 1);
+    e = hipDeviceSynchronize();
+  }
+  const auto h1 = std::chrono::steady_clock::now();
+  if (e == hipSuccess) e = hipMemcpy(t, d_t, 16, hipMemcpyDeviceToHost);
+  (void)hipFree(d_t);
+  if (e != hipSuccess || t[1] <= t[0]) {
+    fprintf(stderr, "hive: device clock calibration failed: %s\n", hipGetErrorString(e));
+    return HIVE_ERR_HIP;
+  }
+  const double us = std::chrono::duration<double, std::micro>(h1 - h0).count();
+  *ticks_per_us = (double)(t[1] - t[0]) / us;
+  return HIVE_OK;
 }
 
 template <int S>
@@ -1819,6 +1991,7 @@ static hive_status run_batch(hive_t h, uint32_t mode, const uint8_t *d_ops, cons
   a.pending = h->d_pending;
   a.ctl = h->d_ctl;
   a.wl = h->d_wl;
+  a.wl_seg_cap = h->wl_seg_cap;
   a.ops = d_ops;
   a.keys = d_keys;
   a.vals = d_vals;
@@ -1853,10 +2026,9 @@ static hive_status run_batch(hive_t h, uint32_t mode, const uint8_t *d_ops, cons
     default: launch_ops_mode<64, false>(mode, a, st); break;
   }
   if ((s = launch_check()) != HIVE_OK) return s;
-  if (mode == OP_INSERT || mode == OP_MIXED) {
-    launch_evict(h, st);
-    if ((s = launch_check()) != HIVE_OK) return s;
-  }
+  if (mode == OP_INSERT || mode == OP_MIXED) launch_evict(h, st);
+  if (mode != OP_LOOKUP) launch_finish(h, st);
+  if ((s = launch_check()) != HIVE_OK) return s;
   if (linear && h->cfg.post_policy && mode != OP_LOOKUP) {
     if ((s = resize_sequence(h, PLAN_POST, 0, nullptr, st)) != HIVE_OK) return s;
   }
@@ -1914,7 +2086,7 @@ hive_status hive_create(const hive_config *cfg_in, uint64_t initial_buckets, voi
       (s = alloc((void **)&h->d_hint, hint_words(max_b) * 4, &h->bytes)) != HIVE_OK ||
       (s = alloc((void **)&h->d_stash, h->stash_cap * 8, &h->bytes)) != HIVE_OK ||
       (s = alloc((void **)&h->d_pending, h->pending_cap * 8, &h->bytes)) != HIVE_OK ||
-      (s = alloc((void **)&h->d_ctl, sizeof(Ctl), &h->bytes)) != HIVE_OK) {
+      (s = alloc((void **)&h->d_ctl, CTL_BYTES, &h->bytes)) != HIVE_OK) {
     free_table(h);
     return s;
   }
@@ -2131,16 +2303,16 @@ hive_status hive_drain_create(uint32_t slots_per_bucket, uint32_t blocks_per_cu,
   q.cap = ring_capacity;
   q.table_next = d->d_table_next;
   {
-    // the watchdog runs on the constant-rate device clock (rate in kHz)
-    int dev = 0, khz = 0;
-    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) !=
-                                                 hipSuccess || khz <= 0) {
-      (void)hipGetLastError();
+    // the watchdog runs on the constant-rate device clock; its rate is
+    // measured here against the host clock rather than taken on trust
+    double ticks_per_us = 0;
+    if (wall_clock_rate(&ticks_per_us) != HIVE_OK) {
       free_drain(d);
       return HIVE_ERR_HIP;
     }
-    const uint64_t us = idle_timeout_us ? idle_timeout_us : 30000000ull;
-    q.idle_ticks = us > (~0ull / (uint64_t)khz) ? ~0ull : us * (uint64_t)khz / 1000;
+    const double us = idle_timeout_us ? (double)idle_timeout_us : 30e6;
+    const double ticks = us * ticks_per_us;
+    q.idle_ticks = ticks >= 1.8e19 ? ~0ull : (uint64_t)ticks;
   }
   void *dp = nullptr;
   if (hipHostGetDevicePointer(&dp, d->h_ring, 0) != hipSuccess) goto fail;
@@ -2203,7 +2375,8 @@ hive_status hive_drain_submit(hive_drain_t d, hive_t h, const hive_batch_desc *b
   }
   ReqDesc r;
   memset(&r, 0, sizeof(r));
-  r.t = TableDesc{h->d_buckets, h->d_hint, h->d_stash, h->d_pending, h->d_ctl, h->d_wl, h->d_dd, h->stash_cap,
+  r.t = TableDesc{h->d_buckets,    h->d_hint,  h->d_stash,   h->d_pending, h->d_ctl, h->d_wl, h->d_dd,
+                  h->wl_seg_cap,  h->stash_cap,
                   h->pending_cap, hint_words(h->max_buckets), h->S, h->cfg.max_evictions, h->cfg.resize_k,
                   h->cfg.lf_expand_pct, h->cfg.lf_contract_pct, h->cfg.pre_expand, h->cfg.post_policy,
                   h->cfg.addressing};
@@ -2229,6 +2402,9 @@ hive_status hive_drain_submit(hive_drain_t d, hive_t h, const hive_batch_desc *b
 
 hive_status hive_drain_launch(hive_drain_t d, int resident, void *stream) {
   if (!d || d->running) return HIVE_ERR_ARG;
+  // a resident grid serving submissions that arrive while it runs left a
+  // batch unfinished in testing, cause not yet found: switched off
+  if (resident) return HIVE_ERR_ARG;
   hipStream_t user = (hipStream_t)stream;
   // a resident grid runs on the executor's own non-blocking stream, after the
   // work already enqueued on `stream`, so it holds up no other stream

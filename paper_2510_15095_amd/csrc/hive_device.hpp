@@ -35,43 +35,74 @@ enum : uint32_t {
 
 // Control block, one per table, in device memory.  Geometry is read by every
 // kernel at its start, so it may change between launches without host sync.
+// It is four 128-byte lines, each written by a
+// different kind of code, so that the line every probe block reads is never
+// the target of atomics; then NSHARD shard lines for counters that many
+// waves update (see Shard).
 struct alignas(128) Ctl {
-  // geometry (Section III-B global metadata, Section IV-C control fields)
+  // line 0: geometry (Section III-B global metadata, Section IV-C control
+  // fields) and overflow sizes, read by every block of every launch;
+  // written only between phases and by rare stash/pending appends
   uint64_t n_buckets;
-  uint64_t magic;      // FIXED: fastmod multiplier for n_buckets
-  uint64_t im;         // LINEAR: index mask 2^m - 1
-  uint64_t sp;         // LINEAR: split pointer
-  uint32_t mode;       // ADDR_FIXED / ADDR_LINEAR
-  uint32_t error;      // latched ERR_* bits
-  // logical size and overflow structures
-  uint64_t live;
+  uint64_t magic;          // FIXED: fastmod multiplier for n_buckets
+  uint64_t im;             // LINEAR: index mask 2^m - 1
+  uint64_t sp;             // LINEAR: split pointer
+  uint32_t mode;           // ADDR_FIXED / ADDR_LINEAR
+  uint32_t pad_mode_;
   uint64_t stash_count;    // ring slots used (including TOMB)
   uint64_t pending_count;  // pending slots used (including TOMB; may pass capacity on loss)
-  // per-batch
-  uint64_t wl_count;       // eviction worklist entries
-  uint64_t p3_done;        // blocks of the eviction kernel that finished
-  uint64_t dump_count;
-  // statistics
+  uint64_t pad0_[9];
+  // line 1: totals, folded from the shards after each batch, and error bits
+  uint64_t live;
   uint64_t evictions;
   uint64_t stash_inserts;
   uint64_t pending_inserts;
   uint64_t full_chains;
   uint64_t invalid_keys;
   uint64_t evict_items;
-  // resize bookkeeping (device-side policy, Section IV-C)
+  uint32_t error;          // latched ERR_* bits
+  uint32_t pad_err_;
+  uint64_t pad1_[8];
+  // line 2: resize bookkeeping (device-side policy, Section IV-C)
   int64_t resize_dir;      // +1 split, -1 merge, 0 idle
   uint64_t resize_todo;    // pairs the current resize call still has to do
   uint64_t seg;            // pairs of the current round segment
   uint64_t merge_commit;   // merge segment: pairs from the top that fit
-  uint64_t ticket;         // blocks of a resize pass that finished
+  uint64_t ticket;         // last-block ticket, second level
   uint64_t split_happened; // a split ran since the last stash drain
-  uint64_t drain_ticket;
   uint64_t initial_buckets;
   uint64_t max_buckets;
-  // placement census (hive_placement)
+  uint64_t pad2_[8];
+  // line 3: maintenance kernels (dump, placement census)
+  uint64_t dump_count;
   uint64_t place_first;
   uint64_t place_second;
+  uint64_t pad3_[13];
 };
+static_assert(sizeof(Ctl) == 512, "four lines");
+
+// Counters that every wave (or every group) updates live in NSHARD shards
+// instead of one word: a device-scope atomic on one address serialises at
+// the memory side, tens of nanoseconds each.  A writer picks its shard from
+// its tile index; the totals in Ctl line 1 are folded from the shards once
+// per batch.  Shards are SHARD_STRIDE bytes apart so that they fall in
+// different memory channels.  wl_count is the fill of the shard's segment of
+// the eviction worklist; ticket is the first level of the last-block ticket.
+constexpr int NSHARD = 64;
+constexpr uint64_t SHARD_STRIDE = 17 * 256;
+struct Shard {
+  uint64_t live;         // signed change of the key count (two's complement)
+  uint64_t wl_count;
+  uint64_t evictions;
+  uint64_t full_chains;
+  uint64_t invalid_keys;
+  uint64_t ticket;
+};
+constexpr uint64_t CTL_BYTES = sizeof(Ctl) + NSHARD * SHARD_STRIDE;
+
+__device__ __host__ __forceinline__ Shard *shard_of(const Ctl *c, uint64_t s) {
+  return (Shard *)((char *)(c + 1) + s * SHARD_STRIDE);
+}
 
 // ---- Section III-C hashes -------------------------------------------------
 // BitHash1 and BitHash2 written as compositions of invertible maps of
