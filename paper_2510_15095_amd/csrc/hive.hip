@@ -43,7 +43,7 @@ namespace hive {
 
 constexpr int WAVES = 4;  // waves per block
 constexpr int BLOCK = 64 * WAVES;
-constexpr int EVICT_GRID = 1024;  // blocks of the eviction phase (grid-stride)
+constexpr int EVICT_GRID = 2048;  // most blocks of the eviction phase (all resident at once)
 constexpr int RESIZE_GRID = 2048; // blocks of a resize pass (grid-stride over pairs)
 constexpr int DRAIN_GRID = 256;
 #ifndef OPS_WAVES_PER_EU
@@ -613,17 +613,16 @@ struct EvictArgs {
 
 __device__ __forceinline__ void set_hint(uint32_t *hint, uint32_t b) { or32(&hint[b >> 5], 1u << (b & 31)); }
 
+// Step 4: the item goes to the stash ring, or to the pending list when the
+// ring is full.  A slot is reserved with one fetch-add (the counts may pass
+// their capacities; every reader clamps them), so simultaneous pushes cost
+// one atomic each instead of a retry loop.
 __device__ __forceinline__ void overflow_push(const EvictArgs &a, const Geo &geo, uint64_t kv) {
   bool stashed = false;
-  uint64_t c = load_fresh(&a.ctl->stash_count);
-  while (c < a.stash_cap) {
-    const uint64_t found = cas64(&a.ctl->stash_count, c, c + 1);
-    if (found == c) {
-      __hip_atomic_store(a.stash + c, kv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      stashed = true;
-      break;
-    }
-    c = found;
+  const uint64_t c = load_fresh(&a.ctl->stash_count) < a.stash_cap ? add64(&a.ctl->stash_count, 1) : a.stash_cap;
+  if (c < a.stash_cap) {
+    __hip_atomic_store(a.stash + c, kv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    stashed = true;
   }
   if (stashed) {
     add64(&a.ctl->stash_inserts, 1);
@@ -1133,6 +1132,10 @@ __global__ __launch_bounds__(BLOCK) void dump_kernel(const uint64_t *buckets, ui
 // Placement census: live bucket entries in their first candidate bucket and
 // in their second one (the two differ).
 __global__ __launch_bounds__(BLOCK) void placement_kernel(const uint64_t *buckets, uint32_t S, Ctl *ctl) {
+  __shared__ unsigned long long s_first, s_second;
+  if (threadIdx.x == 0) s_first = s_second = 0;
+  __syncthreads();
+  unsigned long long n_first = 0, n_second = 0;
   const Geo geo = read_geo(ctl);
   const uint64_t n_slots = geo.n_buckets * S;
   const uint64_t stride = (uint64_t)gridDim.x * BLOCK;
@@ -1143,9 +1146,19 @@ __global__ __launch_bounds__(BLOCK) void placement_kernel(const uint64_t *bucket
     const bool first = live && address(geo, bithash1(key_of(w))) == (uint32_t)(t / S);
     const uint64_t mf = ballot(first), ms = ballot(live && !first);
     if ((threadIdx.x & 63) == 0) {
-      if (mf) add64(&ctl->place_first, (uint64_t)__popcll(mf));
-      if (ms) add64(&ctl->place_second, (uint64_t)__popcll(ms));
+      n_first += (uint64_t)__popcll(mf);
+      n_second += (uint64_t)__popcll(ms);
     }
+  }
+  // one pair of atomics per block
+  if ((threadIdx.x & 63) == 0) {
+    atomicAdd(&s_first, n_first);
+    atomicAdd(&s_second, n_second);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (s_first) add64(&ctl->place_first, s_first);
+    if (s_second) add64(&ctl->place_second, s_second);
   }
 }
 
@@ -1847,13 +1860,18 @@ static void launch_ops_mode(uint32_t mode, const OpsArgs &a, hipStream_t st) {
   }
 }
 
-static void launch_evict(hive_table *h, hipStream_t st) {
+// The eviction grid: one group per item up to EVICT_GRID blocks (chains are
+// latency-bound, so items run side by side rather than one after another in
+// a group); `max_items` bounds the worklist (the batch's inserts, or the
+// stash and pending capacity for a drain).
+static void launch_evict(hive_table *h, uint64_t max_items, hipStream_t st) {
   EvictArgs e{h->d_buckets, h->d_hint,       h->d_stash, h->d_pending,  h->d_ctl,
               h->d_wl,      h->wl_seg_cap,   h->stash_cap, h->pending_cap, h->cfg.max_evictions};
+  const dim3 grid(grid_for(max_items, (uint64_t)WAVES * (64 / h->S), EVICT_GRID));
   switch (h->S) {
-    case 16: hipLaunchKernelGGL(evict_kernel<16>, dim3(EVICT_GRID), dim3(BLOCK), 0, st, e); break;
-    case 32: hipLaunchKernelGGL(evict_kernel<32>, dim3(EVICT_GRID), dim3(BLOCK), 0, st, e); break;
-    default: hipLaunchKernelGGL(evict_kernel<64>, dim3(EVICT_GRID), dim3(BLOCK), 0, st, e); break;
+    case 16: hipLaunchKernelGGL(evict_kernel<16>, grid, dim3(BLOCK), 0, st, e); break;
+    case 32: hipLaunchKernelGGL(evict_kernel<32>, grid, dim3(BLOCK), 0, st, e); break;
+    default: hipLaunchKernelGGL(evict_kernel<64>, grid, dim3(BLOCK), 0, st, e); break;
   }
 }
 
@@ -1892,7 +1910,7 @@ static hive_status resize_sequence(hive_table *h, uint32_t mode, uint64_t amount
   }
   hipLaunchKernelGGL(drain_kernel, dim3(DRAIN_GRID), dim3(BLOCK), 0, st, h->d_stash, h->stash_cap, h->d_pending,
                      h->pending_cap, h->d_hint, hint_words(h->max_buckets), h->d_wl, h->wl_seg_cap, h->d_ctl);
-  launch_evict(h, st);
+  launch_evict(h, h->stash_cap + h->pending_cap, st);
   launch_finish(h, st);
   return launch_check();
 }
@@ -2026,7 +2044,7 @@ static hive_status run_batch(hive_t h, uint32_t mode, const uint8_t *d_ops, cons
     default: launch_ops_mode<64, false>(mode, a, st); break;
   }
   if ((s = launch_check()) != HIVE_OK) return s;
-  if (mode == OP_INSERT || mode == OP_MIXED) launch_evict(h, st);
+  if (mode == OP_INSERT || mode == OP_MIXED) launch_evict(h, n, st);
   if (mode != OP_LOOKUP) launch_finish(h, st);
   if ((s = launch_check()) != HIVE_OK) return s;
   if (linear && h->cfg.post_policy && mode != OP_LOOKUP) {
