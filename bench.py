@@ -139,8 +139,6 @@ def run_mixed(args):
     batches of 2^22 operations (40% insert incl. repeats, 40% delete, 20%
     lookup; Zipf(0.99) keys; per-batch disjoint key sets per type), each one
     hive_mixed_batch call with dedupe; post-batch load-factor rule at 95%."""
-    import multiprocessing as mp
-
     import torch
     from paper_2510_15095_amd import hive as H
     from paper_2510_15095_amd import workload as wl
@@ -150,10 +148,9 @@ def run_mixed(args):
     ks = wl.KeyStream(3)
     pre_ranks = wl.DomainPerm(wl.batch_seed(3, 0xBEEF), universe).sample(n_pre)
     pre_keys = ks.keys(pre_ranks)
-    # generate every batch before the GPU is touched (worker processes are
-    # forked from this one)
-    with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
-        gen = pool.starmap(_gen_mixed, [(b, n_ops, universe) for b in range(nbat)])
+    # generate every batch before the GPU is touched, in worker processes
+    gen = wl.parallel_map(_gen_mixed, [(b, n_ops, universe) for b in range(nbat)], min(16, os.cpu_count() or 1))
+    print(f"[bench] generated {nbat} mixed batches", file=sys.stderr, flush=True)
     dev = torch.device("cuda:0")
     pk = torch.from_numpy(pre_keys).to(dev)
     pv = torch.from_numpy(wl.values_for(pre_keys)).to(dev)
@@ -191,11 +188,12 @@ def run_mixed(args):
         prefill()
         run(mk())
     times = []
-    for _ in range(args.steps):
+    for step in range(args.steps):
         prefill()
         ev = mk()
         run(ev)
         torch.cuda.synchronize()
+        print(f"[bench] mixed step {step} done", file=sys.stderr, flush=True)
         if drain is not None:
             times.append([ev[0].elapsed_time(ev[-1]) / nbat] * nbat)
         else:
@@ -231,6 +229,7 @@ def run_served(args):
     reqs = sv.make_requests(specs, args.requests, 5, rate=0, log2_max_size=args.request_log2,
                             workers=min(16, os.cpu_count() or 1))
     budget = sv.footprint_bytes(specs)
+    print(f"[bench] {len(reqs)} requests on {len(specs)} tables generated", file=sys.stderr, flush=True)
     srv = sv.Server(specs, budget, max_request=1 << int(np.ceil(args.request_log2)), ring=1024, streams=8)
     res = {}
     for mode in ("plain", "persistent"):
@@ -238,6 +237,7 @@ def run_served(args):
         srv.run(reqs[: min(200, len(reqs))], mode)  # warm-up
         srv.load()
         res[mode + "_saturation"] = srv.run(reqs, mode)
+        print(f"[bench] served {mode} saturation run done", file=sys.stderr, flush=True)
     mean_ops = float(np.mean([r.n for r in reqs]))
     sat_rate = min(res["plain_saturation"]["mops"], res["persistent_saturation"]["mops"]) * 1e6 / mean_ops
     rate = 0.7 * sat_rate
@@ -278,6 +278,7 @@ def run_resize(args):
     keys = torch.from_numpy(ks.range(0, n)).to(dev)
     vals = torch.from_numpy(wl.values_for(keys.cpu().numpy())).to(dev)
     dkeys = torch.from_numpy(ks.keys(wl.DomainPerm(wl.batch_seed(4, 0xDE1), n).sample(n_del))).to(dev)
+    print(f"[bench] resize inputs ready: {n} inserts, {n_del} deletes", file=sys.stderr, flush=True)
     nb0 = 1 << 16
     max_b = 1
     while max_b * 16 * 0.9 < n * 1.05:
@@ -306,9 +307,10 @@ def run_resize(args):
         run(mk())
     res = []
     peak = 0
-    for _ in range(args.steps):
+    for step in range(args.steps):
         ev = mk()
         peak = run(ev)
+        print(f"[bench] resize step {step} done", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         res.append((ev[0].elapsed_time(ev[1]), ev[2].elapsed_time(ev[3])))
     ms = np.array(res)

@@ -83,9 +83,8 @@ def make_requests(specs, n_req: int, seed: int, rate: float, log2_max_size: floa
     """Poisson arrivals at `rate` requests/s (rate <= 0: all at time 0);
     sizes floor(2^U(0, log2_max_size)), at most the table's initial key count;
     50% lookup / 25% insert / 25% delete; uniform or Zipf(0.99) keys by a
-    per-request coin; tables uniform.  Call before the GPU is used (the
-    generator runs in forked worker processes)."""
-    import multiprocessing as mp
+    per-request coin; tables uniform.  With workers > 1, call before the
+    GPU is used (the generator runs in worker processes)."""
     rng = np.random.default_rng(wl.batch_seed(seed, 0x5E5))
     tables = rng.integers(0, len(specs), n_req)
     sizes = np.floor(2.0 ** rng.uniform(0, log2_max_size, n_req)).astype(np.int64)
@@ -94,11 +93,8 @@ def make_requests(specs, n_req: int, seed: int, rate: float, log2_max_size: floa
     arrivals = np.cumsum(gaps) - (gaps[0] if n_req else 0)
     sizes = np.minimum(sizes, [specs[t].n_keys for t in tables])
     jobs = [(r, specs[tables[r]].seed, specs[tables[r]].universe, int(sizes[r]), bool(zipf[r])) for r in range(n_req)]
-    if workers > 1:
-        with mp.get_context("fork").Pool(workers) as pool:
-            gen = pool.map(_gen_request, jobs, chunksize=16)
-    else:  # no worker processes (e.g. once the GPU is in use in this process)
-        gen = [_gen_request(j) for j in jobs]
+    # worker processes only before the GPU is used in this process
+    gen = wl.parallel_map(_gen_request, [(j,) for j in jobs], workers)
     out = []
     for r, (ops, keys, vals) in enumerate(gen):
         out.append(Request(r, int(tables[r]), float(arrivals[r]), int(sizes[r]),

@@ -407,3 +407,28 @@ def resolve_mixed_reference(ops: np.ndarray, ranks: np.ndarray, draw) -> np.ndar
             r = int(pool.pop(0))
         out[i] = r
     return out
+
+
+def parallel_map(fn, jobs, workers: int):
+    """[fn(*job) for job in jobs] in `workers` worker processes.
+
+    Workers are started fresh (the "spawn" method), never forked: this
+    module's native generator runs OpenMP, and a process forked after its
+    thread pool exists can deadlock in it.  Each worker runs OpenMP on one
+    thread, since the workers already fill the cores.  `fn` must be a
+    module-level function.  Call it before the GPU is used."""
+    import multiprocessing as mp
+    jobs = list(jobs)
+    if workers <= 1 or len(jobs) <= 1:
+        return [fn(*j) for j in jobs]
+    old = os.environ.get("OMP_NUM_THREADS")
+    os.environ["OMP_NUM_THREADS"] = "1"  # inherited by the workers at start
+    try:
+        pool = mp.get_context("spawn").Pool(min(workers, len(jobs)))
+    finally:
+        if old is None:
+            del os.environ["OMP_NUM_THREADS"]
+        else:
+            os.environ["OMP_NUM_THREADS"] = old
+    with pool:
+        return pool.starmap(fn, jobs, chunksize=1)

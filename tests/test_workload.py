@@ -137,3 +137,16 @@ def test_mixed_batch_native_resolver_matches_reference():
     # op5 lookup takes 8; op6 delete takes 9; op7 repeated delete 9 -> 14;
     # op8 insert cannot take 9 -> 15
     assert r.tolist() == [5, 11, 12, 7, 13, 8, 9, 14, 15]
+
+
+def test_parallel_map_equals_sequential_after_native_use():
+    """Worker processes start fresh, so generating after the native
+    (OpenMP) generator has run in this process neither deadlocks nor
+    changes the draws."""
+    wl.KeyStream(9).keys(np.arange(1 << 16, dtype=np.uint64))  # native code runs here first
+    jobs = [(4, b, 4096, 1 << 16) for b in range(4)]
+    par = wl.parallel_map(wl.mixed_batch, jobs, 2)
+    for j, p in zip(jobs, par):
+        q = wl.mixed_batch(*j)
+        for f in ("ops", "keys", "vals"):
+            assert np.array_equal(p[f], q[f])
