@@ -145,12 +145,13 @@ def run_mixed(args):
     universe, n_pre = 1 << 26, 1 << 24
     n_ops, nbat = 1 << args.batch_log2, args.batches
     nb0 = 1103765
+    # generate every batch before the GPU is touched and before this process
+    # runs the native generator itself (the workers are forked)
+    gen = wl.parallel_map(_gen_mixed, [(b, n_ops, universe) for b in range(nbat)], min(16, os.cpu_count() or 1))
+    print(f"[bench] generated {nbat} mixed batches", file=sys.stderr, flush=True)
     ks = wl.KeyStream(3)
     pre_ranks = wl.DomainPerm(wl.batch_seed(3, 0xBEEF), universe).sample(n_pre)
     pre_keys = ks.keys(pre_ranks)
-    # generate every batch before the GPU is touched, in worker processes
-    gen = wl.parallel_map(_gen_mixed, [(b, n_ops, universe) for b in range(nbat)], min(16, os.cpu_count() or 1))
-    print(f"[bench] generated {nbat} mixed batches", file=sys.stderr, flush=True)
     dev = torch.device("cuda:0")
     pk = torch.from_numpy(pre_keys).to(dev)
     pv = torch.from_numpy(wl.values_for(pre_keys)).to(dev)

@@ -1795,7 +1795,9 @@ static void free_table(hive_table *h) {
 }
 
 static hive_status alloc(void **p, uint64_t bytes, uint64_t *total) {
-  if (hipMalloc(p, bytes ? bytes : 8) != hipSuccess) {
+  const hipError_t e = hipMalloc(p, bytes ? bytes : 8);
+  if (e != hipSuccess) {
+    fprintf(stderr, "hive: hipMalloc of %llu bytes failed: %s\n", (unsigned long long)bytes, hipGetErrorString(e));
     (void)hipGetLastError();
     *p = nullptr;
     return HIVE_ERR_OOM;

@@ -45,11 +45,13 @@ OP_LOOKUP = 2
 
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libworkload_gen.so")
 _lib = None
+_native_touched = False  # the OpenMP generator may have run in this process
 
 
 def _native():
     """The compiled generator (csrc/workload_gen.c), or None if not built."""
-    global _lib
+    global _lib, _native_touched
+    _native_touched = True
     if _lib is None and os.path.exists(_LIB_PATH):
         lib = ctypes.CDLL(_LIB_PATH)
         p = ctypes.c_void_p
@@ -410,25 +412,19 @@ def resolve_mixed_reference(ops: np.ndarray, ranks: np.ndarray, draw) -> np.ndar
 
 
 def parallel_map(fn, jobs, workers: int):
-    """[fn(*job) for job in jobs] in `workers` worker processes.
+    """[fn(*job) for job in jobs] in `workers` forked worker processes.
 
-    Workers are started fresh (the "spawn" method), never forked: this
-    module's native generator runs OpenMP, and a process forked after its
-    thread pool exists can deadlock in it.  Each worker runs OpenMP on one
-    thread, since the workers already fill the cores.  `fn` must be a
-    module-level function.  Call it before the GPU is used."""
+    The native generator runs OpenMP, and a process forked after its thread
+    pool exists can deadlock in it, so workers are forked only while this
+    process has not touched the native generator; otherwise the jobs run
+    here, one after another.  Call it before the GPU is used."""
     import multiprocessing as mp
+    import sys
     jobs = list(jobs)
-    if workers <= 1 or len(jobs) <= 1:
+    if workers <= 1 or len(jobs) <= 1 or _native_touched:
+        if workers > 1 and len(jobs) > 1:
+            print("workload: native generator already used in this process; generating without workers",
+                  file=sys.stderr, flush=True)
         return [fn(*j) for j in jobs]
-    old = os.environ.get("OMP_NUM_THREADS")
-    os.environ["OMP_NUM_THREADS"] = "1"  # inherited by the workers at start
-    try:
-        pool = mp.get_context("spawn").Pool(min(workers, len(jobs)))
-    finally:
-        if old is None:
-            del os.environ["OMP_NUM_THREADS"]
-        else:
-            os.environ["OMP_NUM_THREADS"] = old
-    with pool:
+    with mp.get_context("fork").Pool(min(workers, len(jobs))) as pool:
         return pool.starmap(fn, jobs, chunksize=1)
