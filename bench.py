@@ -94,6 +94,9 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
+    # inputs generated in forked worker processes come first: no process may
+    # fork once the HIP runtime is loaded into it
+    pre = {"mixed": gen_mixed, "served": gen_served}.get(args.workload, lambda a: None)(args)
     tuned = {}
     if args.workload in ("mixed", "resize", "served"):
         from paper_2510_15095_amd import autotune
@@ -103,7 +106,8 @@ def main():
     if not args.resize_k:
         args.resize_k = (tuned.get("resize") or {}).get("resize_k", 1024)
     args.blocks_per_cu = (tuned.get("executor") or {}).get("blocks_per_cu", 0)
-    out = {"bulk": run_bulk, "mixed": run_mixed, "resize": run_resize, "served": run_served}[args.workload](args)
+    run = {"bulk": run_bulk, "mixed": run_mixed, "resize": run_resize, "served": run_served}[args.workload]
+    out = run(args) if pre is None else run(args, pre)
     if tuned:
         out["autotuned"] = {k: v for k, v in tuned.items() if v}
     print(json.dumps(out), flush=True)
@@ -133,7 +137,27 @@ def _gen_mixed(b, n_ops, universe):
     return mb["ops"], mb["keys"], mb["vals"]
 
 
-def run_mixed(args):
+def gen_mixed(args):
+    """The mixed workload's batches (before anything loads the HIP runtime)."""
+    from paper_2510_15095_amd import workload as wl
+    n_ops, nbat = 1 << args.batch_log2, args.batches
+    gen = wl.parallel_map(_gen_mixed, [(b, n_ops, 1 << 26) for b in range(nbat)], min(16, os.cpu_count() or 1))
+    print(f"[bench] generated {nbat} mixed batches", file=sys.stderr, flush=True)
+    return gen
+
+
+def gen_served(args):
+    """The served workload's tables and requests (before anything loads the
+    HIP runtime)."""
+    from paper_2510_15095_amd import serve as sv
+    specs = sv.make_specs(args.tables, 5, log2_min=12, log2_max=22)
+    reqs = sv.make_requests(specs, args.requests, 5, rate=0, log2_max_size=args.request_log2,
+                            workers=min(16, os.cpu_count() or 1))
+    print(f"[bench] {len(reqs)} requests on {len(specs)} tables generated", file=sys.stderr, flush=True)
+    return specs, reqs
+
+
+def run_mixed(args, gen):
     """Mixed contended workload: a LINEAR table pre-filled with 2^24 keys
     (uniform sample of a 2^26-key Zipf universe) at 95% load, then `batches`
     batches of 2^22 operations (40% insert incl. repeats, 40% delete, 20%
@@ -145,10 +169,6 @@ def run_mixed(args):
     universe, n_pre = 1 << 26, 1 << 24
     n_ops, nbat = 1 << args.batch_log2, args.batches
     nb0 = 1103765
-    # generate every batch before the GPU is touched and before this process
-    # runs the native generator itself (the workers are forked)
-    gen = wl.parallel_map(_gen_mixed, [(b, n_ops, universe) for b in range(nbat)], min(16, os.cpu_count() or 1))
-    print(f"[bench] generated {nbat} mixed batches", file=sys.stderr, flush=True)
     ks = wl.KeyStream(3)
     pre_ranks = wl.DomainPerm(wl.batch_seed(3, 0xBEEF), universe).sample(n_pre)
     pre_keys = ks.keys(pre_ranks)
@@ -217,7 +237,7 @@ def run_mixed(args):
     return rec
 
 
-def run_served(args):
+def run_served(args, pre):
     """Served multi-table loop: many LINEAR tables (log-uniform sizes,
     created at 85% load, 25% HBM headroom each), mixed requests (50% lookup,
     25% insert, 25% delete; uniform or Zipf(0.99) keys; log-uniform sizes)
@@ -226,11 +246,8 @@ def run_served(args):
     mode's saturation rate (p50/p99 latency of each mode)."""
     import torch
     from paper_2510_15095_amd import serve as sv
-    specs = sv.make_specs(args.tables, 5, log2_min=12, log2_max=22)
-    reqs = sv.make_requests(specs, args.requests, 5, rate=0, log2_max_size=args.request_log2,
-                            workers=min(16, os.cpu_count() or 1))
+    specs, reqs = pre
     budget = sv.footprint_bytes(specs)
-    print(f"[bench] {len(reqs)} requests on {len(specs)} tables generated", file=sys.stderr, flush=True)
     srv = sv.Server(specs, budget, max_request=1 << int(np.ceil(args.request_log2)), ring=1024, streams=8)
     res = {}
     for mode in ("plain", "persistent"):

@@ -27,8 +27,15 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from . import hive as H
 from . import workload as wl
+
+
+def _binding():
+    """The C-ABI binding, imported on first use: request generation forks
+    worker processes, which must happen before the HIP runtime is loaded
+    into this process."""
+    from . import hive
+    return hive
 
 BYTES_PER_BUCKET = 128  # 16 slots x 8 B
 
@@ -107,6 +114,7 @@ class Server:
 
     def __init__(self, specs, budget_bytes: int, max_request: int, ring: int = 1024, streams: int = 8):
         import torch
+        H = _binding()
         self.specs = specs
         need = footprint_bytes(specs)
         if need > budget_bytes:
@@ -124,6 +132,7 @@ class Server:
     def load(self):
         """Insert each table's initial keys (indices 0..n-1 of its stream)."""
         import torch
+        H = _binding()
         for s, t in zip(self.specs, self.tables):
             t.clear()
             ks = wl.KeyStream(s.seed)
@@ -141,6 +150,7 @@ class Server:
         """Serve `requests` (device copies made beforehand) and return latency
         and throughput figures; with outputs=True also the per-request results."""
         import torch
+        H = _binding()
         dev = [(torch.from_numpy(r.ops).cuda(), torch.from_numpy(r.keys).cuda(), torch.from_numpy(r.vals).cuda())
                for r in requests]
         vout = [torch.empty(r.n, dtype=torch.uint32, device="cuda") for r in requests]
