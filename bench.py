@@ -94,8 +94,8 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
-    # inputs generated in forked worker processes come first: no process may
-    # fork once the HIP runtime is loaded into it
+    # inputs generated in forked worker processes come first, before this
+    # process uses the GPU or runs the native generator itself
     pre = {"mixed": gen_mixed, "served": gen_served}.get(args.workload, lambda a: None)(args)
     tuned = {}
     if args.workload in ("mixed", "resize", "served"):
@@ -138,7 +138,7 @@ def _gen_mixed(b, n_ops, universe):
 
 
 def gen_mixed(args):
-    """The mixed workload's batches (before anything loads the HIP runtime)."""
+    """The mixed workload's batches (generated before the GPU is used)."""
     from paper_2510_15095_amd import workload as wl
     n_ops, nbat = 1 << args.batch_log2, args.batches
     gen = wl.parallel_map(_gen_mixed, [(b, n_ops, 1 << 26) for b in range(nbat)], min(16, os.cpu_count() or 1))
@@ -147,8 +147,8 @@ def gen_mixed(args):
 
 
 def gen_served(args):
-    """The served workload's tables and requests (before anything loads the
-    HIP runtime)."""
+    """The served workload's tables and requests (generated before the GPU
+    is used)."""
     from paper_2510_15095_amd import serve as sv
     specs = sv.make_specs(args.tables, 5, log2_min=12, log2_max=22)
     reqs = sv.make_requests(specs, args.requests, 5, rate=0, log2_max_size=args.request_log2,

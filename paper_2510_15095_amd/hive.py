@@ -83,6 +83,11 @@ class HiveError(RuntimeError):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2510_15095_amd.build`")
+    # torch ships its own HIP and HSA runtimes.  Loaded first, they also
+    # satisfy libhive.so's dependencies, so the process has one runtime;
+    # loaded after libhive.so (which links the system ROCm copies), the
+    # process holds two, and the one initialised second finds no device.
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     p, u64, u32, i64, st = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int64, ctypes.c_int
     sig = {

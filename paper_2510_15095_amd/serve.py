@@ -31,9 +31,8 @@ from . import workload as wl
 
 
 def _binding():
-    """The C-ABI binding, imported on first use: request generation forks
-    worker processes, which must happen before the HIP runtime is loaded
-    into this process."""
+    """The C-ABI binding, imported on first use (request generation needs
+    neither it nor the GPU)."""
     from . import hive
     return hive
 

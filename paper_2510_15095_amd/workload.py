@@ -417,9 +417,8 @@ def parallel_map(fn, jobs, workers: int):
     The native generator runs OpenMP, and a process forked after its thread
     pool exists can deadlock in it, so workers are forked only while this
     process has not touched the native generator; otherwise the jobs run
-    here, one after another.  Call it before the HIP runtime is loaded into
-    this process (before importing the binding or using the GPU): a process
-    that forks after that lost its GPU device on MI355X."""
+    here, one after another.  Call it before the GPU is used in this
+    process."""
     import multiprocessing as mp
     import sys
     jobs = list(jobs)

@@ -110,3 +110,20 @@ def test_null_handle_and_arguments_rejected(H):
 def test_status_strings_cover_all_codes(H):
     for s in (0, -1, -2, -3, -4, -5, 1, 2):
         assert H.lib.hive_status_string(s).decode() != "unknown status"
+
+
+def test_binding_loads_one_hip_runtime():
+    """Importing the binding in a fresh process maps exactly one HIP and one
+    HSA runtime (two copies in one process leave the second without a
+    device)."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_2510_15095_amd import hive\n"
+            "maps = open('/proc/self/maps').read().split(chr(10))\n"
+            "hip = {l.split()[-1] for l in maps if 'libamdhip64' in l}\n"
+            "hsa = {l.split()[-1] for l in maps if 'libhsa-runtime64' in l}\n"
+            "print(len(hip), len(hsa))\n") % ROOT
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.split()[-2:] == ["1", "1"], out.stdout
