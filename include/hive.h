@@ -66,7 +66,10 @@ typedef struct {
   uint32_t max_evictions;     /* bound on cuckoo displacements per insert
                                  (Section III-B "Global Metadata"); default 8 */
   uint64_t stash_capacity;    /* overflow stash entries (Section IV-A step 4);
-                                 0 = max(1024, 1% of the initial slots) */
+                                 0 = max(1024, 1% of the slots of max_buckets).
+                                 Held as an open-addressed table of at least
+                                 twice as many words, so a search probes a
+                                 short run instead of scanning */
   uint64_t pending_capacity;  /* entries beyond a full stash; 0 = stash_capacity */
   uint32_t addressing;        /* HIVE_FIXED or HIVE_LINEAR */
   uint32_t resize_k;          /* K: bucket pairs per split/merge step (Section
@@ -96,7 +99,7 @@ typedef struct {
   uint64_t n_buckets;       /* current bucket count */
   uint64_t index_mask;      /* LINEAR: 2^m - 1 of the current round */
   uint64_t split_ptr;       /* LINEAR: buckets of this round already split */
-  uint64_t stash_count;     /* stash ring entries in use (incl. deleted ones) */
+  uint64_t stash_count;     /* stash entries in use (incl. deleted ones) */
   uint64_t pending_count;   /* pending entries in use (incl. deleted ones) */
   uint64_t evictions;       /* cuckoo displacements (Section IV-A step 3) */
   uint64_t stash_inserts;   /* entries that entered the stash */

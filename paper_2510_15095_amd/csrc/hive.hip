@@ -328,14 +328,21 @@ __device__ __forceinline__ bool hinted(const uint32_t *hint, uint32_t c1, uint32
   return ((hint[c1 >> 5] >> (c1 & 31)) & 1u) | ((hint[c2 >> 5] >> (c2 & 31)) & 1u);
 }
 
-// Lane-wise search of the stash ring and the pending list.
-__device__ __forceinline__ uint64_t *overflow_find(uint64_t *stash, uint64_t n_stash, uint64_t *pending, uint64_t n_pend,
-                                          uint32_t k, uint64_t *word, bool fresh) {
-  for (uint64_t p = 0; p < n_stash; ++p) {
-    const uint64_t x = fresh ? load_fresh(stash + p) : stash[p];
-    if (key_of(x) == k) {
-      *word = x;
-      return stash + p;
+// Lane-wise search of the stash and the pending list.  The stash is an
+// open-addressed table (linear probing from mix32(key)); a search ends at
+// the key or at an EMPTY word (tombstones keep probe runs intact).
+__device__ __forceinline__ uint64_t *overflow_find(uint64_t *stash, uint64_t stash_cap, uint64_t n_stash,
+                                                   uint64_t *pending, uint64_t n_pend, uint32_t k, uint64_t *word,
+                                                   bool fresh) {
+  if (n_stash) {
+    const uint64_t mask = stash_slots_for(stash_cap) - 1;
+    for (uint64_t i = 0, p = mix32(k) & mask; i <= mask; ++i, p = (p + 1) & mask) {
+      const uint64_t x = fresh ? load_fresh(stash + p) : stash[p];
+      if (x == EMPTY) break;
+      if (key_of(x) == k) {
+        *word = x;
+        return stash + p;
+      }
     }
   }
   for (uint64_t p = 0; p < n_pend; ++p) {
@@ -494,7 +501,7 @@ __device__ __forceinline__ void ops_tile(const OpsArgs &a, const OpsView &view, 
       word = s_w[1][wv][lane];
       in_bucket = true;
     } else if (overflow_used && hinted(a.hint, c1, c2)) {
-      slot = overflow_find(a.stash, n_stash, a.pending, n_pend, k, &word, false);
+      slot = overflow_find(a.stash, a.stash_cap, n_stash, a.pending, n_pend, k, &word, false);
     }
     if (op == OP_LOOKUP) {
       if (slot) {
@@ -524,7 +531,7 @@ __device__ __forceinline__ void ops_tile(const OpsArgs &a, const OpsView &view, 
           break;
         }
         atomicOr(&a.ctl->error, ERR_CAS_RETRY);
-        slot = overflow_find(a.stash, n_stash, a.pending, n_pend, k, &word, true);
+        slot = overflow_find(a.stash, a.stash_cap, n_stash, a.pending, n_pend, k, &word, true);
       }
       if (op == OP_DELETE && done) {
         out_f = 1;
@@ -613,16 +620,22 @@ struct EvictArgs {
 
 __device__ __forceinline__ void set_hint(uint32_t *hint, uint32_t b) { or32(&hint[b >> 5], 1u << (b & 31)); }
 
-// Step 4: the item goes to the stash ring, or to the pending list when the
-// ring is full.  A slot is reserved with one fetch-add (the counts may pass
-// their capacities; every reader clamps them), so simultaneous pushes cost
-// one atomic each instead of a retry loop.
+// Step 4: the item goes to the stash, or to the pending list when the stash
+// is full.  Room is reserved with one fetch-add on the count (the counts may
+// pass their capacities; every reader clamps them), so simultaneous pushes
+// cost one atomic each; then the entry claims the first EMPTY word of its
+// probe run by CAS (one exists: the table has at least twice the capacity).
 __device__ __forceinline__ void overflow_push(const EvictArgs &a, const Geo &geo, uint64_t kv) {
   bool stashed = false;
   const uint64_t c = load_fresh(&a.ctl->stash_count) < a.stash_cap ? add64(&a.ctl->stash_count, 1) : a.stash_cap;
   if (c < a.stash_cap) {
-    __hip_atomic_store(a.stash + c, kv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    stashed = true;
+    const uint64_t mask = stash_slots_for(a.stash_cap) - 1;
+    for (uint64_t i = 0, p = mix32(key_of(kv)) & mask; i <= mask; ++i, p = (p + 1) & mask) {
+      if (cas64(a.stash + p, EMPTY, kv) == EMPTY) {
+        stashed = true;
+        break;
+      }
+    }
   }
   if (stashed) {
     add64(&a.ctl->stash_inserts, 1);
@@ -1041,16 +1054,19 @@ __global__ __launch_bounds__(BLOCK) void resize_pass2_kernel(ResizeArgs a) {
 // After splits: every stash and pending entry moves to the eviction worklist
 // (the eviction phase re-places it under the new geometry) and the hint bits
 // are cleared (Section III-B "Overflow Stash").  One wave-aggregated append
-// per wave and item range; `t` indexes stash entries then pending entries,
-// and the 256-entry tile t / 256 picks the worklist segment.
-__device__ __forceinline__ void drain_collect(uint64_t t, uint64_t n_stash, uint64_t total, const uint64_t *stash,
+// per wave and item range; `t` indexes stash words (the whole table, which
+// is reset to EMPTY on the way) then pending entries, and the 256-entry tile
+// t / 256 picks the worklist segment.
+__device__ __forceinline__ void drain_collect(uint64_t t, uint64_t n_stash_words, uint64_t total, uint64_t *stash,
                                               const uint64_t *pending, uint64_t *wl, uint64_t seg_cap, Ctl *c) {
   uint64_t w = TOMB;
-  if (t < n_stash)
+  if (t < n_stash_words) {
     w = stash[t];
-  else if (t < total)
-    w = pending[t - n_stash];
-  const bool live = w != TOMB;
+    if (w != EMPTY) stash[t] = EMPTY;
+  } else if (t < total) {
+    w = pending[t - n_stash_words];
+  }
+  const bool live = w != TOMB && w != EMPTY;
   const uint64_t m = ballot(live);
   if (m) {
     const int lane = threadIdx.x & 63;
@@ -1073,7 +1089,7 @@ __global__ __launch_bounds__(BLOCK) void drain_kernel(uint64_t *stash, uint64_t 
                                                       uint64_t pending_cap, uint32_t *hint, uint64_t hint_n,
                                                       uint64_t *wl, uint64_t seg_cap, Ctl *c) {
   if (!c->split_happened) return;
-  const uint64_t n_stash = min(c->stash_count, stash_cap);
+  const uint64_t n_stash = min(c->stash_count, stash_cap) ? stash_slots_for(stash_cap) : 0;
   const uint64_t n_pend = min(c->pending_count, pending_cap);
   const uint64_t total = n_stash + n_pend;
   const uint64_t stride = (uint64_t)gridDim.x * BLOCK;
@@ -1094,7 +1110,7 @@ __global__ __launch_bounds__(BLOCK) void dump_kernel(const uint64_t *buckets, ui
                                                      uint64_t pending_cap, uint64_t *out, int64_t *where,
                                                      uint64_t cap) {
   const uint64_t nb = ctl->n_buckets;
-  const uint64_t n_stash = min(ctl->stash_count, stash_cap);
+  const uint64_t n_stash = min(ctl->stash_count, stash_cap) ? stash_slots_for(stash_cap) : 0;
   const uint64_t n_pend = min(ctl->pending_count, pending_cap);
   const uint64_t n_slots = nb * S, total = n_slots + n_stash + n_pend;
   const uint64_t stride = (uint64_t)gridDim.x * BLOCK;
@@ -1335,7 +1351,8 @@ __device__ __forceinline__ uint64_t enter(volatile ReqState *r, const ReqDesc &d
     case PH_SEG_A: return ceil_div(r->seg_n, gpb);
     case PH_SEG_B: return ceil_div(c->merge_commit, gpb);
     case PH_DRAIN: {
-      const uint64_t total = min(c->stash_count, d.t.stash_cap) + min(c->pending_count, d.t.pending_cap);
+      const uint64_t total = (min(c->stash_count, d.t.stash_cap) ? stash_slots_for(d.t.stash_cap) : 0) +
+                             min(c->pending_count, d.t.pending_cap);
       return total ? max(ceil_div(total, BLOCK), ceil_div(d.t.hint_words, FILL_PER_CHUNK)) : 0;
     }
     case PH_REPLACE:
@@ -1539,7 +1556,7 @@ __device__ void run_chunk(ReqState *r, const ReqDesc &d, uint32_t ph, uint64_t c
     }
     case PH_DRAIN: {
       const Ctl *cc = d.t.ctl;
-      const uint64_t n_stash = min(ld_ctl(&cc->stash_count), d.t.stash_cap);
+      const uint64_t n_stash = min(ld_ctl(&cc->stash_count), d.t.stash_cap) ? stash_slots_for(d.t.stash_cap) : 0;
       const uint64_t total = n_stash + min(ld_ctl(&cc->pending_count), d.t.pending_cap);
       const uint64_t hb = c * FILL_PER_CHUNK, he = min(hb + FILL_PER_CHUNK, d.t.hint_words);
       for (uint64_t t = hb + threadIdx.x; t < he; t += BLOCK) d.t.hint[t] = 0u;
@@ -1777,6 +1794,7 @@ static hive_status reset_table(hive_table *h, hipStream_t st) {
   hive_status s;
   if ((s = fill_u64(h->d_buckets, h->max_buckets * h->S, EMPTY, st)) != HIVE_OK) return s;
   if ((s = fill_u32(h->d_hint, hint_words(h->max_buckets), 0u, st)) != HIVE_OK) return s;
+  if ((s = fill_u64(h->d_stash, stash_slots_for(h->stash_cap), EMPTY, st)) != HIVE_OK) return s;
   if ((s = fill_u64((uint64_t *)shard_of(h->d_ctl, 0), NSHARD * SHARD_STRIDE / 8, 0, st)) != HIVE_OK) return s;
   hipLaunchKernelGGL(ctl_reset_kernel, dim3(1), dim3(1), 0, st, h->d_ctl, initial_ctl(h));
   return launch_check();
@@ -1912,7 +1930,7 @@ static hive_status resize_sequence(hive_table *h, uint32_t mode, uint64_t amount
   }
   hipLaunchKernelGGL(drain_kernel, dim3(DRAIN_GRID), dim3(BLOCK), 0, st, h->d_stash, h->stash_cap, h->d_pending,
                      h->pending_cap, h->d_hint, hint_words(h->max_buckets), h->d_wl, h->wl_seg_cap, h->d_ctl);
-  launch_evict(h, h->stash_cap + h->pending_cap, st);
+  launch_evict(h, h->stash_cap + h->pending_cap, st);  // live entries of a drain
   launch_finish(h, st);
   return launch_check();
 }
@@ -2095,7 +2113,8 @@ hive_status hive_create(const hive_config *cfg_in, uint64_t initial_buckets, voi
   h->S = S;
   h->initial_buckets = initial_buckets;
   h->max_buckets = max_b;
-  h->stash_cap = cfg.stash_capacity ? cfg.stash_capacity : std::max<uint64_t>(1024, initial_buckets * S / 100);
+  // default: 1% of the slots of the largest table (the arena)
+  h->stash_cap = cfg.stash_capacity ? cfg.stash_capacity : std::max<uint64_t>(1024, max_b * S / 100);
   h->pending_cap = cfg.pending_capacity ? cfg.pending_capacity : h->stash_cap;
   cfg.stash_capacity = h->stash_cap;
   cfg.pending_capacity = h->pending_cap;
@@ -2104,7 +2123,7 @@ hive_status hive_create(const hive_config *cfg_in, uint64_t initial_buckets, voi
   hive_status s = HIVE_OK;
   if ((s = alloc((void **)&h->d_buckets, max_b * S * 8, &h->bytes)) != HIVE_OK ||
       (s = alloc((void **)&h->d_hint, hint_words(max_b) * 4, &h->bytes)) != HIVE_OK ||
-      (s = alloc((void **)&h->d_stash, h->stash_cap * 8, &h->bytes)) != HIVE_OK ||
+      (s = alloc((void **)&h->d_stash, stash_slots_for(h->stash_cap) * 8, &h->bytes)) != HIVE_OK ||
       (s = alloc((void **)&h->d_pending, h->pending_cap * 8, &h->bytes)) != HIVE_OK ||
       (s = alloc((void **)&h->d_ctl, CTL_BYTES, &h->bytes)) != HIVE_OK) {
     free_table(h);
@@ -2112,8 +2131,9 @@ hive_status hive_create(const hive_config *cfg_in, uint64_t initial_buckets, voi
   }
   hipStream_t st = (hipStream_t)stream;
   h->last = st;
-  // the worklist must hold a full stash + pending drain (after a split)
-  const uint64_t min_wl = h->stash_cap + h->pending_cap;
+  // the worklist must hold a full stash + pending drain (after a split);
+  // the drain walks the whole stash table
+  const uint64_t min_wl = stash_slots_for(h->stash_cap) + h->pending_cap;
   if ((s = ensure_scratch(h, std::max<uint64_t>(cfg.max_batch, min_wl), cfg.max_batch > 0, st)) != HIVE_OK) {
     free_table(h);
     return s;

@@ -220,6 +220,16 @@ __device__ __forceinline__ uint32_t or32(uint32_t *p, uint32_t v) {
   return __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// The stash as an open-addressed table of words: at least twice its entry
+// capacity, so that (the count of used slots, tombstones included, never
+// exceeds the capacity) linear-probe runs stay short and an EMPTY word
+// always ends a search.
+__host__ __device__ __forceinline__ uint64_t stash_slots_for(uint64_t cap) {
+  uint64_t s = 16;
+  while (s < 2 * cap) s <<= 1;
+  return s;
+}
+
 // Mix for the per-batch dedupe set and the eviction victim choice: the
 // "lowbias32" integer hash published by C. Wellons (hash-prospector, 2018).
 // It is not one of the bucket hashes, so it is independent of placement.
