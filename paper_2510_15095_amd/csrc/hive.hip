@@ -183,11 +183,14 @@ __global__ __launch_bounds__(BLOCK) void fill_u32_kernel(uint32_t *p, uint64_t n
   for (uint64_t t = (uint64_t)blockIdx.x * BLOCK + threadIdx.x; t < n; t += (uint64_t)gridDim.x * BLOCK) p[t] = v;
 }
 
-__device__ __forceinline__ void dedupe_insert(uint64_t *dd, uint64_t mask, uint32_t mode, const uint8_t *ops,
-                                              const uint32_t *keys, uint64_t i) {
-  const uint32_t op = (mode == OP_MIXED) ? ops[i] : mode;
+// Record operation i (of type `op`) in the set.  Plain loads come first:
+// a key already present costs no CAS, and an index that cannot win costs no
+// max/min atomic (a stale load is only ever an older value, which would
+// already beat i, so the skip is safe).
+__device__ __forceinline__ void dedupe_insert(uint64_t *dd, uint64_t mask, uint32_t op, const uint32_t *keys,
+                                              uint64_t i) {
   const uint32_t k = keys[i];
-  if (op > OP_DELETE || !valid_key(k)) return;
+  if (!valid_key(k)) return;
   const uint64_t e = ((uint64_t)k << 32) | (uint32_t)i;
   uint64_t s = mix32(k) & mask;
   for (uint64_t probe = 0; probe <= mask; ++probe) {
@@ -197,20 +200,33 @@ __device__ __forceinline__ void dedupe_insert(uint64_t *dd, uint64_t mask, uint3
       if (cur == EMPTY) return;
     }
     if ((uint32_t)(cur >> 32) == k) {
-      if (op == OP_INSERT)
-        __hip_atomic_fetch_max(&dd[s], e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      else
+      if (op == OP_INSERT) {
+        if (cur < e) __hip_atomic_fetch_max(&dd[s], e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      } else if (cur > e) {
         __hip_atomic_fetch_min(&dd[s], e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
       return;
     }
     s = (s + 1) & mask;
   }
 }
 
+// Thread t records operation n-1-t if it is an insert and operation t if it
+// is a delete: blocks start roughly in order, so inserts arrive in falling
+// index order (the winner, the last, comes first) and deletes in rising
+// order (the first comes first), and repeated hot keys mostly skip their
+// atomics.
+__device__ __forceinline__ void dedupe_thread(uint64_t *dd, uint64_t mask, uint32_t mode, const uint8_t *ops,
+                                              const uint32_t *keys, uint64_t n, uint64_t t) {
+  if (t >= n) return;
+  const uint64_t ii = n - 1 - t;
+  if (mode == OP_INSERT || (mode == OP_MIXED && ops[ii] == OP_INSERT)) dedupe_insert(dd, mask, OP_INSERT, keys, ii);
+  if (mode == OP_DELETE || (mode == OP_MIXED && ops[t] == OP_DELETE)) dedupe_insert(dd, mask, OP_DELETE, keys, t);
+}
+
 __global__ __launch_bounds__(BLOCK) void dedupe_build_kernel(uint64_t *dd, uint64_t mask, uint32_t mode,
                                                              const uint8_t *ops, const uint32_t *keys, uint64_t n) {
-  const uint64_t i = (uint64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (i < n) dedupe_insert(dd, mask, mode, ops, keys, i);
+  dedupe_thread(dd, mask, mode, ops, keys, n, (uint64_t)blockIdx.x * BLOCK + threadIdx.x);
 }
 
 __device__ __forceinline__ bool dedupe_winner(const uint64_t *dd, uint64_t mask, uint32_t k, uint32_t i) {
@@ -1459,8 +1475,12 @@ __device__ void ingest(DrainQueue *q) {
   __hip_atomic_store(&q->ingest_lock, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Claim a chunk of runnable work.  Returns 0 (work), 1 (none now), 2 (exit).
-__device__ uint32_t find_work(DrainQueue *q, uint64_t *req, uint32_t *phase, uint64_t *chunk, uint64_t *nch) {
+// Claim a run of chunks of runnable work: `*chunk` is the first, `*count`
+// how many (a phase of n chunks is claimed in grains of about n / (4 x grid)
+// chunks, so a large phase costs few atomics on the request's state word).
+// Returns 0 (work), 1 (none now), 2 (exit).
+__device__ uint32_t find_work(DrainQueue *q, uint64_t *req, uint32_t *phase, uint64_t *chunk, uint64_t *count,
+                              uint64_t *nch) {
   ingest(q);
   const uint64_t ing = ld_ctl(&q->ingested);
   uint64_t head = ld_ctl(&q->head);
@@ -1487,12 +1507,14 @@ __device__ uint32_t find_work(DrainQueue *q, uint64_t *req, uint32_t *phase, uin
     if (ph == PH_DONE || (st & M28) >= ((st >> 28) & M28)) continue;
     const uint64_t slot = ld_ctl(&r->d.table_slot), seq = ld_ctl(&r->d.seq);
     if (ld_ctl(&q->table_next[slot]) != seq) continue;
-    const uint64_t old = add64(&r->state, 1);
+    const uint64_t grain = max(1ull, ((st >> 28) & M28) / (4ull * gridDim.x));
+    const uint64_t old = add64(&r->state, grain);
     const uint64_t n = (old >> 28) & M28, c = old & M28;
     if ((uint32_t)(old >> 56) == PH_DONE || c >= n) continue;
     *req = t;
     *phase = (uint32_t)(old >> 56);
     *chunk = c;
+    *count = min(grain, n - c);
     *nch = n;
     return 0;
   }
@@ -1507,7 +1529,7 @@ __device__ __forceinline__ void load_desc(ReqDesc *dst, const ReqDesc *src) {
 }
 
 template <int S>
-__device__ void run_chunk(ReqState *r, const ReqDesc &d, uint32_t ph, uint64_t c, OpsShared<S> &sh) {
+__device__ __forceinline__ void run_chunk(ReqState *r, const ReqDesc &d, uint32_t ph, uint64_t c, OpsShared<S> &sh) {
   using T = Traits<S>;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = lane / S, sl = lane % S;
@@ -1520,8 +1542,7 @@ __device__ void run_chunk(ReqState *r, const ReqDesc &d, uint32_t ph, uint64_t c
       break;
     }
     case PH_DEDUPE: {
-      const uint64_t i = c * BLOCK + threadIdx.x;
-      if (i < d.n) dedupe_insert(d.t.dd, d.dd_size - 1, d.mode, d.ops, d.keys, i);
+      dedupe_thread(d.t.dd, d.dd_size - 1, d.mode, d.ops, d.keys, d.n, c * BLOCK + threadIdx.x);
       break;
     }
     case PH_COUNT: {
@@ -1623,7 +1644,7 @@ template <int S>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void drain_worker_kernel(DrainQueue *q) {
   __shared__ OpsShared<S> sh;
   __shared__ ReqDesc desc;
-  __shared__ uint64_t s_req, s_chunk, s_nch;
+  __shared__ uint64_t s_req, s_chunk, s_cnt, s_nch;
   __shared__ uint32_t s_phase, s_cmd;
   __shared__ bool s_last;
   // watchdog (thread 0 decides for the block): time without any progress
@@ -1634,7 +1655,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
   const uint64_t idle_ticks = ld_ctl(&q->idle_ticks);
   for (;;) {
     if (threadIdx.x == 0) {
-      uint32_t cmd = find_work(q, &s_req, &s_phase, &s_chunk, &s_nch);
+      uint32_t cmd = find_work(q, &s_req, &s_phase, &s_chunk, &s_cnt, &s_nch);
       if (cmd == 1) {
         const uint64_t ing = ld_ctl(&q->ingested), head = ld_ctl(&q->head);
         const uint64_t now = wall_clock64();
@@ -1662,11 +1683,13 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
     ReqState *r = q->req + s_req % q->cap;
     load_desc(&desc, &r->d);
     __syncthreads();
-    run_chunk<S>(r, desc, s_phase, s_chunk, sh);
-    __syncthreads();
+    for (uint64_t k = 0; k < s_cnt; ++k) {
+      run_chunk<S>(r, desc, s_phase, s_chunk + k, sh);
+      __syncthreads();
+    }
     if (threadIdx.x == 0) {
-      __threadfence();  // this chunk's writes before its completion count
-      s_last = add64(&r->done, 1) + 1 == s_nch;
+      __threadfence();  // these chunks' writes before their completion count
+      s_last = add64(&r->done, s_cnt) + s_cnt == s_nch;
     }
     __syncthreads();
     if (s_last) {
