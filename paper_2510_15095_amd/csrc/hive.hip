@@ -637,13 +637,13 @@ struct EvictArgs {
 __device__ __forceinline__ void set_hint(uint32_t *hint, uint32_t b) { or32(&hint[b >> 5], 1u << (b & 31)); }
 
 // Step 4: the item goes to the stash, or to the pending list when the stash
-// is full.  Room is reserved with one fetch-add on the count (the counts may
-// pass their capacities; every reader clamps them), so simultaneous pushes
-// cost one atomic each; then the entry claims the first EMPTY word of its
-// probe run by CAS (one exists: the table has at least twice the capacity).
-__device__ __forceinline__ void overflow_push(const EvictArgs &a, const Geo &geo, uint64_t kv) {
+// is full.  Room is reserved by a fetch-add on the count, one per wave for
+// all of its pushes (the counts may pass their capacities; every reader
+// clamps them); given its reserved position c (c >= capacity: pending), the
+// entry claims the first EMPTY word of its probe run by CAS (one exists: the
+// table has at least twice the capacity).
+__device__ __forceinline__ void overflow_place(const EvictArgs &a, const Geo &geo, uint64_t kv, uint64_t c) {
   bool stashed = false;
-  const uint64_t c = load_fresh(&a.ctl->stash_count) < a.stash_cap ? add64(&a.ctl->stash_count, 1) : a.stash_cap;
   if (c < a.stash_cap) {
     const uint64_t mask = stash_slots_for(a.stash_cap) - 1;
     for (uint64_t i = 0, p = mix32(key_of(kv)) & mask; i <= mask; ++i, p = (p + 1) & mask) {
@@ -696,11 +696,10 @@ __device__ __forceinline__ bool group_claim(uint64_t *bkt, typename Traits<S>::M
 // An item still in hand after max_evictions displacements goes to the stash
 // ring, or to the pending list when the ring is full.
 template <int S>
-__device__ __forceinline__ void evict_item(const EvictArgs &a, const Geo &geo, uint64_t pos, int g, int sl,
-                                           uint64_t &n_evict, uint64_t &n_full) {
+__device__ __forceinline__ bool evict_chain(const EvictArgs &a, const Geo &geo, uint64_t &kv, uint32_t max_kicks,
+                                            int g, int sl, uint64_t &n_evict) {
   using T = Traits<S>;
   using Mask = typename T::Mask;
-  uint64_t kv = a.wl[pos];
   const uint32_t c1 = address(geo, bithash1(key_of(kv))), c2 = address(geo, bithash2(key_of(kv)));
   // step 2 with fresh loads (fresh: other items of this phase change buckets)
   const uint64_t w1 = load_fresh(a.buckets + (uint64_t)c1 * S + sl);
@@ -715,7 +714,7 @@ __device__ __forceinline__ void evict_item(const EvictArgs &a, const Geo &geo, u
     placed = group_claim<S>(a.buckets + (uint64_t)c1 * S, f1, kv, g, sl) ||
              group_claim<S>(a.buckets + (uint64_t)c2 * S, f2, kv, g, sl);
   uint32_t b = c1;  // chains start at the first candidate
-  for (uint32_t kick = 1; kick <= a.max_evictions && !placed; ++kick) {
+  for (uint32_t kick = 1; kick <= max_kicks && !placed; ++kick) {
     uint64_t *bkt = a.buckets + (uint64_t)b * S;
     const uint64_t w = load_fresh(bkt + sl);
     const Mask fm = (Mask)((ballot(w == EMPTY) >> (g * S)) & T::FULL);
@@ -746,9 +745,38 @@ __device__ __forceinline__ void evict_item(const EvictArgs &a, const Geo &geo, u
     const uint32_t v2 = address(geo, bithash2(key_of(kv)));
     b = (b == v1) ? v2 : v1;  // AltBucket: the victim's other candidate
   }
-  if (!placed && sl == 0) {
-    ++n_full;
-    overflow_push(a, geo, kv);
+  return placed;  // if not, kv is the entry in hand
+}
+
+// One item per group of the wave (`have`: the group has one, at worklist
+// position `pos`); every lane of the wave calls it.  Each item takes step 2
+// (two-choice claim on fresh loads) and the bounded chain of Algorithm 3;
+// an entry still in hand goes to the stash, with one count reservation per
+// wave for all of its groups.
+template <int S>
+__device__ __forceinline__ void evict_round(const EvictArgs &a, const Geo &geo, bool have, uint64_t pos, int g,
+                                            int sl, uint64_t &n_evict, uint64_t &n_full) {
+  uint64_t kv = 0;
+  bool placed = true;
+  if (have) {
+    kv = a.wl[pos];
+    placed = evict_chain<S>(a, geo, kv, a.max_evictions, g, sl, n_evict);
+  }
+  const bool push = !placed && sl == 0;
+  const uint64_t pm = ballot(push);
+  if (pm) {
+    const int lane = threadIdx.x & 63;
+    const int leader = __builtin_ctzll(pm);
+    uint64_t base = 0;
+    if (lane == leader) {
+      const uint64_t n = (uint64_t)__popcll(pm);
+      base = load_fresh(&a.ctl->stash_count) < a.stash_cap ? add64(&a.ctl->stash_count, n) : a.stash_cap;
+    }
+    base = read_lane64(base, leader);
+    if (push) {
+      ++n_full;
+      overflow_place(a, geo, kv, base + rank_below(pm));
+    }
   }
 }
 
@@ -786,11 +814,11 @@ __global__ __launch_bounds__(BLOCK) void evict_kernel(EvictArgs a) {
   const uint64_t groups = (uint64_t)gridDim.x * WAVES * T::G;
   uint64_t n_evict = 0, n_full = 0;
   const uint64_t first = ((uint64_t)blockIdx.x * WAVES + wv) * T::G + g;
-  // a uniform trip count per wave, so that every lane reaches the counters
+  // a uniform trip count per wave: every lane reaches the wave-wide steps
   const uint64_t wave_first = ((uint64_t)blockIdx.x * WAVES + wv) * T::G;
   for (uint64_t base = wave_first; base < cnt; base += groups) {
     const uint64_t t = base - wave_first + first;
-    if (t < cnt) evict_item<S>(a, geo, wl_slot(pre, t, a.wl_seg_cap), g, sl, n_evict, n_full);
+    evict_round<S>(a, geo, t < cnt, t < cnt ? wl_slot(pre, t, a.wl_seg_cap) : 0, g, sl, n_evict, n_full);
   }
   evict_counters(a, (uint64_t)blockIdx.x * WAVES + wv, n_evict, n_full, sl);
 }
@@ -1595,7 +1623,7 @@ __device__ __forceinline__ void run_chunk(ReqState *r, const ReqDesc &d, uint32_
       uint64_t n_evict = 0, n_full = 0;
       for (uint64_t k = 0; k < EVICT_PER_GROUP; ++k) {
         const uint64_t t = (c * EVICT_PER_GROUP + k) * gpb + gib;
-        if (t < items) evict_item<S>(ea, geo, wl_slot(pre, t, d.t.wl_seg_cap), g, sl, n_evict, n_full);
+        evict_round<S>(ea, geo, t < items, t < items ? wl_slot(pre, t, d.t.wl_seg_cap) : 0, g, sl, n_evict, n_full);
       }
       evict_counters(ea, c * WAVES + wv, n_evict, n_full, sl);
       break;
@@ -1908,7 +1936,7 @@ static void launch_ops_mode(uint32_t mode, const OpsArgs &a, hipStream_t st) {
 // a group); `max_items` bounds the worklist (the batch's inserts, or the
 // stash and pending capacity for a drain).
 static void launch_evict(hive_table *h, uint64_t max_items, hipStream_t st) {
-  EvictArgs e{h->d_buckets, h->d_hint,       h->d_stash, h->d_pending,  h->d_ctl,
+  EvictArgs e{h->d_buckets, h->d_hint,       h->d_stash,   h->d_pending,   h->d_ctl,
               h->d_wl,      h->wl_seg_cap,   h->stash_cap, h->pending_cap, h->cfg.max_evictions};
   const dim3 grid(grid_for(max_items, (uint64_t)WAVES * (64 / h->S), EVICT_GRID));
   switch (h->S) {
