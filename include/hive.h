@@ -230,13 +230,15 @@ hive_status hive_drain_create(uint32_t slots_per_bucket, uint32_t blocks_per_cu,
  * a stopped executor grows the scratch instead. */
 hive_status hive_drain_submit(hive_drain_t d, hive_t table, const hive_batch_desc *b, uint64_t *ticket);
 
-/* Launch the grid on `stream` (resident = 0); it exits once every batch it
- * has taken in is complete.  Batches submitted while it runs are taken in
- * until it has seen the last submission; a later launch (on the same
- * stream, so after this one) serves the rest, so a serving loop relaunches
- * when the previous grid has finished and batches are still pending.
- * resident = 1 (a grid that keeps serving until hive_drain_stop) is switched
- * off in this build and returns HIVE_ERR_ARG. */
+/* Launch the grid.  resident = 0: on `stream`; it exits once every batch it
+ * has taken in is complete (batches submitted while it runs are taken in
+ * until it has seen the last submission; a later launch serves the rest).
+ * resident = 1: on the executor's own non-blocking stream, after the work
+ * already enqueued on `stream`; it keeps serving batches submitted later
+ * until hive_drain_stop, and holds up no other stream meanwhile (device
+ * memory the batches use must be allocated before the launch).  A resident
+ * grid leaves one block's room per compute unit free, so that other kernels
+ * of the process (copies included) can run while it waits. */
 hive_status hive_drain_launch(hive_drain_t d, int resident, void *stream);
 
 /* *done = 1 once the batch's outputs and table updates are complete and

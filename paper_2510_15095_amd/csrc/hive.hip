@@ -1762,7 +1762,7 @@ struct hive_drain {
   uint32_t S = 16;
   uint64_t cap = 0;
   uint32_t max_tables = 0;
-  unsigned grid = 0;
+  unsigned grid[2] = {0, 0};  // blocks of a launch: [0] draining, [1] resident
   DrainQueue *d_q = nullptr;
   ReqState *d_req = nullptr;
   uint64_t *d_table_next = nullptr;
@@ -1777,8 +1777,8 @@ struct hive_drain {
   uint64_t next_seq[4096];
   uint32_t n_tables = 0;
   hipStream_t capture = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
   hipStream_t running_on = nullptr;
   bool running = false;
 };
@@ -1992,8 +1992,10 @@ static hive_status resize_sequence(hive_table *h, uint32_t mode, uint64_t amount
 // ---------------------------------------------------------------------------
 static void free_drain(hive_drain *d) {
   if (!d) return;
-  if (d->exec) (void)hipGraphExecDestroy(d->exec);
-  if (d->graph) (void)hipGraphDestroy(d->graph);
+  for (int m = 0; m < 2; ++m) {
+    if (d->exec[m]) (void)hipGraphExecDestroy(d->exec[m]);
+    if (d->graph[m]) (void)hipGraphDestroy(d->graph[m]);
+  }
   if (d->capture) (void)hipStreamDestroy(d->capture);
   (void)hipFree(d->d_q);
   (void)hipFree(d->d_req);
@@ -2032,28 +2034,35 @@ static hive_status wall_clock_rate(double *ticks_per_us) {
   return HIVE_OK;
 }
 
+// Grid sizes.  A draining grid may fill every CU: it exits once its work is
+// done.  A resident grid waits for work that the host has not submitted yet,
+// and the host may first need other kernels to run (its own copies: HIP runs
+// small pageable copies as kernels); with every CU's registers held by the
+// polling grid such a kernel cannot start until the grid exits.  So a
+// resident grid takes one block per CU fewer than fit (at least one).
 template <int S>
-static hive_status drain_grid(uint32_t blocks_per_cu, unsigned *grid) {
+static hive_status drain_grid(uint32_t blocks_per_cu, unsigned grid[2]) {
   int dev = 0, cus = 0, per_cu = 0;
   HIP_OK(hipGetDevice(&dev));
   HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, drain_worker_kernel<S>, BLOCK, 0));
   if (per_cu < 1) return HIVE_ERR_HIP;
   const unsigned want = blocks_per_cu ? blocks_per_cu : (unsigned)per_cu;
-  *grid = (unsigned)cus * std::min<unsigned>(want, (unsigned)per_cu);
+  grid[0] = (unsigned)cus * std::min<unsigned>(want, (unsigned)per_cu);
+  grid[1] = (unsigned)cus * std::min<unsigned>(want, (unsigned)std::max(1, per_cu - 1));
   return HIVE_OK;
 }
 
 template <int S>
-static void launch_drain_kernel(hive_drain *d, hipStream_t st) {
-  hipLaunchKernelGGL(drain_worker_kernel<S>, dim3(d->grid), dim3(BLOCK), 0, st, d->d_q);
+static void launch_drain_kernel(hive_drain *d, int mode, hipStream_t st) {
+  hipLaunchKernelGGL(drain_worker_kernel<S>, dim3(d->grid[mode]), dim3(BLOCK), 0, st, d->d_q);
 }
 
-static void launch_drain_any(hive_drain *d, hipStream_t st) {
+static void launch_drain_any(hive_drain *d, int mode, hipStream_t st) {
   switch (d->S) {
-    case 16: launch_drain_kernel<16>(d, st); break;
-    case 32: launch_drain_kernel<32>(d, st); break;
-    default: launch_drain_kernel<64>(d, st); break;
+    case 16: launch_drain_kernel<16>(d, mode, st); break;
+    case 32: launch_drain_kernel<32>(d, mode, st); break;
+    default: launch_drain_kernel<64>(d, mode, st); break;
   }
 }
 
@@ -2358,9 +2367,9 @@ hive_status hive_drain_create(uint32_t slots_per_bucket, uint32_t blocks_per_cu,
   d->max_tables = max_tables;
   hive_status s = HIVE_OK;
   switch (d->S) {
-    case 16: s = drain_grid<16>(blocks_per_cu, &d->grid); break;
-    case 32: s = drain_grid<32>(blocks_per_cu, &d->grid); break;
-    default: s = drain_grid<64>(blocks_per_cu, &d->grid); break;
+    case 16: s = drain_grid<16>(blocks_per_cu, d->grid); break;
+    case 32: s = drain_grid<32>(blocks_per_cu, d->grid); break;
+    default: s = drain_grid<64>(blocks_per_cu, d->grid); break;
   }
   if (s != HIVE_OK) {
     free_drain(d);
@@ -2493,9 +2502,7 @@ hive_status hive_drain_submit(hive_drain_t d, hive_t h, const hive_batch_desc *b
 
 hive_status hive_drain_launch(hive_drain_t d, int resident, void *stream) {
   if (!d || d->running) return HIVE_ERR_ARG;
-  // a resident grid serving submissions that arrive while it runs left a
-  // batch unfinished in testing, cause not yet found: switched off
-  if (resident) return HIVE_ERR_ARG;
+  const int mode = resident ? 1 : 0;
   hipStream_t user = (hipStream_t)stream;
   // a resident grid runs on the executor's own non-blocking stream, after the
   // work already enqueued on `stream`, so it holds up no other stream
@@ -2511,20 +2518,20 @@ hive_status hive_drain_launch(hive_drain_t d, int resident, void *stream) {
   // the grid of the previous launch has exited; clear its exit flag
   hipLaunchKernelGGL(drain_reset_kernel, dim3(1), dim3(1), 0, st, d->d_q);
   HIP_OK(hipGetLastError());
-  if (!d->exec) {
-    // the launch is captured once; replays read everything dynamic from the
-    // queue in memory
+  if (!d->exec[mode]) {
+    // each launch form is captured once; replays read everything dynamic
+    // from the queue in memory
     HIP_OK(hipStreamBeginCapture(d->capture, hipStreamCaptureModeRelaxed));
-    launch_drain_any(d, d->capture);
+    launch_drain_any(d, mode, d->capture);
     hipError_t e = hipGetLastError();
-    hipError_t e2 = hipStreamEndCapture(d->capture, &d->graph);
+    hipError_t e2 = hipStreamEndCapture(d->capture, &d->graph[mode]);
     if (e != hipSuccess || e2 != hipSuccess) {
       fprintf(stderr, "hive: drain graph capture failed: %s / %s\n", hipGetErrorString(e), hipGetErrorString(e2));
       return HIVE_ERR_HIP;
     }
-    HIP_OK(hipGraphInstantiate(&d->exec, d->graph, nullptr, nullptr, 0));
+    HIP_OK(hipGraphInstantiate(&d->exec[mode], d->graph[mode], nullptr, nullptr, 0));
   }
-  HIP_OK(hipGraphLaunch(d->exec, st));
+  HIP_OK(hipGraphLaunch(d->exec[mode], st));
   d->running = resident != 0;
   d->running_on = st;
   return HIVE_OK;

@@ -5,11 +5,9 @@ one of many tables.  The server admits a request when a slot is free and its
 table has room for the request's inserts inside the table's HBM reservation
 (its bucket arena, resize headroom included), then runs it
 
-* on the persistent executor (`hive_drain_*`): admitted requests are staged
-  on the host; whenever the executor is idle the server submits every staged
-  request to its ring and launches it once, and that one grid drains them
-  all, requests on different tables overlapping on the device (continuous
-  batching by relaunch, not one launch per request); or
+* on the persistent executor (`hive_drain_*`): one resident grid, launched
+  once, takes each request as it is admitted (continuous batching: requests
+  on different tables overlap on the device, no launch per request); or
 * with plain per-request launches (`hive_mixed_batch`) spread over a pool of
   streams (a table always maps to the same stream, so its requests stay in
   order).
@@ -161,20 +159,19 @@ class Server:
         inflight_ins = [0] * len(self.specs)
         live = list(self.live)
         pending = []       # arrived, not yet admitted (FIFO)
-        inflight = {}      # rid -> completion handle (persistent: ticket, None while staged)
+        inflight = {}      # rid -> completion handle (persistent: ticket)
         nxt = 0
         deferred = 0
         if mode == "persistent":
             drain = H.hive_drain_create(16, 0, self.ring, len(self.specs), 0)
             side = torch.cuda.Stream()
-            grid_done = None  # event after the latest launch
+            H.hive_drain_launch(drain, 1, side)
             # a ticket's result stays readable until its ring slot is reused,
             # i.e. until `ring` later submissions: keep new tickets within
             # `ring` of the oldest unread one
             unread = collections.deque()
             read = set()
             n_submitted = 0
-            staged = collections.deque()
         elif mode == "plain":
             events = {}
             live_pinned = torch.zeros(n, dtype=torch.int64).pin_memory()
@@ -200,8 +197,16 @@ class Server:
                     o_, k_, v_ = dev[r.rid]
                     h = self.tables[r.table].h
                     if mode == "persistent":
-                        inflight[r.rid] = None
-                        staged.append(r.rid)
+                        while unread and unread[0] in read:
+                            read.discard(unread.popleft())
+                        if unread and n_submitted - unread[0] >= self.ring:
+                            break
+                        tk = H.hive_drain_submit(drain, h, H.HIVE_OP_MIXED, k_, v_, o_, vout[r.rid], fout[r.rid])
+                        if tk is None:
+                            break
+                        n_submitted += 1
+                        unread.append(tk)
+                        inflight[r.rid] = tk
                     else:
                         st = self.streams[r.table % len(self.streams)]
                         H.hive_mixed_batch(h, o_, k_, v_, vout[r.rid], fout[r.rid], stream=st)
@@ -213,35 +218,9 @@ class Server:
                     admitted_at[r.rid] = time.perf_counter() - t0
                     inflight_ins[r.table] += r.n_ins
                     pending.pop(0)
-                # when the executor is idle: submit the staged requests and
-                # launch it once for all of them (nothing is submitted while
-                # a grid runs)
-                if mode == "persistent" and staged and (grid_done is None or grid_done.query()):
-                    while unread and unread[0] in read:
-                        read.discard(unread.popleft())
-                    launched = 0
-                    while staged and not (unread and n_submitted - unread[0] >= self.ring):
-                        rid = staged[0]
-                        r = requests[rid]
-                        o_, k_, v_ = dev[rid]
-                        tk = H.hive_drain_submit(drain, self.tables[r.table].h, H.HIVE_OP_MIXED, k_, v_, o_,
-                                                 vout[rid], fout[rid])
-                        if tk is None:
-                            break
-                        staged.popleft()
-                        n_submitted += 1
-                        unread.append(tk)
-                        inflight[rid] = tk
-                        launched += 1
-                    if launched:
-                        H.hive_drain_launch(drain, 0, side)
-                        grid_done = torch.cuda.Event()
-                        grid_done.record(side)
                 # completions
                 for rid in list(inflight):
                     if mode == "persistent":
-                        if inflight[rid] is None:
-                            continue  # staged, not yet submitted
                         ok, lv = H.hive_drain_result(drain, inflight[rid])
                         if ok:
                             read.add(inflight[rid])

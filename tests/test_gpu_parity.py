@@ -543,18 +543,6 @@ def test_drain_multi_table_linear_policies(H):
     H.hive_drain_destroy(d)
 
 
-def test_drain_resident_launch_is_refused(H):
-    """Resident launches are switched off: the call returns an argument
-    error and launches nothing."""
-    d = H.hive_drain_create(16, 0, 4, 4, 10_000_000)
-    with pytest.raises(H.HiveError):
-        H.hive_drain_launch(d, 1)
-    H.hive_drain_destroy(d)
-
-
-@pytest.mark.skip(reason="resident grid left a lookup batch unfinished after the shard-counter change "
-                         "(cause not found: the device clock rate was ruled out); resident launches are "
-                         "switched off until it is")
 def test_drain_resident_incremental_and_backpressure(H):
     """A resident grid serves batches submitted while it runs; a full ring
     refuses submissions until earlier batches complete."""
