@@ -669,20 +669,65 @@ __device__ __forceinline__ void overflow_place(const EvictArgs &a, const Geo &ge
   set_hint(a.hint, address(geo, bithash2(k)));
 }
 
-// Claim-then-commit by one 16-lane group (WABC): `free_mask` holds the
-// group's view of the bucket's EMPTY slots; the lowest one is claimed with
-// one CAS by its lane, and a failed CAS (the view was stale) drops that slot
-// and tries the next.  Returns true when the entry was committed.
+// Eviction group shape.  A group of L lanes works on one item and sees a
+// bucket as P adjacent slots per lane (L x P = S).  For S = 16 a lane holds
+// two slots, so a wave runs eight chains at once (chains are a sequence of
+// dependent memory round trips, so more chains per wave is more memory
+// parallelism); wider buckets keep one slot per lane.
+template <int S>
+struct EvictShape {
+  static constexpr int P = (S == 16) ? 2 : 1;
+  static constexpr int L = S / P;
+  static constexpr int G = 64 / L;  // items per wave
+  static constexpr uint64_t LANES = (L == 64) ? ~0ull : ((1ull << L) - 1ull);
+};
+
+__host__ __device__ __forceinline__ int evict_groups_per_wave(uint32_t S) { return S == 16 ? 8 : (int)(64 / S); }
+
+// Bits of slots s = l * P + p from per-word masks (bit l of m[p]).
+template <int P, typename Mask>
+__device__ __forceinline__ Mask interleave_slots(const uint64_t *m) {
+  if constexpr (P == 1) {
+    return (Mask)m[0];
+  } else {
+    uint32_t a = (uint32_t)m[0], b = (uint32_t)m[1];  // 8 bits each
+    a = (a | (a << 4)) & 0x0F0Fu;
+    a = (a | (a << 2)) & 0x3333u;
+    a = (a | (a << 1)) & 0x5555u;
+    b = (b | (b << 4)) & 0x0F0Fu;
+    b = (b | (b << 2)) & 0x3333u;
+    b = (b | (b << 1)) & 0x5555u;
+    return (Mask)(a | (b << 1));
+  }
+}
+
+// The group's fresh view of bucket `bkt`: words w[p] of slots sl * P + p,
+// and its EMPTY-slot mask.
+template <int S>
+__device__ __forceinline__ typename Traits<S>::Mask load_view(const uint64_t *bkt, int g, int sl, uint64_t *w) {
+  using E = EvictShape<S>;
+  uint64_t m[E::P];
+#pragma unroll
+  for (int p = 0; p < E::P; ++p) w[p] = load_fresh(bkt + sl * E::P + p);
+#pragma unroll
+  for (int p = 0; p < E::P; ++p) m[p] = (ballot(w[p] == EMPTY) >> (g * E::L)) & E::LANES;
+  return interleave_slots<E::P, typename Traits<S>::Mask>(m);
+}
+
+// Claim-then-commit by one group (WABC): `free_mask` holds the group's view
+// of the bucket's EMPTY slots; the lowest one is claimed with one CAS by the
+// lane holding it, and a failed CAS (the view was stale) drops that slot and
+// tries the next.  Returns true when the entry was committed.
 template <int S>
 __device__ __forceinline__ bool group_claim(uint64_t *bkt, typename Traits<S>::Mask free_mask, uint64_t kv, int g,
                                             int sl) {
-  using T = Traits<S>;
-  using Mask = typename T::Mask;
+  using E = EvictShape<S>;
+  using Mask = typename Traits<S>::Mask;
   while (free_mask) {
     const int s = ctz_mask(free_mask);
     bool won = false;
-    if (sl == s) won = cas64(bkt + s, EMPTY, kv) == EMPTY;
-    if ((Mask)((ballot(won) >> (g * S)) & T::FULL)) return true;
+    if (sl == s / E::P) won = cas64(bkt + s, EMPTY, kv) == EMPTY;
+    if ((ballot(won) >> (g * E::L)) & E::LANES) return true;
     free_mask &= (Mask)(free_mask - 1);
   }
   return false;
@@ -700,12 +745,12 @@ __device__ __forceinline__ bool evict_chain(const EvictArgs &a, const Geo &geo, 
                                             int g, int sl, uint64_t &n_evict) {
   using T = Traits<S>;
   using Mask = typename T::Mask;
+  using E = EvictShape<S>;
   const uint32_t c1 = address(geo, bithash1(key_of(kv))), c2 = address(geo, bithash2(key_of(kv)));
   // step 2 with fresh loads (fresh: other items of this phase change buckets)
-  const uint64_t w1 = load_fresh(a.buckets + (uint64_t)c1 * S + sl);
-  const uint64_t w2 = load_fresh(a.buckets + (uint64_t)c2 * S + sl);
-  const Mask f1 = (Mask)((ballot(w1 == EMPTY) >> (g * S)) & T::FULL);
-  const Mask f2 = (c2 != c1) ? (Mask)((ballot(w2 == EMPTY) >> (g * S)) & T::FULL) : (Mask)0;
+  uint64_t w[E::P], w2v[E::P];
+  const Mask f1 = load_view<S>(a.buckets + (uint64_t)c1 * S, g, sl, w);
+  const Mask f2 = load_view<S>(a.buckets + (uint64_t)c2 * S, g, sl, w2v) & (Mask)((c2 != c1) ? ~0ull : 0ull);
   bool placed;
   if (popc_mask(f2) > popc_mask(f1))
     placed = group_claim<S>(a.buckets + (uint64_t)c2 * S, f2, kv, g, sl) ||
@@ -716,8 +761,7 @@ __device__ __forceinline__ bool evict_chain(const EvictArgs &a, const Geo &geo, 
   uint32_t b = c1;  // chains start at the first candidate
   for (uint32_t kick = 1; kick <= max_kicks && !placed; ++kick) {
     uint64_t *bkt = a.buckets + (uint64_t)b * S;
-    const uint64_t w = load_fresh(bkt + sl);
-    const Mask fm = (Mask)((ballot(w == EMPTY) >> (g * S)) & T::FULL);
+    const Mask fm = load_view<S>(bkt, g, sl, w);
     if (group_claim<S>(bkt, fm, kv, g, sl)) {
       placed = true;
       break;
@@ -726,14 +770,11 @@ __device__ __forceinline__ bool evict_chain(const EvictArgs &a, const Geo &geo, 
     // slot 0 of every full bucket, which lets two chains trade the same
     // pair of entries back and forth)
     const int s0 = (int)(mix32(key_of(kv) ^ (kick * 0x9E3779B9u)) & (S - 1));
-    uint64_t found = 0;
+    const uint64_t ws = w[s0 % E::P];  // this lane's word at the victim's position in its pair
     bool won = false;
-    if (sl == s0) {
-      found = cas64(bkt + s0, w, kv);
-      won = found == w;
-    }
-    const bool ok = (ballot(won) >> (g * S)) & T::FULL;
-    const uint64_t victim = shfl64(w, g * S + s0);
+    if (sl == s0 / E::P) won = cas64(bkt + s0, ws, kv) == ws;
+    const bool ok = (ballot(won) >> (g * E::L)) & E::LANES;
+    const uint64_t victim = shfl64(ws, g * E::L + s0 / E::P);
     if (!ok) continue;  // the slot changed under us: count the round, keep the item
     if (victim == EMPTY) {
       placed = true;  // the slot was empty after all: the CAS claimed it
@@ -803,19 +844,19 @@ __device__ __forceinline__ void evict_counters(const EvictArgs &a, uint64_t unit
 // items), so this kernel takes no ticket.
 template <int S>
 __global__ __launch_bounds__(BLOCK) void evict_kernel(EvictArgs a) {
-  using T = Traits<S>;
+  using E = EvictShape<S>;
   __shared__ uint64_t pre[NSHARD + 1];
   wl_prefix(a.ctl, pre);
   const uint64_t cnt = pre[NSHARD];
   if (cnt == 0) return;  // same in every block
   const Geo geo = read_geo(a.ctl);
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int g = lane / S, sl = lane % S;
-  const uint64_t groups = (uint64_t)gridDim.x * WAVES * T::G;
+  const int g = lane / E::L, sl = lane % E::L;
+  const uint64_t groups = (uint64_t)gridDim.x * WAVES * E::G;
   uint64_t n_evict = 0, n_full = 0;
-  const uint64_t first = ((uint64_t)blockIdx.x * WAVES + wv) * T::G + g;
+  const uint64_t first = ((uint64_t)blockIdx.x * WAVES + wv) * E::G + g;
   // a uniform trip count per wave: every lane reaches the wave-wide steps
-  const uint64_t wave_first = ((uint64_t)blockIdx.x * WAVES + wv) * T::G;
+  const uint64_t wave_first = ((uint64_t)blockIdx.x * WAVES + wv) * E::G;
   for (uint64_t base = wave_first; base < cnt; base += groups) {
     const uint64_t t = base - wave_first + first;
     evict_round<S>(a, geo, t < cnt, t < cnt ? wl_slot(pre, t, a.wl_seg_cap) : 0, g, sl, n_evict, n_full);
@@ -1401,7 +1442,7 @@ __device__ __forceinline__ uint64_t enter(volatile ReqState *r, const ReqDesc &d
     }
     case PH_REPLACE:
     case PH_EVICT:  // r->items: the worklist size, summed when the phase before it finished
-      return ceil_div(r->items, gpb * EVICT_PER_GROUP);
+      return ceil_div(r->items, (uint64_t)WAVES * evict_groups_per_wave(d.t.S) * EVICT_PER_GROUP);
     case PH_OPS: return ceil_div(d.n, BLOCK);
     default: return 0;
   }
@@ -1615,17 +1656,21 @@ __device__ __forceinline__ void run_chunk(ReqState *r, const ReqDesc &d, uint32_
     }
     case PH_REPLACE:
     case PH_EVICT: {
+      using E = EvictShape<S>;
       __shared__ uint64_t pre[NSHARD + 1];
       const EvictArgs ea = evict_args(d);
       wl_prefix(d.t.ctl, pre);
       const Geo geo = read_geo(d.t.ctl);
       const uint64_t items = pre[NSHARD];
+      const int eg = lane / E::L, esl = lane % E::L;
+      const uint64_t egpb = (uint64_t)WAVES * E::G, egib = (uint64_t)wv * E::G + eg;
       uint64_t n_evict = 0, n_full = 0;
       for (uint64_t k = 0; k < EVICT_PER_GROUP; ++k) {
-        const uint64_t t = (c * EVICT_PER_GROUP + k) * gpb + gib;
-        evict_round<S>(ea, geo, t < items, t < items ? wl_slot(pre, t, d.t.wl_seg_cap) : 0, g, sl, n_evict, n_full);
+        const uint64_t t = (c * EVICT_PER_GROUP + k) * egpb + egib;
+        evict_round<S>(ea, geo, t < items, t < items ? wl_slot(pre, t, d.t.wl_seg_cap) : 0, eg, esl, n_evict,
+                       n_full);
       }
-      evict_counters(ea, c * WAVES + wv, n_evict, n_full, sl);
+      evict_counters(ea, c * WAVES + wv, n_evict, n_full, esl);
       break;
     }
     case PH_OPS: {
@@ -1938,7 +1983,7 @@ static void launch_ops_mode(uint32_t mode, const OpsArgs &a, hipStream_t st) {
 static void launch_evict(hive_table *h, uint64_t max_items, hipStream_t st) {
   EvictArgs e{h->d_buckets, h->d_hint,       h->d_stash,   h->d_pending,   h->d_ctl,
               h->d_wl,      h->wl_seg_cap,   h->stash_cap, h->pending_cap, h->cfg.max_evictions};
-  const dim3 grid(grid_for(max_items, (uint64_t)WAVES * (64 / h->S), EVICT_GRID));
+  const dim3 grid(grid_for(max_items, (uint64_t)WAVES * evict_groups_per_wave(h->S), EVICT_GRID));
   switch (h->S) {
     case 16: hipLaunchKernelGGL(evict_kernel<16>, grid, dim3(BLOCK), 0, st, e); break;
     case 32: hipLaunchKernelGGL(evict_kernel<32>, grid, dim3(BLOCK), 0, st, e); break;

@@ -221,6 +221,44 @@ def test_eviction_stash_pending_heavy(H, E, stash, lf):
     t.close()
 
 
+def test_large_stash_probe_runs(H):
+    """Thousands of entries in the stash (no cuckoo chains, buckets far over
+    capacity): searches, replaces, deletes (tombstones) and re-inserts all go
+    through the stash's linear-probe runs and match the dictionary."""
+    S, nb = 16, 64
+    n = 4000  # 1,024 bucket slots: about 3,000 entries end in the stash
+    case(f"large stash n={n} buckets={nb}")
+    ks = wl.KeyStream(47)
+    keys = ks.range(0, n)
+    vals = wl.values_for(keys)
+    t = H.Table(nb, max_evictions=0, stash_capacity=8192, pending_capacity=1024)
+    o = oracle.O1()
+    t.insert(dev(keys), dev(vals), flags=H.HIVE_UNIQUE)
+    o.insert(keys, vals)
+    st = t.stats()
+    assert st["status"] == H.HIVE_OK and st["live"] == n
+    assert 2500 < st["stash_count"] <= 8192 and st["pending_count"] == 0
+    q = ks.range(0, n + 3000)
+    for step in range(3):
+        v, f = t.lookup(dev(q))
+        ov, of = o.lookup(q)
+        assert np.array_equal(host(f), of) and np.array_equal(host(v), ov), step
+        assert np.array_equal(t.dump(), o.dump()), step
+        if step == 0:  # replace every third key, wherever it sits
+            v2 = (vals[::3] ^ np.uint32(0x5A5A5A)).astype(np.uint32)
+            t.insert(dev(keys[::3]), dev(v2), flags=H.HIVE_UNIQUE)
+            o.insert(keys[::3], v2)
+        elif step == 1:  # delete half, then put a quarter back
+            dk = keys[1::2]
+            assert np.array_equal(host(t.delete(dev(dk), flags=H.HIVE_UNIQUE)), o.delete(dk))
+            rk = dk[::2]
+            rv = (wl.values_for(rk) + np.uint32(1)).astype(np.uint32)
+            t.insert(dev(rk), dev(rv), flags=H.HIVE_UNIQUE)
+            o.insert(rk, rv)
+    assert t.stats()["live"] == len(o)
+    t.close()
+
+
 @pytest.mark.parametrize("probe_both", [0, 1])
 def test_mixed_batches_zipf(H, probe_both):
     """Prefill, then mixed batches (40% insert with repeats, 40% delete, 20%
