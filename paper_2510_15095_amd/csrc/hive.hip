@@ -676,7 +676,7 @@ __device__ __forceinline__ void overflow_place(const EvictArgs &a, const Geo &ge
 // bucket as P adjacent slots per lane (L x P = S).  A chain is a sequence of
 // dependent memory round trips, so the number of chains in flight sets the
 // eviction rate: for S = 16 each lane holds a whole bucket (P = 16, measured
-// best against 2, 4 and 8: mixed Zipf batches at 95% load 1.2 ms against
+// best against 8, 4 and 2: mixed Zipf batches at 95% load 1.2 ms against
 // 1.5, 1.9 and 2.4 ms), so a wave runs 64 chains at once; wider buckets keep
 // one slot per lane.
 template <int S>
