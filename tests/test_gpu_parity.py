@@ -353,22 +353,38 @@ def same_geometry(gpu_st, o2):
     return norm(g) == norm(o)
 
 
-def policy_stable(t, S, lf_e=90, lf_c=25, initial=None):
-    """After a post-batch policy call the table is not over the expand
-    threshold, and it is under the contract threshold only when it is at its
-    initial size or the next merge pair (from the top) does not fit."""
-    st = t.stats()
-    nb, im, sp, live = st["n_buckets"], st["index_mask"], st["split_ptr"], st["live"]
-    assert live * 100 <= lf_e * nb * S
-    if live * 100 >= lf_c * nb * S or nb == initial:
-        return False
+def next_merge_blocked(S, geo, where):
+    """The next merge pair (from the top) of a LINEAR table with geometry
+    (n_buckets, index_mask, split_ptr) does not fit: its high bucket holds
+    more entries than its low bucket has free slots (Section IV-C-2)."""
+    nb, im, sp = geo
     if sp == 0:
         im, sp = im >> 1, (im >> 1) + 1
-    lo, hi = sp - 1, sp - 1 + im + 1
-    _, where = t.dump(with_where=True)
+    lo, hi = sp - 1, sp + im
     counts = np.bincount(where[where >= 0], minlength=nb)
-    assert counts[hi] > S - counts[lo], f"merge of ({lo}, {hi}) fits but the policy stopped"
-    return True
+    return counts[hi] > S - counts[lo]
+
+
+def check_post_policy(t, S, lf_e=90, lf_c=25, initial=None):
+    """After a post-batch policy call the table is not over the expand
+    threshold, and it is under the contract threshold only when it is at its
+    initial size or its next merge pair does not fit."""
+    st = t.stats()
+    nb, live = st["n_buckets"], st["live"]
+    assert live * 100 <= lf_e * nb * S
+    if live * 100 < lf_c * nb * S and nb != initial:
+        _, where = t.dump(with_where=True)
+        assert next_merge_blocked(S, geometry(st), where), f"next merge of {geometry(st)} fits but the policy stopped"
+
+
+def check_divergence(S, geo_a, where_a, geo_b, where_b):
+    """Two tables that ran the same batches part only where a merge step
+    stopped early on one side (the pair did not fit its layout); the side
+    with more buckets is blocked at its next pair."""
+    if geo_a == geo_b:
+        return
+    geo, where = (geo_a, where_a) if geo_a[0] > geo_b[0] else (geo_b, where_b)
+    assert next_merge_blocked(S, geo, where), (geo_a, geo_b)
 
 
 @pytest.mark.parametrize("K", [1, 7, 64])
@@ -414,10 +430,12 @@ def test_linear_growth_and_contraction_match_oracle(H, K):
         o2.policy_post()
         assert np.array_equal(host(d), o1.delete(dk))
         st = t.stats()
-        blocked = policy_stable(t, S, initial=nb0)
+        check_post_policy(t, S, initial=nb0)
         if not diverged and not same_geometry(st, o2):
-            assert blocked, (geometry(st), o2.stats())
-            assert st["n_buckets"] > o2.stats()["n_buckets"]
+            ost = o2.stats()
+            _, ow = o2.dump(with_where=True)
+            _, gw = t.dump(with_where=True)
+            check_divergence(S, geometry(st), gw, (ost["n_buckets"], ost["index_mask"], ost["split_ptr"]), ow)
             diverged = True
         assert st["live"] == len(o1)
         v, f = t.lookup(dev(allk))
@@ -454,6 +472,56 @@ def test_linear_explicit_split_merge_and_stash_drain(H):
         assert np.array_equal(words, o1.dump())
         check_placement(words, where, S, nb0, oracle.ADDR_LINEAR, mb, geo=st["n_buckets"])
     t.close()
+
+
+def test_drain_stash_drain_after_splits(H):
+    """The executor's stash-drain and re-place phases: a LINEAR table whose
+    stash holds entries takes insert batches through the executor with
+    pre-batch expansion, so splits drain the stash and re-place it; lookups,
+    contents and geometry equal the plain path's and the dictionary's."""
+    import torch
+    S, nb0, mb = 16, 64, 2048
+
+    def table():  # no cuckoo kicks, growth only above 96%: the first 980 keys leave some in the stash
+        return H.Table(nb0, addressing=H.HIVE_LINEAR, max_buckets=mb, resize_k=16, pre_expand=1, post_policy=0,
+                       lf_expand_pct=96, lf_contract_pct=25, max_evictions=0, stash_capacity=512,
+                       pending_capacity=1024)
+    o1 = oracle.O1()
+    ks = wl.KeyStream(78)
+    keys = ks.range(0, 980)
+    vals = wl.values_for(keys)
+    plain, drained = table(), table()
+    for t in (plain, drained):
+        t.insert(dev(keys), dev(vals), flags=H.HIVE_UNIQUE)
+        assert t.stats()["n_buckets"] == nb0
+    o1.insert(keys, vals)
+    assert drained.stats()["stash_count"] > 0
+    # each later batch grows the table first: splits, then the stash drain
+    d = H.hive_drain_create(16, 0, 16, 4, 10_000_000)
+    keep, plan = [], []
+    for b in range(4):
+        bk = ks.range(1000 + b * 700, 1000 + (b + 1) * 700)
+        bv = wl.values_for(bk)
+        k_, v_ = dev(bk), dev(bv)
+        keep += [k_, v_]
+        assert H.hive_drain_submit(d, drained.h, H.HIVE_OP_INSERT, k_, v_, flags=H.HIVE_UNIQUE) is not None
+        plan.append((bk, bv))
+    case("drain launch, stash drain after splits")
+    H.hive_drain_launch(d, 0)
+    torch.cuda.synchronize()
+    for bk, bv in plan:
+        plain.insert(dev(bk), dev(bv), flags=H.HIVE_UNIQUE)
+        o1.insert(bk, bv)
+    q = np.concatenate([keys] + [bk for bk, _ in plan] + [ks.range(9000, 9500)])
+    ov, of = o1.lookup(q)
+    for t in (plain, drained):
+        v, f = t.lookup(dev(q))
+        assert np.array_equal(host(f), of) and np.array_equal(host(v), ov)
+        assert np.array_equal(t.dump(), o1.dump())
+    assert geometry(plain.stats()) == geometry(drained.stats())
+    H.hive_drain_destroy(d)
+    for t in (plain, drained):
+        t.close()
 
 
 def test_linear_merge_stops_when_pair_does_not_fit(H):
@@ -575,8 +643,10 @@ def test_drain_multi_table_linear_policies(H):
             ov, of = o1[i].lookup(keys)
             assert np.array_equal(host(fo), of) and np.array_equal(host(vo), ov)
     for i in names:
-        g1, g2 = geometry(tabs[i].stats()), geometry(refs[i].stats())
-        assert g1 == g2 or policy_stable(tabs[i], S, initial=nb0), (g1, g2)
+        check_post_policy(tabs[i], S, initial=nb0)
+        check_post_policy(refs[i], S, initial=nb0)
+        check_divergence(S, geometry(tabs[i].stats()), tabs[i].dump(with_where=True)[1],
+                         geometry(refs[i].stats()), refs[i].dump(with_where=True)[1])
         assert np.array_equal(tabs[i].dump(), o1[i].dump())
     H.hive_drain_destroy(d)
 
