@@ -1329,9 +1329,13 @@ enum : uint32_t {
   PH_START = 0, PH_FILL = 1, PH_DEDUPE = 2, PH_COUNT = 3, PH_SEG_A = 4, PH_SEG_B = 5, PH_DRAIN = 6,
   PH_REPLACE = 7, PH_OPS = 8, PH_EVICT = 9, PH_DONE = 10
 };
-constexpr uint64_t FILL_PER_CHUNK = BLOCK * 16;   // words per fill chunk
+// Chunk sizes.  A claim costs a few dependent device-scope round trips, so
+// streaming phases take large chunks; an eviction chunk gives each group
+// one item, so a phase's chains run side by side in as many waves as the
+// grid holds instead of one after another in fewer waves.
+constexpr uint64_t FILL_PER_CHUNK = BLOCK * 64;   // words per fill chunk
 constexpr uint64_t COUNT_PER_CHUNK = BLOCK * 16;  // operations per count chunk
-constexpr uint64_t EVICT_PER_GROUP = 4;           // eviction items per group per chunk
+constexpr uint64_t DRAIN_TILES = 16;              // stash tiles of BLOCK words per drain chunk
 constexpr uint64_t M28 = (1ull << 28) - 1;
 constexpr uint32_t DRAIN_WINDOW = 64;             // batches scanned for work
 
@@ -1474,11 +1478,11 @@ __device__ __forceinline__ uint64_t enter(volatile ReqState *r, const ReqDesc &d
     case PH_DRAIN: {
       const uint64_t total = (min(c->stash_count, d.t.stash_cap) ? stash_slots_for(d.t.stash_cap) : 0) +
                              min(c->pending_count, d.t.pending_cap);
-      return total ? max(ceil_div(total, BLOCK), ceil_div(d.t.hint_words, FILL_PER_CHUNK)) : 0;
+      return total ? max(ceil_div(total, BLOCK * DRAIN_TILES), ceil_div(d.t.hint_words, FILL_PER_CHUNK)) : 0;
     }
     case PH_REPLACE:
     case PH_EVICT:  // r->items: the worklist size, summed when the phase before it finished
-      return ceil_div(r->items, (uint64_t)WAVES * evict_groups_per_wave(d.t.S) * EVICT_PER_GROUP);
+      return ceil_div(r->items, (uint64_t)WAVES * evict_groups_per_wave(d.t.S));
     case PH_OPS: return ceil_div(d.n, BLOCK);
     default: return 0;
   }
@@ -1581,8 +1585,10 @@ __device__ void ingest(DrainQueue *q) {
 }
 
 // Claim a run of chunks of runnable work: `*chunk` is the first, `*count`
-// how many (a phase of n chunks is claimed in grains of about n / (4 x grid)
-// chunks, so a large phase costs few atomics on the request's state word).
+// how many (a phase of n chunks is claimed in grains of about n / (2 x grid)
+// chunks, so a large phase costs few claims: each is a chain of dependent
+// device-scope accesses, and the one on the request's state word is the
+// same address for every block).
 // Returns 0 (work), 1 (none now), 2 (exit).
 __device__ uint32_t find_work(DrainQueue *q, uint64_t *req, uint32_t *phase, uint64_t *chunk, uint64_t *count,
                               uint64_t *nch) {
@@ -1612,7 +1618,7 @@ __device__ uint32_t find_work(DrainQueue *q, uint64_t *req, uint32_t *phase, uin
     if (ph == PH_DONE || (st & M28) >= ((st >> 28) & M28)) continue;
     const uint64_t slot = ld_ctl(&r->d.table_slot), seq = ld_ctl(&r->d.seq);
     if (ld_ctl(&q->table_next[slot]) != seq) continue;
-    const uint64_t grain = max(1ull, ((st >> 28) & M28) / (4ull * gridDim.x));
+    const uint64_t grain = max(1ull, ((st >> 28) & M28) / (2ull * gridDim.x));
     const uint64_t old = add64(&r->state, grain);
     const uint64_t n = (old >> 28) & M28, c = old & M28;
     if ((uint32_t)(old >> 56) == PH_DONE || c >= n) continue;
@@ -1631,6 +1637,45 @@ __device__ __forceinline__ void load_desc(ReqDesc *dst, const ReqDesc *src) {
   const uint64_t *s = (const uint64_t *)src;
   uint64_t *d = (uint64_t *)dst;
   for (uint32_t w = threadIdx.x; w < sizeof(ReqDesc) / 8; w += BLOCK) d[w] = ld_ctl(s + w);
+}
+
+// A pointer the compiler knows to be global memory.  Pointers read from
+// memory are generic (flat) to it; rebuilt from their address as global
+// ones, their loads and stores become global instructions, which do not
+// share the LDS wait counter with the tile staging.
+template <typename T>
+__device__ __forceinline__ T *as_global(T *p) {
+  return (T *)(__attribute__((address_space(1))) T *)(uintptr_t)p;
+}
+
+// The LDS descriptor copied into scalar registers (every word goes through
+// readfirstlane, so the compiler knows it is uniform), its buffers marked
+// global.  Every buffer a descriptor names is device or mapped host memory.
+__device__ __forceinline__ ReqDesc uniform_desc(const ReqDesc &src) {
+  uint32_t w[sizeof(ReqDesc) / 4];
+  __builtin_memcpy(w, &src, sizeof(ReqDesc));
+#pragma unroll
+  for (uint32_t i = 0; i < sizeof(ReqDesc) / 4; ++i) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
+  ReqDesc d;
+  __builtin_memcpy(&d, w, sizeof(ReqDesc));
+  d.t.buckets = as_global(d.t.buckets);
+  d.t.hint = as_global(d.t.hint);
+  d.t.stash = as_global(d.t.stash);
+  d.t.pending = as_global(d.t.pending);
+  d.t.ctl = as_global(d.t.ctl);
+  d.t.wl = as_global(d.t.wl);
+  d.t.dd = as_global(d.t.dd);
+  d.ops = as_global(d.ops);
+  d.keys = as_global(d.keys);
+  d.vals = as_global(d.vals);
+  d.vals_out = as_global(d.vals_out);
+  d.flags_out = as_global(d.flags_out);
+  return d;
+}
+
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+  return ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(v >> 32)) << 32) |
+         __builtin_amdgcn_readfirstlane((uint32_t)v);
 }
 
 template <int S>
@@ -1686,8 +1731,9 @@ __device__ __forceinline__ void run_chunk(ReqState *r, const ReqDesc &d, uint32_
       const uint64_t total = n_stash + min(ld_ctl(&cc->pending_count), d.t.pending_cap);
       const uint64_t hb = c * FILL_PER_CHUNK, he = min(hb + FILL_PER_CHUNK, d.t.hint_words);
       for (uint64_t t = hb + threadIdx.x; t < he; t += BLOCK) d.t.hint[t] = 0u;
-      drain_collect(c * BLOCK + threadIdx.x, n_stash, total, d.t.stash, d.t.pending, d.t.wl, d.t.wl_seg_cap,
-                    d.t.ctl);
+      for (uint64_t k = 0; k < DRAIN_TILES; ++k)
+        drain_collect((c * DRAIN_TILES + k) * BLOCK + threadIdx.x, n_stash, total, d.t.stash, d.t.pending, d.t.wl,
+                      d.t.wl_seg_cap, d.t.ctl);
       break;
     }
     case PH_REPLACE:
@@ -1701,11 +1747,8 @@ __device__ __forceinline__ void run_chunk(ReqState *r, const ReqDesc &d, uint32_
       const int eg = lane / E::L, esl = lane % E::L;
       const uint64_t egpb = (uint64_t)WAVES * E::G, egib = (uint64_t)wv * E::G + eg;
       uint64_t n_evict = 0, n_full = 0;
-      for (uint64_t k = 0; k < EVICT_PER_GROUP; ++k) {
-        const uint64_t t = (c * EVICT_PER_GROUP + k) * egpb + egib;
-        evict_round<S>(ea, geo, t < items, t < items ? wl_slot(pre, t, d.t.wl_seg_cap) : 0, eg, esl, n_evict,
-                       n_full);
-      }
+      const uint64_t t = c * egpb + egib;
+      evict_round<S>(ea, geo, t < items, t < items ? wl_slot(pre, t, d.t.wl_seg_cap) : 0, eg, esl, n_evict, n_full);
       evict_counters(ea, c * WAVES + wv, n_evict, n_full, esl);
       break;
     }
@@ -1748,7 +1791,9 @@ __global__ void drain_reset_kernel(DrainQueue *q) { q->final_seen = 0; }
 // One reading of the constant-rate device clock (clock-rate calibration).
 __global__ void wall_clock_kernel(uint64_t *out) { *out = wall_clock64(); }
 
-// Occupancy target: 3 waves per SIMD (at most 168 VGPRs) fits without spills.
+// Occupancy target: 3 waves per SIMD (at most 168 VGPRs).  The 16-slot build
+// spills three registers of the control loop, none inside a phase; a cap of
+// 128 (4 waves) spills inside the phases and runs slower.
 template <int S>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void drain_worker_kernel(DrainQueue *q) {
   __shared__ OpsShared<S> sh;
@@ -1792,8 +1837,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
     ReqState *r = q->req + s_req % q->cap;
     load_desc(&desc, &r->d);
     __syncthreads();
-    for (uint64_t k = 0; k < s_cnt; ++k) {
-      run_chunk<S>(r, desc, s_phase, s_chunk + k, sh);
+    const ReqDesc d = uniform_desc(desc);
+    const uint32_t phase = __builtin_amdgcn_readfirstlane(s_phase);
+    const uint64_t chunk = uniform64(s_chunk), cnt = uniform64(s_cnt);
+    for (uint64_t k = 0; k < cnt; ++k) {
+      run_chunk<S>(r, d, phase, chunk + k, sh);
       __syncthreads();
     }
     if (threadIdx.x == 0) {
@@ -1804,9 +1852,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
     if (s_last) {
       // the block that completed the phase: shard folds by wave 0, then the
       // scalar epilogue and the next phase by thread 0
-      if (threadIdx.x < 64) phase_fold(r, desc, s_phase);
+      if (threadIdx.x < 64) phase_fold(r, desc, phase);
       __syncthreads();
-      if (threadIdx.x == 0) advance(q, r, desc, s_phase);
+      if (threadIdx.x == 0) advance(q, r, desc, phase);
     }
     __syncthreads();
   }
