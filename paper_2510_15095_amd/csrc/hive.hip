@@ -12,8 +12,10 @@
 //           P1, so lookups and deletes never miss a key in flight;
 //   P3      inserts whose two buckets were full: bounded cuckoo eviction
 //           (Algorithm 3), and after max_evictions displacements the item in
-//           hand goes to the stash ring, or the pending list when the ring is
-//           full (Section IV-A step 4).
+//           hand goes to the stash, or the pending list when the stash is
+//           full (Section IV-A step 4; the stash here is an open-addressed
+//           table rather than the paper's ring, so a search stops at the
+//           first EMPTY slot of its key's probe run instead of scanning).
 //
 // gfx950 mapping of the warp protocols: with S = 16 a bucket is one 128-byte
 // line probed by a 16-lane group, so one wave-wide load probes 4 buckets.
@@ -128,20 +130,28 @@ __device__ __forceinline__ uint64_t wl_slot(const uint64_t *pre, uint64_t k, uin
 __device__ __forceinline__ uint64_t fold_shards_wave(Ctl *c, bool wl_done) {
   const int lane = threadIdx.x & 63;
   Shard *sh = shard_of(c, lane);
-  uint64_t v[4] = {ld_ctl(&sh->live), ld_ctl(&sh->evictions), ld_ctl(&sh->full_chains), ld_ctl(&sh->invalid_keys)};
+  // the last pair: stash placements made without a reservation join the
+  // stash count here, after the launch (or executor phase) that made them
+  constexpr int NF = 7;
+  uint64_t *src[NF] = {&sh->live,          &sh->evictions,       &sh->full_chains,     &sh->invalid_keys,
+                       &sh->stash_inserts, &sh->pending_inserts, &sh->stash_unreserved};
+  uint64_t *dst[NF] = {&c->live,          &c->evictions,       &c->full_chains, &c->invalid_keys,
+                       &c->stash_inserts, &c->pending_inserts, &c->stash_count};
+  uint64_t v[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) v[f] = ld_ctl(src[f]);
   const uint64_t wl = ld_ctl(&sh->wl_count);
-  if (v[0]) __hip_atomic_store(&sh->live, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if (v[1]) __hip_atomic_store(&sh->evictions, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if (v[2]) __hip_atomic_store(&sh->full_chains, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if (v[3]) __hip_atomic_store(&sh->invalid_keys, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+  for (int f = 0; f < NF; ++f)
+    if (v[f]) __hip_atomic_store(src[f], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (wl_done && wl) __hip_atomic_store(&sh->wl_count, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  for (int f = 0; f < 4; ++f) v[f] = wave_sum64(v[f]);
+#pragma unroll
+  for (int f = 0; f < NF; ++f) v[f] = wave_sum64(v[f]);
   const uint64_t total_wl = wave_sum64(wl);
   if (lane == 0) {
-    if (v[0]) add64(&c->live, v[0]);
-    if (v[1]) add64(&c->evictions, v[1]);
-    if (v[2]) add64(&c->full_chains, v[2]);
-    if (v[3]) add64(&c->invalid_keys, v[3]);
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+      if (v[f]) add64(dst[f], v[f]);
     if (wl_done && total_wl) add64(&c->evict_items, total_wl);
   }
   return total_wl;
@@ -644,8 +654,9 @@ __device__ __forceinline__ void set_hint(uint32_t *hint, uint32_t b) { or32(&hin
 // all of its pushes (the counts may pass their capacities; every reader
 // clamps them); given its reserved position c (c >= capacity: pending), the
 // entry claims the first EMPTY word of its probe run by CAS (one exists: the
-// table has at least twice the capacity).
-__device__ __forceinline__ void overflow_place(const EvictArgs &a, const Geo &geo, uint64_t kv, uint64_t c) {
+// table has at least twice the capacity).  Returns where it went: 0 stash,
+// 1 pending, 2 lost (the pending list was full too; latched as an error).
+__device__ __forceinline__ int overflow_place(const EvictArgs &a, const Geo &geo, uint64_t kv, uint64_t c) {
   bool stashed = false;
   if (c < a.stash_cap) {
     const uint64_t mask = stash_slots_for(a.stash_cap) - 1;
@@ -656,20 +667,21 @@ __device__ __forceinline__ void overflow_place(const EvictArgs &a, const Geo &ge
       }
     }
   }
-  if (stashed) {
-    add64(&a.ctl->stash_inserts, 1);
-  } else {
+  int where = 0;
+  if (!stashed) {
     const uint64_t p = add64(&a.ctl->pending_count, 1);
     if (p < a.pending_cap) {
       __hip_atomic_store(a.pending + p, kv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      add64(&a.ctl->pending_inserts, 1);
+      where = 1;
     } else {
       atomicOr(&a.ctl->error, ERR_PENDING_LOST);
+      where = 2;
     }
   }
   const uint32_t k = key_of(kv);
   set_hint(a.hint, address(geo, bithash1(k)));
   set_hint(a.hint, address(geo, bithash2(k)));
+  return where;
 }
 
 // Eviction group shape.  A group of L lanes works on one item and sees a
@@ -732,14 +744,50 @@ __device__ __forceinline__ Mask interleave_slots(const uint64_t *m) {
   }
 }
 
+// One lane's fresh copy of a whole 16-slot bucket (128 bytes, 128-byte
+// aligned) in eight 16-byte loads with the cache policy of an agent-scope
+// relaxed atomic load (sc1: served coherently, not from a stale vector-cache
+// line).  Atomic loads are at most 8 bytes wide; in the one-lane-per-item
+// shape sixteen of them cost each wave instruction 64 scattered lines, eight
+// wide ones half the instructions (bulk eviction 205 -> 162 us).  The block
+// ends in its own wait for the loads, so the registers are complete when it
+// returns.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void load_bucket16_fresh(const uint64_t *b, uint64_t *w) {
+  u32x4 x0, x1, x2, x3, x4, x5, x6, x7;
+  asm volatile(
+      "global_load_dwordx4 %0, %8, off sc1\n"
+      "global_load_dwordx4 %1, %8, off offset:16 sc1\n"
+      "global_load_dwordx4 %2, %8, off offset:32 sc1\n"
+      "global_load_dwordx4 %3, %8, off offset:48 sc1\n"
+      "global_load_dwordx4 %4, %8, off offset:64 sc1\n"
+      "global_load_dwordx4 %5, %8, off offset:80 sc1\n"
+      "global_load_dwordx4 %6, %8, off offset:96 sc1\n"
+      "global_load_dwordx4 %7, %8, off offset:112 sc1\n"
+      "s_waitcnt vmcnt(0)\n"
+      : "=&v"(x0), "=&v"(x1), "=&v"(x2), "=&v"(x3), "=&v"(x4), "=&v"(x5), "=&v"(x6), "=&v"(x7)
+      : "v"(b)
+      : "memory");
+  const u32x4 xs[8] = {x0, x1, x2, x3, x4, x5, x6, x7};
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    w[2 * j] = ((uint64_t)xs[j][1] << 32) | xs[j][0];
+    w[2 * j + 1] = ((uint64_t)xs[j][3] << 32) | xs[j][2];
+  }
+}
+
 // The group's fresh view of bucket `bkt`: words w[p] of slots sl * P + p,
 // and its EMPTY-slot mask.
 template <int S>
 __device__ __forceinline__ typename Traits<S>::Mask load_view(const uint64_t *bkt, int g, int sl, uint64_t *w) {
   using E = EvictShape<S>;
   uint64_t m[E::P];
+  if constexpr (E::L == 1 && E::P == 16) {
+    load_bucket16_fresh(bkt, w);
+  } else {
 #pragma unroll
-  for (int p = 0; p < E::P; ++p) w[p] = load_fresh(bkt + sl * E::P + p);
+    for (int p = 0; p < E::P; ++p) w[p] = load_fresh(bkt + sl * E::P + p);
+  }
   if constexpr (E::L == 1) {  // the lane holds the whole bucket
 #pragma unroll
     for (int p = 0; p < E::P; ++p) m[p] = w[p] == EMPTY;
@@ -828,11 +876,17 @@ __device__ __forceinline__ bool evict_chain(const EvictArgs &a, const Geo &geo, 
 // One item per group of the wave (`have`: the group has one, at worklist
 // position `pos`); every lane of the wave calls it.  Each item takes step 2
 // (two-choice claim on fresh loads) and the bounded chain of Algorithm 3;
-// an entry still in hand goes to the stash, with one count reservation per
-// wave for all of its groups.
+// an entry still in hand goes to the stash.  `unreserved`: the launch cannot
+// fill the stash (its count when the launch started plus the launch's items
+// is within capacity), so entries take stash slots without touching the
+// count, which every pushing wave would otherwise reserve from, one atomic
+// each on a single address (thousands of waves queue there in a stash drain);
+// their number is added per wave to the shards and folded into the count
+// after the launch.  Otherwise one count reservation per wave.
 template <int S>
-__device__ __forceinline__ void evict_round(const EvictArgs &a, const Geo &geo, bool have, uint64_t pos, int g,
-                                            int sl, uint64_t &n_evict, uint64_t &n_full) {
+__device__ __forceinline__ void evict_round(const EvictArgs &a, const Geo &geo, bool unreserved, bool have,
+                                            uint64_t pos, int g, int sl, uint64_t &n_evict, uint64_t &n_full,
+                                            uint64_t &n_side) {
   uint64_t kv = 0;
   bool placed = true;
   if (have) {
@@ -845,27 +899,35 @@ __device__ __forceinline__ void evict_round(const EvictArgs &a, const Geo &geo, 
     const int lane = threadIdx.x & 63;
     const int leader = __builtin_ctzll(pm);
     uint64_t base = 0;
-    if (lane == leader) {
-      const uint64_t n = (uint64_t)__popcll(pm);
-      base = load_fresh(&a.ctl->stash_count) < a.stash_cap ? add64(&a.ctl->stash_count, n) : a.stash_cap;
+    if (!unreserved) {
+      if (lane == leader) {
+        const uint64_t n = (uint64_t)__popcll(pm);
+        base = load_fresh(&a.ctl->stash_count) < a.stash_cap ? add64(&a.ctl->stash_count, n) : a.stash_cap;
+      }
+      base = read_lane64(base, leader);
     }
-    base = read_lane64(base, leader);
     if (push) {
       ++n_full;
-      overflow_place(a, geo, kv, base + rank_below(pm));
+      const int where = overflow_place(a, geo, kv, base + rank_below(pm));
+      n_side += where == 0 ? 1 : where == 1 ? (1ull << 32) : 0;
     }
   }
 }
 
 // Chain statistics of a wave (per group, held by its lane 0) added to the
-// wave's shard.  Every lane of the wave calls it.
-__device__ __forceinline__ void evict_counters(const EvictArgs &a, uint64_t unit, uint64_t n_evict, uint64_t n_full,
-                                               int sl) {
-  const uint64_t e = wave_sum64(sl == 0 ? n_evict : 0), f = wave_sum64(n_full);
+// wave's shard.  Every lane of the wave calls it.  n_side counts the lane's
+// stash placements in its low half and pending ones in its high half (a
+// wave places far fewer than 2^32 entries).
+__device__ __forceinline__ void evict_counters(const EvictArgs &a, bool unreserved, uint64_t unit, uint64_t n_evict,
+                                               uint64_t n_full, uint64_t n_side, int sl) {
+  const uint64_t e = wave_sum64(sl == 0 ? n_evict : 0), f = wave_sum64(n_full), sd = wave_sum64(n_side);
   if ((threadIdx.x & 63) == 0 && (e | f)) {
     Shard *sh = shard_of(a.ctl, unit % NSHARD);
     if (e) add64(&sh->evictions, e);
     if (f) add64(&sh->full_chains, f);
+    if ((uint32_t)sd) add64(&sh->stash_inserts, (uint32_t)sd);
+    if ((uint32_t)sd && unreserved) add64(&sh->stash_unreserved, (uint32_t)sd);
+    if (sd >> 32) add64(&sh->pending_inserts, sd >> 32);
   }
 }
 
@@ -874,10 +936,11 @@ __device__ __forceinline__ void evict_counters(const EvictArgs &a, uint64_t unit
 // fresh view of both buckets (two-choice), then the bounded cuckoo chain of
 // Algorithm 3: each round claims a free slot of the current bucket or
 // displaces a victim by CAS and carries the victim to its alternate bucket.
-// An item still in hand after max_evictions displacements goes to the stash
-// ring, or to the pending list when the ring is full.
+// An item still in hand after max_evictions displacements goes to the stash,
+// or to the pending list when the stash is full.
 // The worklist is emptied afterwards by finish_kernel (it also counts the
-// items), so this kernel takes no ticket.
+// items and folds unreserved stash placements into the stash count), so this
+// kernel takes no ticket.
 template <int S>
 __global__ __launch_bounds__(BLOCK) void evict_kernel(EvictArgs a) {
   using E = EvictShape<S>;
@@ -886,18 +949,21 @@ __global__ __launch_bounds__(BLOCK) void evict_kernel(EvictArgs a) {
   const uint64_t cnt = pre[NSHARD];
   if (cnt == 0) return;  // same in every block
   const Geo geo = read_geo(a.ctl);
+  // the same in every block: an unreserved launch leaves the count alone
+  const bool unreserved = ld_ctl(&a.ctl->stash_count) + cnt <= a.stash_cap;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = lane / E::L, sl = lane % E::L;
   const uint64_t groups = (uint64_t)gridDim.x * WAVES * E::G;
-  uint64_t n_evict = 0, n_full = 0;
+  uint64_t n_evict = 0, n_full = 0, n_side = 0;
   const uint64_t first = ((uint64_t)blockIdx.x * WAVES + wv) * E::G + g;
   // a uniform trip count per wave: every lane reaches the wave-wide steps
   const uint64_t wave_first = ((uint64_t)blockIdx.x * WAVES + wv) * E::G;
   for (uint64_t base = wave_first; base < cnt; base += groups) {
     const uint64_t t = base - wave_first + first;
-    evict_round<S>(a, geo, t < cnt, t < cnt ? wl_slot(pre, t, a.wl_seg_cap) : 0, g, sl, n_evict, n_full);
+    evict_round<S>(a, geo, unreserved, t < cnt, t < cnt ? wl_slot(pre, t, a.wl_seg_cap) : 0, g, sl, n_evict, n_full,
+                   n_side);
   }
-  evict_counters(a, (uint64_t)blockIdx.x * WAVES + wv, n_evict, n_full, sl);
+  evict_counters(a, unreserved, (uint64_t)blockIdx.x * WAVES + wv, n_evict, n_full, n_side, sl);
 }
 
 // ---------------------------------------------------------------------------
@@ -1746,10 +1812,12 @@ __device__ __forceinline__ void run_chunk(ReqState *r, const ReqDesc &d, uint32_
       const uint64_t items = pre[NSHARD];
       const int eg = lane / E::L, esl = lane % E::L;
       const uint64_t egpb = (uint64_t)WAVES * E::G, egib = (uint64_t)wv * E::G + eg;
-      uint64_t n_evict = 0, n_full = 0;
+      uint64_t n_evict = 0, n_full = 0, n_side = 0;
       const uint64_t t = c * egpb + egib;
-      evict_round<S>(ea, geo, t < items, t < items ? wl_slot(pre, t, d.t.wl_seg_cap) : 0, eg, esl, n_evict, n_full);
-      evict_counters(ea, c * WAVES + wv, n_evict, n_full, esl);
+      const bool unreserved = ld_ctl(&d.t.ctl->stash_count) + items <= d.t.stash_cap;
+      evict_round<S>(ea, geo, unreserved, t < items, t < items ? wl_slot(pre, t, d.t.wl_seg_cap) : 0, eg, esl, n_evict,
+                     n_full, n_side);
+      evict_counters(ea, unreserved, c * WAVES + wv, n_evict, n_full, n_side, esl);
       break;
     }
     case PH_OPS: {

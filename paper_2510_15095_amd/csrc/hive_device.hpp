@@ -5,8 +5,8 @@
 //            words [b*S, b*S + S): one 128-byte line for S = 16
 //   hint     one bit per bucket: set when a key with this bucket as a
 //            candidate was sent to the stash or pending list
-//   stash    ring of packed words (Section IV-A step 4); deleted entries
-//            become TOMB
+//   stash    open-addressed table of packed words (Section IV-A step 4),
+//            twice its capacity in slots; deleted entries become TOMB
 //   pending  entries that found the stash full
 //   ctl      the control block below
 #pragma once
@@ -49,7 +49,7 @@ struct alignas(128) Ctl {
   uint64_t sp;             // LINEAR: split pointer
   uint32_t mode;           // ADDR_FIXED / ADDR_LINEAR
   uint32_t pad_mode_;
-  uint64_t stash_count;    // ring slots used (including TOMB)
+  uint64_t stash_count;    // stash slots used (including TOMB)
   uint64_t pending_count;  // pending slots used (including TOMB; may pass capacity on loss)
   uint64_t pad0_[9];
   // line 1: totals, folded from the shards after each batch, and error bits
@@ -97,6 +97,9 @@ struct Shard {
   uint64_t full_chains;
   uint64_t invalid_keys;
   uint64_t ticket;
+  uint64_t stash_inserts;
+  uint64_t pending_inserts;
+  uint64_t stash_unreserved;  // stash placements of launches that needed no reservation
 };
 constexpr uint64_t CTL_BYTES = sizeof(Ctl) + NSHARD * SHARD_STRIDE;
 

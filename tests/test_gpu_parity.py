@@ -201,6 +201,11 @@ def test_eviction_stash_pending_heavy(H, E, stash, lf):
     st = t.stats()
     assert st["status"] in (H.HIVE_OK, H.HIVE_WARN_PENDING), st
     assert st["live"] == n and st["stash_count"] <= stash
+    # every chain that ran out of kicks placed its entry in the stash or the
+    # pending list, and the counters (summed per wave) say which
+    _, where0 = t.dump(with_where=True)
+    assert st["full_chains"] == st["stash_inserts"] + st["pending_inserts"]
+    assert st["stash_inserts"] == int((where0 == -1).sum()) and st["pending_inserts"] == int((where0 == -2).sum())
     q = ks.range(0, n + 500)
     v, f = t.lookup(dev(q))
     ov, of = o.lookup(q)
