@@ -250,6 +250,16 @@ hive_status hive_drain_poll(hive_drain_t d, uint64_t ticket, int *done);
  * Valid while the ticket's ring slot has not been reused. */
 hive_status hive_drain_result(hive_drain_t d, uint64_t ticket, int *done, uint64_t *live_after);
 
+/* hive_drain_result for n tickets in one call, for serving loops that poll
+ * every batch in flight on each turn.  tickets, done and live_after are
+ * host arrays of n entries owned by the caller: done[i] = 1 once tickets[i]
+ * is complete, and then live_after[i] = the table's key count right after
+ * it (0 while it runs).  HIVE_ERR_ARG, with nothing written, when a pointer
+ * is null with n > 0, or any ticket was never submitted or has had its ring
+ * slot reused. */
+hive_status hive_drain_results(hive_drain_t d, const uint64_t *tickets, uint64_t n, uint8_t *done,
+                               uint64_t *live_after);
+
 /* Tell a resident grid to exit when its queue is empty and wait for it
  * (`stream` is unused).  Returns HIVE_ERR_HIP if a block gave up on its idle
  * watchdog. */

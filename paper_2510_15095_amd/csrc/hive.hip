@@ -2751,6 +2751,19 @@ hive_status hive_drain_result(hive_drain_t d, uint64_t ticket, int *done, uint64
   return HIVE_OK;
 }
 
+hive_status hive_drain_results(hive_drain_t d, const uint64_t *tickets, uint64_t n, uint8_t *done,
+                               uint64_t *live_after) {
+  if (!d || (n && (!tickets || !done || !live_after))) return HIVE_ERR_ARG;
+  for (uint64_t i = 0; i < n; ++i)
+    if (tickets[i] >= d->submitted || d->submitted - tickets[i] > d->cap) return HIVE_ERR_ARG;
+  for (uint64_t i = 0; i < n; ++i) {
+    const uint64_t t = tickets[i];
+    done[i] = __atomic_load_n(&d->h_done[t % d->cap], __ATOMIC_ACQUIRE) == t + 1;
+    live_after[i] = done[i] ? __atomic_load_n(&d->h_live[t % d->cap], __ATOMIC_RELAXED) : 0;
+  }
+  return HIVE_OK;
+}
+
 hive_status hive_drain_stop(hive_drain_t d, void *stream) {
   if (!d) return HIVE_ERR_ARG;
   (void)stream;

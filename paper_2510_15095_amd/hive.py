@@ -115,6 +115,7 @@ def _load():
         "hive_drain_launch": ([p, st, p], st),
         "hive_drain_poll": ([p, u64, ctypes.POINTER(st)], st),
         "hive_drain_result": ([p, u64, ctypes.POINTER(st), ctypes.POINTER(u64)], st),
+        "hive_drain_results": ([p, p, u64, p, p], st),
         "hive_drain_stop": ([p, p], st),
         "hive_drain_destroy": ([p], st),
     }
@@ -320,6 +321,17 @@ def hive_drain_result(d, ticket: int) -> tuple[bool, int]:
     done, live = ctypes.c_int(), ctypes.c_uint64()
     _check(_lib.hive_drain_result(d, ticket, ctypes.byref(done), ctypes.byref(live)), "hive_drain_result")
     return bool(done.value), int(live.value)
+
+
+def hive_drain_results(d, tickets):
+    """(done, live_after) numpy arrays for an array of tickets, in one call."""
+    import numpy as np
+    t = np.ascontiguousarray(tickets, dtype=np.uint64)
+    done = np.zeros(t.size, dtype=np.uint8)
+    live = np.zeros(t.size, dtype=np.uint64)
+    _check(_lib.hive_drain_results(d, t.ctypes.data, t.size, done.ctypes.data, live.ctypes.data),
+           "hive_drain_results")
+    return done.astype(bool), live
 
 
 def hive_drain_stop(d, stream=None) -> None:

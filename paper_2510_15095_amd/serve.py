@@ -173,7 +173,9 @@ class Server:
             read = set()
             n_submitted = 0
         elif mode == "plain":
-            events = {}
+            # per stream, requests complete in submission order: a turn checks
+            # only the oldest event of each stream
+            fifo = [collections.deque() for _ in self.streams]
             live_pinned = torch.zeros(n, dtype=torch.int64).pin_memory()
         else:
             raise ValueError(mode)
@@ -208,31 +210,38 @@ class Server:
                         unread.append(tk)
                         inflight[r.rid] = tk
                     else:
-                        st = self.streams[r.table % len(self.streams)]
+                        si = r.table % len(self.streams)
+                        st = self.streams[si]
                         H.hive_mixed_batch(h, o_, k_, v_, vout[r.rid], fout[r.rid], stream=st)
                         H.hive_live_async(h, live_pinned.data_ptr() + 8 * r.rid, stream=st)
                         ev = torch.cuda.Event()
                         ev.record(st)
-                        events[r.rid] = ev
+                        fifo[si].append((r.rid, ev))
                         inflight[r.rid] = r.rid
                     admitted_at[r.rid] = time.perf_counter() - t0
                     inflight_ins[r.table] += r.n_ins
                     pending.pop(0)
-                # completions
-                for rid in list(inflight):
-                    if mode == "persistent":
-                        ok, lv = H.hive_drain_result(drain, inflight[rid])
-                        if ok:
-                            read.add(inflight[rid])
-                    else:
-                        ok = events[rid].query()
-                        lv = int(live_pinned[rid]) if ok else 0
-                    if ok:
-                        r = requests[rid]
-                        done_at[rid] = time.perf_counter() - t0
-                        inflight_ins[r.table] -= r.n_ins
-                        live[r.table] = lv
-                        del inflight[rid]
+                # completions: one call for every ticket in flight, or the
+                # heads of the stream queues
+                finished = []
+                if mode == "persistent" and inflight:
+                    rids = list(inflight)
+                    ok, lv = H.hive_drain_results(drain, [inflight[i] for i in rids])
+                    for j in np.flatnonzero(ok):
+                        read.add(inflight[rids[j]])
+                        finished.append((rids[j], int(lv[j])))
+                elif mode == "plain":
+                    for q in fifo:
+                        while q and q[0][1].query():
+                            rid = q.popleft()[0]
+                            finished.append((rid, int(live_pinned[rid])))
+                t_done = time.perf_counter() - t0
+                for rid, lv in finished:
+                    r = requests[rid]
+                    done_at[rid] = t_done
+                    inflight_ins[r.table] -= r.n_ins
+                    live[r.table] = lv
+                    del inflight[rid]
         finally:
             if mode == "persistent":
                 H.hive_drain_stop(drain, side)

@@ -104,6 +104,8 @@ def test_null_handle_and_arguments_rejected(H):
     assert lib.hive_resize(None, 1, None) == H.HIVE_ERR_ARG
     assert lib.hive_stats(None, None, None) == H.HIVE_ERR_ARG
     assert lib.hive_destroy(None) == H.HIVE_ERR_ARG
+    assert lib.hive_drain_results(None, None, 0, None, None) == H.HIVE_ERR_ARG
+    assert lib.hive_drain_result(None, 0, None, None) == H.HIVE_ERR_ARG
     assert lib.hive_status_string(H.HIVE_ERR_LOST).decode().startswith("pending")
 
 

@@ -589,6 +589,11 @@ def test_drain_matches_plain_and_oracle_mixed(H):
     H.hive_drain_launch(d, 0)
     torch.cuda.synchronize()
     assert all(H.hive_drain_poll(d, t) for t in tickets)
+    done, live_after = H.hive_drain_results(d, tickets)
+    assert done.all()
+    assert [int(x) for x in live_after] == [H.hive_drain_result(d, t)[1] for t in tickets]
+    with pytest.raises(H.HiveError):
+        H.hive_drain_results(d, [tickets[-1] + 1])  # never submitted
     for b, mb in enumerate(batches):
         pv, pf = plain.mixed(dev(mb["ops"]), dev(mb["keys"]), dev(mb["vals"]))
         ov, of = o.apply(mb["ops"], mb["keys"], mb["vals"])
