@@ -1616,59 +1616,93 @@ __device__ void advance(DrainQueue *q, ReqState *rs, const ReqDesc &d, uint32_t 
   __hip_atomic_store(&rs->state, make_state(ph, nch), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Copy new host descriptors into the device ring.  Only the block holding
-// the ingest lock reads host memory (the tail, the stop flag, descriptors);
-// every other block polls device memory.  The stop flag is read before the
-// tail, so once it is seen set, the tail read after it is final.
+// A value the whole wave holds, in a scalar register (the first active
+// lane's copy).
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+  return ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(v >> 32)) << 32) |
+         __builtin_amdgcn_readfirstlane((uint32_t)v);
+}
+
+// Copy new host descriptors into the device ring, by the 64 lanes of one
+// wave.  Only the block holding the ingest lock reads host memory (the tail,
+// the stop flag, descriptors); every other block polls device memory.  The
+// descriptors' words are copied lane-parallel (up to 64 descriptors per
+// call): host reads cross the bus, and a one-thread copy of 16 descriptors
+// word by word had been hundreds of dependent reads, long enough to be the
+// executor's intake limit.  Lane j then publishes descriptor j.  The stop
+// flag is read before the tail, so once it is seen set, the tail read after
+// it is final.
 __device__ void ingest(DrainQueue *q) {
-  if (__hip_atomic_load(&q->ingest_lock, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
-  uint32_t expect = 0;
-  if (!__hip_atomic_compare_exchange_strong(&q->ingest_lock, &expect, 1u, __ATOMIC_ACQUIRE, __ATOMIC_RELAXED,
-                                            __HIP_MEMORY_SCOPE_AGENT))
-    return;
+  const int lane = threadIdx.x & 63;
+  uint32_t got = 0;
+  if (lane == 0 && __hip_atomic_load(&q->ingest_lock, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+    uint32_t expect = 0;
+    got = __hip_atomic_compare_exchange_strong(&q->ingest_lock, &expect, 1u, __ATOMIC_ACQUIRE, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if (!__builtin_amdgcn_readfirstlane(got)) return;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   const bool stop = __hip_atomic_load(q->host_stop, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM) != 0;
-  const uint64_t tail = ld_sys(q->host_tail);
-  uint64_t i = ld_ctl(&q->ingested);
-  const uint64_t lim = min(tail, i + 16);
-  for (; i < lim; ++i) {
-    const uint64_t *src = (const uint64_t *)(q->host_ring + i % q->cap);
-    ReqState *r = q->req + i % q->cap;
-    uint64_t *dst = (uint64_t *)&r->d;
-    for (uint32_t w = 0; w < sizeof(ReqDesc) / 8; ++w) dst[w] = ld_sys(src + w);
+  const uint64_t tail = uniform64(ld_sys(q->host_tail));
+  const uint64_t i0 = uniform64(ld_ctl(&q->ingested));
+  const uint64_t n = min(tail - i0, (uint64_t)64);
+  constexpr uint64_t W = sizeof(ReqDesc) / 8;
+  for (uint64_t k = lane; k < n * W; k += 64) {
+    const uint64_t i = (i0 + k / W) % q->cap, w = k % W;
+    ((uint64_t *)&q->req[i].d)[w] = ld_sys((const uint64_t *)(q->host_ring + i) + w);
+  }
+  ReqState *r = q->req + (i0 + lane) % q->cap;
+  if ((uint64_t)lane < n) {
     volatile ReqState *vr = r;
     vr->done = 0;
     vr->aux = 0;
     vr->items = 0;
     vr->resume = PH_DONE;
-    __threadfence();
-    // one START chunk: the batch's first real phase is chosen when it runs,
-    // i.e. after every earlier batch on its table has finished
-    __hip_atomic_store(&r->state, make_state(PH_START, 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   }
-  __hip_atomic_store(&q->ingested, i, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-  if (stop && i == tail) __hip_atomic_store(&q->final_seen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_store(&q->ingest_lock, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  __threadfence();  // every lane's descriptor words and fields before any state
+  // one START chunk: the batch's first real phase is chosen when it runs,
+  // i.e. after every earlier batch on its table has finished
+  if ((uint64_t)lane < n)
+    __hip_atomic_store(&r->state, make_state(PH_START, 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  __threadfence();  // the states before the new ingest count
+  if (lane == 0) {
+    __hip_atomic_store(&q->ingested, i0 + n, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (stop && i0 + n == tail) __hip_atomic_store(&q->final_seen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&q->ingest_lock, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
-// Claim a run of chunks of runnable work: `*chunk` is the first, `*count`
-// how many (a phase of n chunks is claimed in grains of about n / (2 x grid)
-// chunks, so a large phase costs few claims: each is a chain of dependent
-// device-scope accesses, and the one on the request's state word is the
-// same address for every block).
-// Returns 0 (work), 1 (none now), 2 (exit).
+// Claim a run of chunks of runnable work, by the 64 lanes of one wave: lane
+// j looks at ring entry head + j of the window (its state, then whether its
+// table's previous batch is done), so a scan costs a few parallel round
+// trips instead of a chain of them per entry; the oldest runnable entry is
+// claimed first.  `*chunk` is the first chunk, `*count` how many (a phase of
+// n chunks is claimed in grains of about n / (2 x grid) chunks, so a large
+// phase costs few claims: the atomic on the request's state word is the
+// same address for every block); the claiming lane writes the outputs.
+// Returns, in every lane, 0 (work), 1 (none now) or 2 (exit).
+static_assert(DRAIN_WINDOW == 64, "one window entry per lane");
 __device__ uint32_t find_work(DrainQueue *q, uint64_t *req, uint32_t *phase, uint64_t *chunk, uint64_t *count,
                               uint64_t *nch) {
+  const int lane = threadIdx.x & 63;
   ingest(q);
-  const uint64_t ing = ld_ctl(&q->ingested);
-  uint64_t head = ld_ctl(&q->head);
-  // retire completed batches at the head of the ring
-  while (head < ing &&
-         (__hip_atomic_load(&q->req[head % q->cap].state, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >> 56) ==
-             PH_DONE) {
-    uint64_t h = head;
-    __hip_atomic_compare_exchange_strong(&q->head, &h, head + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                         __HIP_MEMORY_SCOPE_AGENT);
-    head = ld_ctl(&q->head);
+  const uint64_t ing = uniform64(ld_ctl(&q->ingested));
+  uint64_t head = uniform64(ld_ctl(&q->head));
+  // retire the completed batches at the head of the ring
+  {
+    const uint64_t t = head + lane;
+    const bool done = t < ing && (__hip_atomic_load(&q->req[t % q->cap].state, __ATOMIC_ACQUIRE,
+                                                    __HIP_MEMORY_SCOPE_AGENT) >> 56) == PH_DONE;
+    const uint64_t dm = ballot(done);
+    const int lead = (dm == ~0ull) ? 64 : __builtin_ctzll(~dm);
+    if (lead > 0) {
+      if (lane == 0) {
+        uint64_t h = head;
+        __hip_atomic_compare_exchange_strong(&q->head, &h, head + lead, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+      }
+      head = uniform64(ld_ctl(&q->head));
+    }
   }
   if (head == ing) {
     if (__hip_atomic_load(&q->final_seen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != 0 &&
@@ -1676,24 +1710,35 @@ __device__ uint32_t find_work(DrainQueue *q, uint64_t *req, uint32_t *phase, uin
       return 2;
     return 1;
   }
-  const uint64_t end = min(ing, head + DRAIN_WINDOW);
-  for (uint64_t t = head; t < end; ++t) {
-    ReqState *r = q->req + t % q->cap;
-    const uint64_t st = __hip_atomic_load(&r->state, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-    const uint32_t ph = (uint32_t)(st >> 56);
-    if (ph == PH_DONE || (st & M28) >= ((st >> 28) & M28)) continue;
-    const uint64_t slot = ld_ctl(&r->d.table_slot), seq = ld_ctl(&r->d.seq);
-    if (ld_ctl(&q->table_next[slot]) != seq) continue;
-    const uint64_t grain = max(1ull, ((st >> 28) & M28) / (2ull * gridDim.x));
-    const uint64_t old = add64(&r->state, grain);
-    const uint64_t n = (old >> 28) & M28, c = old & M28;
-    if ((uint32_t)(old >> 56) == PH_DONE || c >= n) continue;
-    *req = t;
-    *phase = (uint32_t)(old >> 56);
-    *chunk = c;
-    *count = min(grain, n - c);
-    *nch = n;
-    return 0;
+  const uint64_t t = head + lane;
+  ReqState *r = q->req + t % q->cap;
+  uint64_t st = 0;
+  bool runnable = false;
+  if (t < ing) {
+    st = __hip_atomic_load(&r->state, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    runnable = (uint32_t)(st >> 56) != PH_DONE && (st & M28) < ((st >> 28) & M28);
+    if (runnable) {
+      const uint64_t slot = ld_ctl(&r->d.table_slot), seq = ld_ctl(&r->d.seq);
+      runnable = ld_ctl(&q->table_next[slot]) == seq;
+    }
+  }
+  for (uint64_t m = ballot(runnable); m; m &= m - 1) {
+    const int j = __builtin_ctzll(m);
+    bool won = false;
+    if (lane == j) {
+      const uint64_t grain = max(1ull, ((st >> 28) & M28) / (2ull * gridDim.x));
+      const uint64_t old = add64(&r->state, grain);
+      const uint64_t n = (old >> 28) & M28, c = old & M28;
+      if ((uint32_t)(old >> 56) != PH_DONE && c < n) {
+        won = true;
+        *req = t;
+        *phase = (uint32_t)(old >> 56);
+        *chunk = c;
+        *count = min(grain, n - c);
+        *nch = n;
+      }
+    }
+    if (ballot(won)) return 0;
   }
   return 1;
 }
@@ -1739,10 +1784,6 @@ __device__ __forceinline__ ReqDesc uniform_desc(const ReqDesc &src) {
   return d;
 }
 
-__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
-  return ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(v >> 32)) << 32) |
-         __builtin_amdgcn_readfirstlane((uint32_t)v);
-}
 
 template <int S>
 __device__ __forceinline__ void run_chunk(ReqState *r, const ReqDesc &d, uint32_t ph, uint64_t c, OpsShared<S> &sh) {
@@ -1876,9 +1917,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
   uint64_t idle_since = wall_clock64();
   const uint64_t idle_ticks = ld_ctl(&q->idle_ticks);
   for (;;) {
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < 64) {
       uint32_t cmd = find_work(q, &s_req, &s_phase, &s_chunk, &s_cnt, &s_nch);
-      if (cmd == 1) {
+      if (threadIdx.x == 0 && cmd == 1) {
         const uint64_t ing = ld_ctl(&q->ingested), head = ld_ctl(&q->head);
         const uint64_t now = wall_clock64();
         if (ing != seen_ing || head != seen_head) {
@@ -1891,7 +1932,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
           cmd = 2;
         }
       }
-      s_cmd = cmd;
+      if (threadIdx.x == 0) s_cmd = cmd;
     }
     __syncthreads();
     const uint32_t cmd = s_cmd;
