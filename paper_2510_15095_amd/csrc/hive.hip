@@ -1587,8 +1587,10 @@ __device__ __forceinline__ void phase_fold(ReqState *rs, const ReqDesc &d, uint3
   __threadfence();
 }
 
-// Finish phase `ph` of r and publish the next one (one thread).
-__device__ void advance(DrainQueue *q, ReqState *rs, const ReqDesc &d, uint32_t ph) {
+// Finish phase `ph` of r and publish the next one (one thread).  Returns the
+// state word published for that phase (nothing claimed yet), or 0 when the
+// batch is done.
+__device__ uint64_t advance(DrainQueue *q, ReqState *rs, const ReqDesc &d, uint32_t ph) {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   volatile ReqState *r = rs;
   uint64_t nch = 0;
@@ -1610,10 +1612,32 @@ __device__ void advance(DrainQueue *q, ReqState *rs, const ReqDesc &d, uint32_t 
     __hip_atomic_store(&rs->state, make_state(PH_DONE, 0), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store(&q->host_done[ticket % q->cap], ticket + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     add64(&q->completed, 1);
-    return;
+    return 0;
   }
   __threadfence();
   __hip_atomic_store(&rs->state, make_state(ph, nch), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  return make_state(ph, nch);
+}
+
+// The block that published a batch's next phase claims its first grain at
+// once, without a window scan (the batch is running, so its table order is
+// already satisfied).  The claim is a CAS from exactly the published state:
+// if other blocks have claimed chunks meanwhile it fails and the block scans
+// as usual, and a ring slot reused by a later batch cannot match, since a
+// published phase is never PH_START.
+__device__ bool claim_published(ReqState *r, uint64_t published, uint32_t *phase, uint64_t *chunk, uint64_t *count,
+                                uint64_t *nch) {
+  const uint64_t n = (published >> 28) & M28;
+  const uint64_t grain = max(1ull, n / (2ull * gridDim.x));
+  uint64_t expect = published;
+  if (!__hip_atomic_compare_exchange_strong(&r->state, &expect, published + min(grain, n), __ATOMIC_ACQUIRE,
+                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+    return false;
+  *phase = (uint32_t)(published >> 56);
+  *chunk = 0;
+  *count = min(grain, n);
+  *nch = n;
+  return true;
 }
 
 // A value the whole wave holds, in a scalar register (the first active
@@ -1909,15 +1933,19 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
   __shared__ ReqDesc desc;
   __shared__ uint64_t s_req, s_chunk, s_cnt, s_nch;
   __shared__ uint32_t s_phase, s_cmd;
-  __shared__ bool s_last;
+  __shared__ bool s_last, s_cont;
   // watchdog (thread 0 decides for the block): time without any progress
   // of the queue as a whole (nothing newly ingested, nothing retired), so
   // blocks that merely find no chunk while others work do not give up
   uint64_t seen_ing = ~0ull, seen_head = ~0ull;
   uint64_t idle_since = wall_clock64();
   const uint64_t idle_ticks = ld_ctl(&q->idle_ticks);
+  if (threadIdx.x == 0) s_cont = false;
+  __syncthreads();
   for (;;) {
-    if (threadIdx.x < 64) {
+    // s_cont: this block claimed the next phase of its batch when it
+    // published it, so it needs no scan
+    if (threadIdx.x < 64 && !s_cont) {
       uint32_t cmd = find_work(q, &s_req, &s_phase, &s_chunk, &s_cnt, &s_nch);
       if (threadIdx.x == 0 && cmd == 1) {
         const uint64_t ing = ld_ctl(&q->ingested), head = ld_ctl(&q->head);
@@ -1935,7 +1963,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
       if (threadIdx.x == 0) s_cmd = cmd;
     }
     __syncthreads();
-    const uint32_t cmd = s_cmd;
+    const uint32_t cmd = s_cont ? 0u : s_cmd;
     if (cmd == 2) break;
     if (cmd == 1) {
       __builtin_amdgcn_s_sleep(7);  // about 450 clocks
@@ -1956,14 +1984,19 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
     if (threadIdx.x == 0) {
       __threadfence();  // these chunks' writes before their completion count
       s_last = add64(&r->done, s_cnt) + s_cnt == s_nch;
+      s_cont = false;
     }
     __syncthreads();
     if (s_last) {
       // the block that completed the phase: shard folds by wave 0, then the
-      // scalar epilogue and the next phase by thread 0
+      // scalar epilogue and the next phase by thread 0, which claims the
+      // start of that phase for this block
       if (threadIdx.x < 64) phase_fold(r, desc, phase);
       __syncthreads();
-      if (threadIdx.x == 0) advance(q, r, desc, phase);
+      if (threadIdx.x == 0) {
+        const uint64_t published = advance(q, r, desc, phase);
+        s_cont = published != 0 && claim_published(r, published, &s_phase, &s_chunk, &s_cnt, &s_nch);
+      }
     }
     __syncthreads();
   }
