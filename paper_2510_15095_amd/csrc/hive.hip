@@ -1571,8 +1571,10 @@ __device__ __forceinline__ void epilogue(volatile ReqState *r, const ReqDesc &d,
 // completed it): after the probe phase the key-count changes are folded and
 // the worklist is sized; after a stash drain the worklist is sized; after an
 // eviction phase its statistics are folded and the worklist emptied.
-__device__ __forceinline__ void phase_fold(ReqState *rs, const ReqDesc &d, uint32_t ph) {
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+// own: this block ran every chunk of the phase, so no other block's writes
+// need acquiring.
+__device__ __forceinline__ void phase_fold(ReqState *rs, const ReqDesc &d, uint32_t ph, bool own) {
+  if (!own) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   volatile ReqState *r = rs;
   Ctl *c = d.t.ctl;
   uint64_t items = 0;
@@ -1583,15 +1585,21 @@ __device__ __forceinline__ void phase_fold(ReqState *rs, const ReqDesc &d, uint3
     case PH_EVICT: (void)fold_shards_wave(c, true); break;
     default: return;
   }
-  if ((threadIdx.x & 63) == 0) r->items = items;
-  __threadfence();
+  if ((threadIdx.x & 63) == 0) r->items = items;  // read by the same thread in advance
 }
 
 // Finish phase `ph` of r and publish the next one (one thread).  Returns the
-// state word published for that phase (nothing claimed yet), or 0 when the
-// batch is done.
-__device__ uint64_t advance(DrainQueue *q, ReqState *rs, const ReqDesc &d, uint32_t ph) {
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+// state word published for that phase, or 0 when the batch is done.
+// own: this block ran every chunk of `ph`.  Then a next phase of at most
+// SOLO_CHUNKS chunks is published already fully claimed, by this block: a
+// small batch runs phase after phase in one block, without a window scan
+// and without the acquires (L2 invalidations) of a handoff, since no other
+// block writes its data meanwhile.  The release before publishing stays
+// (later phases read buckets with coherent loads, which must see this
+// block's plain stores), and so does the full release when the batch is done.
+constexpr uint64_t SOLO_CHUNKS = 4;
+__device__ uint64_t advance(DrainQueue *q, ReqState *rs, const ReqDesc &d, uint32_t ph, bool own) {
+  if (!own) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   volatile ReqState *r = rs;
   uint64_t nch = 0;
   epilogue(r, d, ph);
@@ -1614,9 +1622,10 @@ __device__ uint64_t advance(DrainQueue *q, ReqState *rs, const ReqDesc &d, uint3
     add64(&q->completed, 1);
     return 0;
   }
+  const uint64_t published = make_state(ph, nch) + (own && nch <= SOLO_CHUNKS ? nch : 0);
   __threadfence();
-  __hip_atomic_store(&rs->state, make_state(ph, nch), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-  return make_state(ph, nch);
+  __hip_atomic_store(&rs->state, published, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  return published;
 }
 
 // The block that published a batch's next phase claims its first grain at
@@ -1933,14 +1942,17 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
   __shared__ ReqDesc desc;
   __shared__ uint64_t s_req, s_chunk, s_cnt, s_nch;
   __shared__ uint32_t s_phase, s_cmd;
-  __shared__ bool s_last, s_cont;
+  __shared__ bool s_last, s_cont, s_solo;
   // watchdog (thread 0 decides for the block): time without any progress
   // of the queue as a whole (nothing newly ingested, nothing retired), so
   // blocks that merely find no chunk while others work do not give up
   uint64_t seen_ing = ~0ull, seen_head = ~0ull;
   uint64_t idle_since = wall_clock64();
   const uint64_t idle_ticks = ld_ctl(&q->idle_ticks);
-  if (threadIdx.x == 0) s_cont = false;
+  if (threadIdx.x == 0) {
+    s_cont = false;
+    s_solo = false;
+  }
   __syncthreads();
   for (;;) {
     // s_cont: this block claimed the next phase of its batch when it
@@ -1970,10 +1982,14 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
       __syncthreads();
       continue;
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     ReqState *r = q->req + s_req % q->cap;
-    load_desc(&desc, &r->d);
-    __syncthreads();
+    // s_solo: this block also ran the batch's previous phases alone since it
+    // last acquired, and its descriptor is still in LDS
+    if (!s_solo) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      load_desc(&desc, &r->d);
+      __syncthreads();
+    }
     const ReqDesc d = uniform_desc(desc);
     const uint32_t phase = __builtin_amdgcn_readfirstlane(s_phase);
     const uint64_t chunk = uniform64(s_chunk), cnt = uniform64(s_cnt);
@@ -1981,21 +1997,37 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
       run_chunk<S>(r, d, phase, chunk + k, sh);
       __syncthreads();
     }
+    const bool own = cnt == uniform64(s_nch);  // every chunk of the phase ran here
     if (threadIdx.x == 0) {
-      __threadfence();  // these chunks' writes before their completion count
-      s_last = add64(&r->done, s_cnt) + s_cnt == s_nch;
+      if (s_solo) {
+        s_last = true;  // the phase was published claimed by this block
+      } else {
+        __threadfence();  // these chunks' writes before their completion count
+        s_last = add64(&r->done, s_cnt) + s_cnt == s_nch;
+      }
       s_cont = false;
+      s_solo = false;
     }
     __syncthreads();
     if (s_last) {
       // the block that completed the phase: shard folds by wave 0, then the
       // scalar epilogue and the next phase by thread 0, which claims the
       // start of that phase for this block
-      if (threadIdx.x < 64) phase_fold(r, desc, phase);
+      if (threadIdx.x < 64) phase_fold(r, desc, phase, own);
       __syncthreads();
       if (threadIdx.x == 0) {
-        const uint64_t published = advance(q, r, desc, phase);
-        s_cont = published != 0 && claim_published(r, published, &s_phase, &s_chunk, &s_cnt, &s_nch);
+        const uint64_t published = advance(q, r, desc, phase, own);
+        const uint64_t n = (published >> 28) & M28;
+        if (published != 0 && (published & M28) == n) {  // published claimed by this block
+          s_phase = (uint32_t)(published >> 56);
+          s_chunk = 0;
+          s_cnt = n;
+          s_nch = n;
+          s_cont = true;
+          s_solo = true;
+        } else {
+          s_cont = published != 0 && claim_published(r, published, &s_phase, &s_chunk, &s_cnt, &s_nch);
+        }
       }
     }
     __syncthreads();
