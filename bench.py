@@ -39,7 +39,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=("bulk", "mixed", "resize", "served"), default="bulk")
+    ap.add_argument("--workload", choices=("bulk", "mixed", "resize", "served", "breakdown"), default="bulk")
     ap.add_argument("--executor", choices=("plain", "persistent"), default="plain",
                     help="mixed: one launch sequence per batch, or the persistent executor")
     ap.add_argument("--tables", type=int, default=256, help="served: tables")
@@ -106,7 +106,8 @@ def main():
     if not args.resize_k:
         args.resize_k = (tuned.get("resize") or {}).get("resize_k", 1024)
     args.blocks_per_cu = (tuned.get("executor") or {}).get("blocks_per_cu", 0)
-    run = {"bulk": run_bulk, "mixed": run_mixed, "resize": run_resize, "served": run_served}[args.workload]
+    run = {"bulk": run_bulk, "mixed": run_mixed, "resize": run_resize, "served": run_served,
+           "breakdown": run_breakdown}[args.workload]
     out = run(args) if pre is None else run(args, pre)
     if tuned:
         out["autotuned"] = {k: v for k, v in tuned.items() if v}
@@ -277,6 +278,80 @@ def run_served(args, pre):
                        "poisson_rate_req_per_s": round(rate, 1)})
     rec["served"] = {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                      for k, v in res.items()}
+    return rec
+
+
+BREAKDOWN_LF = (0.55, 0.65, 0.75, 0.85, 0.90, 0.95, 0.97)
+
+
+def run_breakdown(args):
+    """Insert time by step against load factor (where Section V says insert
+    time goes: steps 1 and 2 dominate at moderate load, the stash step grows
+    near full).  A FIXED table of the bulk geometry (4,415,057 x 16-slot
+    buckets) is built in slices, from empty to 55% load and then to 65, 75,
+    85, 90, 95 and 97%, one hive_insert_batch of unique uniform keys per
+    slice, with phase timing on: steps 1 and 2 (replace, claim-then-commit)
+    run in the probe launch, steps 3 and 4 (bounded cuckoo chains, then stash
+    or pending) in the eviction launch.  Per slice: both times, the eviction
+    share, items sent to eviction, displacements and stash placements;
+    medians over the timed builds."""
+    import torch
+    from paper_2510_15095_amd import hive as H
+    from paper_2510_15095_amd import workload as wl
+    nb = 4415057
+    slots = nb * S
+    bounds = [0] + [int(round(f * slots)) for f in BREAKDOWN_LF]
+    ks = wl.KeyStream(6)
+    keys = ks.range(0, bounds[-1])
+    dk = torch.from_numpy(keys).cuda()
+    dv = torch.from_numpy(wl.values_for(keys)).cuda()
+    del keys
+    widest = max(b - a for a, b in zip(bounds, bounds[1:]))
+    t = H.Table(nb, slots_per_bucket=S, max_evictions=8, max_batch=widest)
+    H.hive_phase_timing(t.h, True)
+    fields = ("evictions", "evict_items", "stash_inserts", "pending_inserts")
+
+    def build():
+        t.clear()
+        torch.cuda.synchronize()
+        H.hive_phase_times(t.h)
+        prev = t.stats()
+        rows = []
+        for a, b in zip(bounds, bounds[1:]):
+            t.insert(dk[a:b], dv[a:b], flags=H.HIVE_UNIQUE)
+            ph = H.hive_phase_times(t.h)
+            st = t.stats()
+            rows.append({"inserts": b - a, **{k: ph[k] for k in ("probe", "evict", "finish")},
+                         **{f: st[f] - prev[f] for f in fields}})
+            prev = st
+        assert st["status"] in (H.HIVE_OK, H.HIVE_WARN_PENDING) and st["live"] == bounds[-1], st
+        return rows
+
+    for _ in range(args.warmup):
+        build()
+    runs = [build() for _ in range(args.steps)]
+    out_rows = []
+    lo = 0.0
+    for i, hi in enumerate(BREAKDOWN_LF):
+        probe = float(np.median([r[i]["probe"] for r in runs]))
+        evict = float(np.median([r[i]["evict"] for r in runs]))
+        fin = float(np.median([r[i]["finish"] for r in runs]))
+        last = runs[-1][i]
+        out_rows.append({"load_from": lo, "load_to": hi, "inserts": last["inserts"],
+                         "steps12_ms": round(probe, 4), "steps34_ms": round(evict, 4), "finish_ms": round(fin, 4),
+                         "steps34_share": round(evict / (probe + evict), 4),
+                         "to_eviction": last["evict_items"], "displacements": last["evictions"],
+                         "stash": last["stash_inserts"], "pending": last["pending_inserts"],
+                         "mops": round(last["inserts"] / ((probe + evict + fin) * 1e-3) / 1e6, 1)})
+        lo = hi
+    total_ms = sum(r["steps12_ms"] + r["steps34_ms"] + r["finish_ms"] for r in out_rows)
+    rec = base_record(args, bounds[-1] / (total_ms * 1e-3) / 1e6, total_ms,
+                      f"insert time by step: FIXED {nb} x {S}-slot buckets built from empty to 97% load in "
+                      f"{len(BREAKDOWN_LF)} slices of unique uniform keys, probe launch (steps 1-2) and eviction "
+                      f"launch (steps 3-4) timed apart",
+                      {"slices": len(BREAKDOWN_LF), "max_evictions": 8})
+    rec["breakdown"] = out_rows
+    t.close()
     return rec
 
 

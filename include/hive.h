@@ -191,6 +191,27 @@ hive_status hive_clear(hive_t h, void *stream);
 /* A short English description of a status code (static storage). */
 const char *hive_status_string(hive_status s);
 
+/* ---- Phase timing (a measurement aid; off by default) --------------------
+ * While enabled, every batch call records HIP events on its stream at the
+ * boundaries of its phase groups (Section IV-A's insert steps map onto
+ * them: steps 1 and 2 run in the probe launch, steps 3 and 4 in the
+ * eviction launch).  hive_phase_times waits for the recorded events and
+ * writes, per group, the milliseconds spent since the previous
+ * hive_phase_times call, then starts over: ms_out is a caller-owned host
+ * array of HIVE_PHASE_KINDS doubles.  The events are ordered on each call's
+ * own stream only.  HIVE_ERR_HIP if waiting for the events failed. */
+enum {
+  HIVE_PHASE_DEDUPE = 0,  /* dedupe set fill and build */
+  HIVE_PHASE_PROBE = 1,   /* probe launch: replace, claim (steps 1-2), lookup, delete */
+  HIVE_PHASE_EVICT = 2,   /* eviction chains and stash/pending placement (steps 3-4) */
+  HIVE_PHASE_RESIZE = 3,  /* load-factor plans and split/merge passes */
+  HIVE_PHASE_DRAIN = 4,   /* stash drain after splits and its re-placement */
+  HIVE_PHASE_FINISH = 5,  /* counter folds after a batch */
+  HIVE_PHASE_KINDS = 6
+};
+hive_status hive_phase_timing(hive_t h, int enable);
+hive_status hive_phase_times(hive_t h, double *ms_out);
+
 /* ---- Persistent executor ------------------------------------------------
  * One resident grid drains a queue of batches in one launch (a hipGraph
  * captured once and replayed).  Each batch runs the same phases and gives

@@ -37,6 +37,7 @@
 #include <new>
 #include <thread>
 #include <type_traits>
+#include <vector>
 
 #include "hive.h"
 #include "hive_device.hpp"
@@ -2059,6 +2060,18 @@ struct hive_table {
   uint64_t dd_cap = 0;  // power of two
   uint64_t bytes = 0;
   hipStream_t last = nullptr;
+  // phase timing (hive_phase_timing): events at phase boundaries, spans
+  // [a, b) of one phase group each, waiting to be read
+  struct Span {
+    int kind;
+    hipEvent_t a, b;
+  };
+  bool timing = false;
+  int open_kind = -1;
+  hipEvent_t open_ev = nullptr;
+  std::vector<Span> spans;
+  std::vector<hipEvent_t> free_events;
+  std::vector<hipEvent_t> all_events;
 };
 
 struct hive_drain {
@@ -2156,6 +2169,7 @@ static hive_status reset_table(hive_table *h, hipStream_t st) {
 
 static void free_table(hive_table *h) {
   if (!h) return;
+  for (hipEvent_t e : h->all_events) (void)hipEventDestroy(e);
   (void)hipFree(h->d_buckets);
   (void)hipFree(h->d_hint);
   (void)hipFree(h->d_stash);
@@ -2271,10 +2285,33 @@ static void launch_resize_passes(const ResizeArgs &ra, int rounds, hipStream_t s
   }
 }
 
+// Phase timing: close the open span (if any) at an event recorded now on
+// `st` and open one of `kind` there (kind < 0: open none).  Off unless
+// hive_phase_timing enabled it; a failure to get an event turns it off.
+static void phase_mark(hive_table *h, int kind, hipStream_t st) {
+  if (!h->timing) return;
+  hipEvent_t e = nullptr;
+  if (!h->free_events.empty()) {
+    e = h->free_events.back();
+    h->free_events.pop_back();
+  } else if (hipEventCreate(&e) == hipSuccess) {
+    h->all_events.push_back(e);
+  } else {
+    (void)hipGetLastError();
+    h->timing = false;
+    return;
+  }
+  (void)hipEventRecord(e, st);
+  if (h->open_kind >= 0) h->spans.push_back({h->open_kind, h->open_ev, e});
+  h->open_kind = kind;
+  h->open_ev = e;
+}
+
 static hive_status resize_sequence(hive_table *h, uint32_t mode, uint64_t amount, const uint8_t *d_ops,
                                    hipStream_t st) {
   ResizeArgs ra{h->d_buckets, h->d_hint, h->d_ctl, h->S, h->cfg.resize_k, h->cfg.lf_expand_pct,
                 h->cfg.lf_contract_pct};
+  phase_mark(h, HIVE_PHASE_RESIZE, st);
   hipLaunchKernelGGL(resize_plan_kernel, dim3(1), dim3(BLOCK), 0, st, ra, mode, amount, d_ops);
   const int rounds = resize_rounds(h);
   switch (h->S) {
@@ -2282,6 +2319,7 @@ static hive_status resize_sequence(hive_table *h, uint32_t mode, uint64_t amount
     case 32: launch_resize_passes<32>(ra, rounds, st); break;
     default: launch_resize_passes<64>(ra, rounds, st); break;
   }
+  phase_mark(h, HIVE_PHASE_DRAIN, st);
   hipLaunchKernelGGL(drain_kernel, dim3(DRAIN_GRID), dim3(BLOCK), 0, st, h->d_stash, h->stash_cap, h->d_pending,
                      h->pending_cap, h->d_hint, hint_words(h->max_buckets), h->d_wl, h->wl_seg_cap, h->d_ctl);
   launch_evict(h, h->stash_cap + h->pending_cap, st);  // live entries of a drain
@@ -2402,6 +2440,7 @@ static hive_status run_batch(hive_t h, uint32_t mode, const uint8_t *d_ops, cons
   a.stash_cap = h->stash_cap;
   a.pending_cap = h->pending_cap;
   if (dedupe) {
+    phase_mark(h, HIVE_PHASE_DEDUPE, st);
     uint64_t cap = 16;
     while (cap < 2 * n) cap <<= 1;
     if ((s = fill_u64(h->d_dd, cap, EMPTY, st)) != HIVE_OK) return s;
@@ -2416,6 +2455,7 @@ static hive_status run_batch(hive_t h, uint32_t mode, const uint8_t *d_ops, cons
     // grow before the batch so that live + (inserts of the batch) fits
     if ((s = resize_sequence(h, mode == OP_MIXED ? PLAN_PRE_MIXED : PLAN_PRE, n, d_ops, st)) != HIVE_OK) return s;
   }
+  phase_mark(h, HIVE_PHASE_PROBE, st);
   switch (h->S) {
     case 16:
       if (h->cfg.probe_both)
@@ -2427,12 +2467,19 @@ static hive_status run_batch(hive_t h, uint32_t mode, const uint8_t *d_ops, cons
     default: launch_ops_mode<64, false>(mode, a, st); break;
   }
   if ((s = launch_check()) != HIVE_OK) return s;
-  if (mode == OP_INSERT || mode == OP_MIXED) launch_evict(h, n, st);
-  if (mode != OP_LOOKUP) launch_finish(h, st);
+  if (mode == OP_INSERT || mode == OP_MIXED) {
+    phase_mark(h, HIVE_PHASE_EVICT, st);
+    launch_evict(h, n, st);
+  }
+  if (mode != OP_LOOKUP) {
+    phase_mark(h, HIVE_PHASE_FINISH, st);
+    launch_finish(h, st);
+  }
   if ((s = launch_check()) != HIVE_OK) return s;
   if (linear && h->cfg.post_policy && mode != OP_LOOKUP) {
     if ((s = resize_sequence(h, PLAN_POST, 0, nullptr, st)) != HIVE_OK) return s;
   }
+  phase_mark(h, -1, st);
   return HIVE_OK;
 }
 
@@ -2507,6 +2554,35 @@ hive_status hive_create(const hive_config *cfg_in, uint64_t initial_buckets, voi
   }
   *out = h;
   return HIVE_OK;
+}
+
+hive_status hive_phase_timing(hive_t h, int enable) {
+  if (!h) return HIVE_ERR_ARG;
+  h->timing = enable != 0;
+  return HIVE_OK;
+}
+
+hive_status hive_phase_times(hive_t h, double *ms_out) {
+  if (!h || !ms_out) return HIVE_ERR_ARG;
+  for (int k = 0; k < HIVE_PHASE_KINDS; ++k) ms_out[k] = 0.0;
+  hive_status s = HIVE_OK;
+  if (!h->spans.empty() && hipEventSynchronize(h->spans.back().b) != hipSuccess) s = HIVE_ERR_HIP;
+  std::vector<hipEvent_t> used;
+  for (const auto &sp : h->spans) {
+    float ms = 0.f;
+    if (s == HIVE_OK && hipEventElapsedTime(&ms, sp.a, sp.b) == hipSuccess) ms_out[sp.kind] += ms;
+    used.push_back(sp.a);
+    used.push_back(sp.b);
+  }
+  // an event may end one span and start the next: free each once, except
+  // the start of a span still open
+  std::sort(used.begin(), used.end());
+  used.erase(std::unique(used.begin(), used.end()), used.end());
+  for (hipEvent_t e : used)
+    if (!(h->open_kind >= 0 && e == h->open_ev)) h->free_events.push_back(e);
+  h->spans.clear();
+  if (s != HIVE_OK) (void)hipGetLastError();
+  return s;
 }
 
 hive_status hive_destroy(hive_t h) {

@@ -116,6 +116,8 @@ def _load():
         "hive_drain_poll": ([p, u64, ctypes.POINTER(st)], st),
         "hive_drain_result": ([p, u64, ctypes.POINTER(st), ctypes.POINTER(u64)], st),
         "hive_drain_results": ([p, p, u64, p, p], st),
+        "hive_phase_timing": ([p, st], st),
+        "hive_phase_times": ([p, p], st),
         "hive_drain_stop": ([p, p], st),
         "hive_drain_destroy": ([p], st),
     }
@@ -332,6 +334,20 @@ def hive_drain_results(d, tickets):
     _check(_lib.hive_drain_results(d, t.ctypes.data, t.size, done.ctypes.data, live.ctypes.data),
            "hive_drain_results")
     return done.astype(bool), live
+
+
+PHASE_KINDS = ("dedupe", "probe", "evict", "resize", "drain", "finish")
+
+
+def hive_phase_timing(h, enable: bool) -> None:
+    _check(_lib.hive_phase_timing(h, int(bool(enable))), "hive_phase_timing")
+
+
+def hive_phase_times(h) -> dict:
+    """Milliseconds per phase group since the previous call (then reset)."""
+    out = (ctypes.c_double * len(PHASE_KINDS))()
+    _check(_lib.hive_phase_times(h, out), "hive_phase_times")
+    return {k: float(out[i]) for i, k in enumerate(PHASE_KINDS)}
 
 
 def hive_drain_stop(d, stream=None) -> None:

@@ -106,6 +106,8 @@ def test_null_handle_and_arguments_rejected(H):
     assert lib.hive_destroy(None) == H.HIVE_ERR_ARG
     assert lib.hive_drain_results(None, None, 0, None, None) == H.HIVE_ERR_ARG
     assert lib.hive_drain_result(None, 0, None, None) == H.HIVE_ERR_ARG
+    assert lib.hive_phase_timing(None, 1) == H.HIVE_ERR_ARG
+    assert lib.hive_phase_times(None, None) == H.HIVE_ERR_ARG
     assert lib.hive_status_string(H.HIVE_ERR_LOST).decode().startswith("pending")
 
 

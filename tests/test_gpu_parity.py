@@ -226,6 +226,49 @@ def test_eviction_stash_pending_heavy(H, E, stash, lf):
     t.close()
 
 
+def test_phase_timing_groups_reset_and_results(H):
+    """Phase timing: an insert call times its dedupe, probe, eviction and
+    finish groups, a lookup only its probe launch, a LINEAR insert also its
+    resize and drain groups; reading resets, many calls between reads are
+    summed, turning it off stops it, and results are unchanged."""
+    S, nb = 16, 97
+    n = int(S * nb * 0.97)
+    ks = wl.KeyStream(90)
+    keys = ks.range(0, n)
+    vals = wl.values_for(keys)
+    t = H.Table(nb, stash_capacity=1024, pending_capacity=4096)
+    o = oracle.O1()
+    H.hive_phase_timing(t.h, True)
+    t.insert(dev(keys), dev(vals))  # not flagged unique: the dedupe set runs
+    o.insert(keys, vals)
+    ms = H.hive_phase_times(t.h)
+    assert ms["dedupe"] > 0 and ms["probe"] > 0 and ms["evict"] > 0 and ms["finish"] > 0, ms
+    assert ms["resize"] == 0 and ms["drain"] == 0, ms
+    assert all(x == 0 for x in H.hive_phase_times(t.h).values())
+    q = ks.range(0, n + 100)
+    v, f = t.lookup(dev(q))
+    ms = H.hive_phase_times(t.h)
+    assert ms["probe"] > 0 and ms["evict"] == ms["dedupe"] == ms["finish"] == 0, ms
+    ov, of = o.lookup(q)
+    assert np.array_equal(host(f), of) and np.array_equal(host(v), ov)
+    for _ in range(40):
+        t.lookup(dev(q[:64]))
+    assert H.hive_phase_times(t.h)["probe"] > 0
+    H.hive_phase_timing(t.h, False)
+    t.lookup(dev(q))
+    assert all(x == 0 for x in H.hive_phase_times(t.h).values())
+    assert np.array_equal(t.dump(), o.dump())
+    t.close()
+    lt = linear_table(H, 8, 4096, 64)
+    H.hive_phase_timing(lt.h, True)
+    lk = ks.range(10_000, 13_000)
+    lt.insert(dev(lk), dev(wl.values_for(lk)), flags=H.HIVE_UNIQUE)
+    ms = H.hive_phase_times(lt.h)
+    assert ms["resize"] > 0 and ms["drain"] > 0 and ms["probe"] > 0, ms
+    assert lt.stats()["live"] == lk.size
+    lt.close()
+
+
 def test_large_stash_probe_runs(H):
     """Thousands of entries in the stash (no cuckoo chains, buckets far over
     capacity): searches, replaces, deletes (tombstones) and re-inserts all go
