@@ -285,9 +285,9 @@ BREAKDOWN_LF = (0.55, 0.65, 0.75, 0.85, 0.90, 0.95, 0.97)
 
 
 def run_breakdown(args):
-    """Insert time by step against load factor (where Section V says insert
-    time goes: steps 1 and 2 dominate at moderate load, the stash step grows
-    near full).  A FIXED table of the bulk geometry (4,415,057 x 16-slot
+    """Insert time by step against load factor (the insertion step breakdown
+    of Section V-D: steps 1 and 2 dominate at moderate load, the later steps
+    grow near full).  A FIXED table of the bulk geometry (4,415,057 x 16-slot
     buckets) is built in slices, from empty to 55% load and then to 65, 75,
     85, 90, 95 and 97%, one hive_insert_batch of unique uniform keys per
     slice, with phase timing on: steps 1 and 2 (replace, claim-then-commit)
