@@ -73,6 +73,16 @@ def bind(path: str):
     L.o2_bithash2.restype = u32
     L.o2_bucket_of.argtypes = [p, u32]
     L.o2_bucket_of.restype = u64
+    L.hs_crc32.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
+    L.hs_crc32.restype = u32
+    L.hs_crc64.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
+    L.hs_crc64.restype = u64
+    L.hs_murmur3.argtypes = [ctypes.c_char_p, ctypes.c_size_t, u32]
+    L.hs_murmur3.restype = u32
+    L.hs_city32_short.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
+    L.hs_city32_short.restype = u32
+    L.hs_buckets.argtypes = [i32, p, u64, u64, p]
+    L.hs_buckets.restype = i32
     return L
 
 
@@ -228,3 +238,50 @@ def bithash1(key: int) -> int:
 
 def bithash2(key: int) -> int:
     return int(lib().o2_bithash2(key))
+
+
+# ---- hash-function study (Section III-C; plain transcriptions in hash_study.c)
+HASH_KINDS = ("bithash1", "bithash2", "crc32", "crc64", "murmur3", "city32")
+
+
+def crc32_bytes(data: bytes) -> int:
+    return int(lib().hs_crc32(data, len(data)))
+
+
+def crc64_bytes(data: bytes) -> int:
+    return int(lib().hs_crc64(data, len(data)))
+
+
+def murmur3_bytes(data: bytes, seed: int = 0) -> int:
+    return int(lib().hs_murmur3(data, len(data), seed))
+
+
+def city32_bytes(data: bytes) -> int:
+    """CityHash32 of at most four bytes."""
+    assert len(data) <= 4
+    return int(lib().hs_city32_short(data, len(data)))
+
+
+def hash_buckets(kind: str, keys, m: int) -> np.ndarray:
+    """Bucket of every key: the hash of its four little-endian bytes mod m."""
+    k = np.ascontiguousarray(keys, dtype=np.uint32)
+    out = np.empty(k.size, np.uint32)
+    rc = lib().hs_buckets(HASH_KINDS.index(kind), _ptr(k), k.size, m, _ptr(out))
+    if rc != 0:
+        raise ValueError(f"bad hash kind or m: {kind}, {m}")
+    return out
+
+
+def collisions(buckets, m: int) -> int:
+    """Y = sum over the m buckets of (load - 1)+, loads counted directly."""
+    loads = np.bincount(np.asarray(buckets, dtype=np.int64), minlength=m)
+    return int(np.maximum(loads - 1, 0).sum())
+
+
+def expected_collisions(n: int, m: int) -> float:
+    """E[Y] for n keys thrown independently and uniformly into m buckets
+    (the uniform-hashing theorem of Section III-C): n - m (1 - (1 - 1/m)^n)."""
+    if m == 1:
+        return float(max(n - 1, 0))
+    return float(n - m * -np.expm1(n * np.log1p(-1.0 / m)))
+
