@@ -39,7 +39,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=("bulk", "mixed", "resize", "served", "breakdown"), default="bulk")
+    ap.add_argument("--workload", choices=("bulk", "mixed", "resize", "served", "breakdown", "hashes"),
+                    default="bulk")
     ap.add_argument("--executor", choices=("plain", "persistent"), default="plain",
                     help="mixed: one launch sequence per batch, or the persistent executor")
     ap.add_argument("--tables", type=int, default=256, help="served: tables")
@@ -107,7 +108,7 @@ def main():
         args.resize_k = (tuned.get("resize") or {}).get("resize_k", 1024)
     args.blocks_per_cu = (tuned.get("executor") or {}).get("blocks_per_cu", 0)
     run = {"bulk": run_bulk, "mixed": run_mixed, "resize": run_resize, "served": run_served,
-           "breakdown": run_breakdown}[args.workload]
+           "breakdown": run_breakdown, "hashes": run_hashes}[args.workload]
     out = run(args) if pre is None else run(args, pre)
     if tuned:
         out["autotuned"] = {k: v for k, v in tuned.items() if v}
@@ -352,6 +353,58 @@ def run_breakdown(args):
                       {"slices": len(BREAKDOWN_LF), "max_evictions": 8})
     rec["breakdown"] = out_rows
     t.close()
+    return rec
+
+
+def run_hashes(args):
+    """Hash-function study (Section III-C): the collision speedup ratio
+    CSR = E[Y] / Y of BitHash1/2, CRC-32, CRC-64, MurmurHash3 and CityHash32
+    over m = 512^2 buckets for n = 512 ... 2048^2 keys (E[Y] from the
+    uniform-hashing theorem), for unique uniform keys and for the sequential
+    keys 1..n (the paper does not say which keys it hashed); then each hash's
+    rate over 2^26 keys (key in, bucket out, timed with HIP events)."""
+    import torch
+    from paper_2510_15095_amd import hash_study as hs
+    from paper_2510_15095_amd import hive as H
+    from paper_2510_15095_amd import workload as wl
+    m = 512 * 512
+    ns = [512 << k for k in range(14)]  # 512 ... 4,194,304 = 2048^2
+    uniform = torch.from_numpy(wl.KeyStream(7).range(0, ns[-1])).cuda()
+    sequential = torch.arange(1, ns[-1] + 1, dtype=torch.int64).to(torch.uint32).cuda()
+    scratch = torch.empty(2 + m // 32, dtype=torch.uint32, device="cuda")
+    csr = {}
+    for name, keys in (("uniform", uniform), ("sequential", sequential)):
+        csr[name] = {}
+        for kind in H.HASH_KINDS:
+            row = []
+            for n in ns:
+                y = H.hive_hash_collisions(kind, keys[:n], m, scratch)
+                row.append(round(hs.csr(n, m, y), 4))
+            csr[name][kind] = row
+    big = torch.from_numpy(wl.KeyStream(8).range(0, 1 << args.keys_log2)).cuda()
+    out = torch.empty_like(big)
+    rates = {}
+    reps = max(args.steps, 1)
+    for kind in H.HASH_KINDS:
+        for _ in range(max(args.warmup, 1)):
+            H.hive_hash_buckets(kind, big, m, out)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            H.hive_hash_buckets(kind, big, m, out)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / reps
+        rates[kind] = {"ms": round(ms, 4), "mops": round(big.numel() / (ms * 1e-3) / 1e6, 1),
+                       "gb_s": round(8 * big.numel() / (ms * 1e-3) / 1e9, 1)}
+    rec = base_record(args, rates["bithash1"]["mops"], rates["bithash1"]["ms"],
+                      f"hash study: CSR of 6 hashes over 512^2 buckets for 512..2048^2 uniform and sequential keys; "
+                      f"hash rate over 2^{args.keys_log2} keys (value: BitHash1)", {"buckets": m, "n": ns})
+    rec["csr"] = csr
+    rec["rates"] = rates
+    rec["roofline"] = {"kernel": "hash_study bucket_kernel (BitHash1)", "bound": "hbm",
+                       "achieved": rates["bithash1"]["gb_s"], "peak": 8000.0, "unit": "GB/s",
+                       "frac": round(rates["bithash1"]["gb_s"] / 8000.0, 4), "traffic": None}
     return rec
 
 

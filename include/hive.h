@@ -212,6 +212,41 @@ enum {
 hive_status hive_phase_timing(hive_t h, int enable);
 hive_status hive_phase_times(hive_t h, double *ms_out);
 
+/* ---- Hash-function study (Section III-C) ----------------------------------
+ * The spread of BitHash1/2 and of widely used hashes over m buckets.  Each
+ * hash reads a key as its four little-endian bytes; a key's bucket is the
+ * hash modulo m (all 64 bits for CRC-64):
+ *   HIVE_HASH_CRC32    reflected 0xEDB88320, all-ones init and final xor;
+ *   HIVE_HASH_CRC64    reflected 0xC96C5795D7870F42 (ECMA-182, as in xz),
+ *                      all-ones init and final xor;
+ *   HIVE_HASH_MURMUR3  MurmurHash3, x86 32-bit variant, seed 0;
+ *   HIVE_HASH_CITY32   CityHash32 (its path for inputs of at most 4 bytes).
+ * The CRCs are table-driven (tables in LDS), the others ALU only. */
+enum {
+  HIVE_HASH_BITHASH1 = 0,
+  HIVE_HASH_BITHASH2 = 1,
+  HIVE_HASH_CRC32 = 2,
+  HIVE_HASH_CRC64 = 3,
+  HIVE_HASH_MURMUR3 = 4,
+  HIVE_HASH_CITY32 = 5,
+  HIVE_HASH_KINDS = 6
+};
+
+/* d_out[i] = bucket of d_keys[i] under hash `kind` (device arrays of n
+ * entries, caller-owned), stream-ordered, no synchronization.  HIVE_ERR_ARG
+ * for an unknown kind, m = 0 or m > 2^32, or a null array with n > 0. */
+hive_status hive_hash_buckets(uint32_t kind, const uint32_t *d_keys, uint64_t n, uint64_t m, uint32_t *d_out,
+                              void *stream);
+
+/* *y_out = sum over the m buckets of (load - 1)+ for the n keys of d_keys
+ * under hash `kind`, the collision count Y of the uniform-hashing theorem
+ * (Section III-C; equal to n minus the number of occupied buckets).
+ * d_scratch: caller-owned device memory of at least 2 + ceil(m / 32) 32-bit
+ * words, overwritten.  Synchronizes `stream`.  HIVE_ERR_ARG as for
+ * hive_hash_buckets, or for a null d_scratch or y_out. */
+hive_status hive_hash_collisions(uint32_t kind, const uint32_t *d_keys, uint64_t n, uint64_t m, uint32_t *d_scratch,
+                                 uint64_t *y_out, void *stream);
+
 /* ---- Persistent executor ------------------------------------------------
  * One resident grid drains a queue of batches in one launch (a hipGraph
  * captured once and replayed).  Each batch runs the same phases and gives

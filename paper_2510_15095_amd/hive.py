@@ -117,6 +117,8 @@ def _load():
         "hive_drain_result": ([p, u64, ctypes.POINTER(st), ctypes.POINTER(u64)], st),
         "hive_drain_results": ([p, p, u64, p, p], st),
         "hive_phase_timing": ([p, st], st),
+        "hive_hash_buckets": ([u32, p, u64, u64, p, p], st),
+        "hive_hash_collisions": ([u32, p, u64, u64, p, p, p], st),
         "hive_phase_times": ([p, p], st),
         "hive_drain_stop": ([p, p], st),
         "hive_drain_destroy": ([p], st),
@@ -334,6 +336,29 @@ def hive_drain_results(d, tickets):
     _check(_lib.hive_drain_results(d, t.ctypes.data, t.size, done.ctypes.data, live.ctypes.data),
            "hive_drain_results")
     return done.astype(bool), live
+
+
+HASH_KINDS = ("bithash1", "bithash2", "crc32", "crc64", "murmur3", "city32")
+HIVE_HASH_KINDS = len(HASH_KINDS)
+
+
+def hive_hash_buckets(kind: str, keys, m: int, out, stream=None) -> None:
+    """out[i] = bucket of keys[i] under hash `kind` (uint32 GPU tensors)."""
+    import torch
+    n = keys.numel()
+    _check(_lib.hive_hash_buckets(HASH_KINDS.index(kind), _dev(keys, torch.uint32, "keys"), n, m,
+                                  _dev(out, torch.uint32, "out", n), _stream_ptr(stream)), "hive_hash_buckets")
+
+
+def hive_hash_collisions(kind: str, keys, m: int, scratch, stream=None) -> int:
+    """Collision count Y of `keys` over m buckets; scratch: uint32 GPU tensor
+    of at least 2 + ceil(m / 32) words."""
+    import torch
+    y = ctypes.c_uint64()
+    _check(_lib.hive_hash_collisions(HASH_KINDS.index(kind), _dev(keys, torch.uint32, "keys"), keys.numel(), m,
+                                     _dev(scratch, torch.uint32, "scratch", 2 + (m + 31) // 32),
+                                     ctypes.byref(y), _stream_ptr(stream)), "hive_hash_collisions")
+    return int(y.value)
 
 
 PHASE_KINDS = ("dedupe", "probe", "evict", "resize", "drain", "finish")

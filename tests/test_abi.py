@@ -108,6 +108,11 @@ def test_null_handle_and_arguments_rejected(H):
     assert lib.hive_drain_result(None, 0, None, None) == H.HIVE_ERR_ARG
     assert lib.hive_phase_timing(None, 1) == H.HIVE_ERR_ARG
     assert lib.hive_phase_times(None, None) == H.HIVE_ERR_ARG
+    assert lib.hive_hash_buckets(H.HIVE_HASH_KINDS, None, 0, 8, None, None) == H.HIVE_ERR_ARG
+    assert lib.hive_hash_buckets(0, None, 0, 0, None, None) == H.HIVE_ERR_ARG
+    assert lib.hive_hash_buckets(0, None, 0, (1 << 32) + 1, None, None) == H.HIVE_ERR_ARG
+    assert lib.hive_hash_buckets(0, None, 0, 8, None, None) == H.HIVE_OK  # empty: nothing to launch
+    assert lib.hive_hash_collisions(0, None, 0, 8, None, None, None) == H.HIVE_ERR_ARG
     assert lib.hive_status_string(H.HIVE_ERR_LOST).decode().startswith("pending")
 
 

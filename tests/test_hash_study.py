@@ -100,3 +100,16 @@ def test_uniform_random_buckets_agree_with_expectation():
     b = np.random.default_rng(5).integers(0, m, n)
     csr = oracle.expected_collisions(n, m) / oracle.collisions(b, m)
     assert 0.95 < csr < 1.05
+
+
+@pytest.mark.parametrize("n,m", [(0, 7), (1, 7), (5, 1), (512, 512 * 512), (2048 * 2048, 512 * 512), (10 ** 6, 4415057)])
+def test_package_expectation_equals_oracle(n, m):
+    from paper_2510_15095_amd import hash_study as hs
+    assert hs.expected_collisions(n, m) == pytest.approx(oracle.expected_collisions(n, m), rel=1e-12, abs=1e-9)
+
+
+def test_csr_definition():
+    from paper_2510_15095_amd import hash_study as hs
+    assert hs.csr(100, 10, 0) == float("inf")
+    assert hs.csr(8192, 4096, 4000) == pytest.approx(oracle.expected_collisions(8192, 4096) / 4000)
+
