@@ -819,12 +819,13 @@ __device__ __forceinline__ bool group_claim(uint64_t *bkt, typename Traits<S>::M
 }
 
 // P3: items whose two buckets were full in P1 (or stash entries re-placed
-// after a split), one 16-lane group per item.  Step 2 is tried again with a
-// fresh view of both buckets (two-choice), then the bounded cuckoo chain of
-// Algorithm 3: each round claims a free slot of the current bucket or
-// displaces a victim by CAS and carries the victim to its alternate bucket.
-// An item still in hand after max_evictions displacements goes to the stash
-// ring, or to the pending list when the ring is full.
+// after a split), one group per item (a group of the eviction shape: one
+// lane for 16-slot buckets).  Step 2 is tried again with a fresh view of
+// both buckets (two-choice), then the bounded cuckoo chain of Algorithm 3:
+// each round claims a free slot of the current bucket or displaces a victim
+// by CAS and carries the victim to its alternate bucket.  Returns whether
+// the item was placed; if not, the caller sends the entry in hand to the
+// stash (or the pending list when the stash is full).
 template <int S>
 __device__ __forceinline__ bool evict_chain(const EvictArgs &a, const Geo &geo, uint64_t &kv, uint32_t max_kicks,
                                             int g, int sl, uint64_t &n_evict) {
@@ -932,13 +933,9 @@ __device__ __forceinline__ void evict_counters(const EvictArgs &a, bool unreserv
   }
 }
 
-// P3: items whose two buckets were full in P1 (or stash entries re-placed
-// after a split), one 16-lane group per item.  Step 2 is tried again with a
-// fresh view of both buckets (two-choice), then the bounded cuckoo chain of
-// Algorithm 3: each round claims a free slot of the current bucket or
-// displaces a victim by CAS and carries the victim to its alternate bucket.
-// An item still in hand after max_evictions displacements goes to the stash,
-// or to the pending list when the stash is full.
+// P3 as a launch: every worklist item through evict_round (step 2 again,
+// then the bounded chain of Algorithm 3, then the stash or the pending list),
+// one item per group of the eviction shape, the grid striding over items.
 // The worklist is emptied afterwards by finish_kernel (it also counts the
 // items and folds unreserved stash placements into the stash count), so this
 // kernel takes no ticket.
