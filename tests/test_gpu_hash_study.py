@@ -57,3 +57,17 @@ def test_collisions_match_oracle(H, kind):
     # one bucket: every key but the first collides
     scratch1 = torch.empty(3, dtype=torch.uint32, device="cuda")
     assert H.hive_hash_collisions(kind, dev(uniform[:1000]), 1, scratch1) == 999
+
+
+def test_unaligned_and_ragged_arrays_take_the_scalar_path(H):
+    import torch
+    keys = wl.KeyStream(93).range(0, 10_007)
+    d = dev(keys)
+    for kind in KINDS:
+        out = torch.zeros(keys.size, dtype=torch.uint32, device="cuda")
+        print(f"[case] unaligned {kind}", flush=True)
+        H.hive_hash_buckets(kind, d[1:], 4415057, out[1:])  # 4-byte offsets: not 16-byte aligned
+        assert np.array_equal(out[1:].cpu().numpy(), oracle.hash_buckets(kind, keys[1:], 4415057))
+        assert int(out[0]) == 0
+        H.hive_hash_buckets(kind, d[:7], 512 * 512, out[:7])  # fewer than one 4-key group past 4
+        assert np.array_equal(out[:7].cpu().numpy(), oracle.hash_buckets(kind, keys[:7], 512 * 512))
