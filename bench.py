@@ -57,7 +57,7 @@ def parse():
                     help="bulk: first run one plain device copy of this many MiB (a known-size dispatch that "
                          "scales HBM byte counters read by a profiler)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-log2", type=int, default=22)
+    ap.add_argument("--cpu-sample-log2", type=int, default=23)
     return ap.parse_args()
 
 
