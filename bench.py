@@ -362,7 +362,8 @@ def run_hashes(args):
     over m = 512^2 buckets for n = 512 ... 2048^2 keys (E[Y] from the
     uniform-hashing theorem), for unique uniform keys and for the sequential
     keys 1..n (the paper does not say which keys it hashed); then each hash's
-    rate over 2^26 keys (key in, bucket out, timed with HIP events)."""
+    rate over 2^26 keys (key in, bucket out, timed with HIP events); then the
+    bulk insert rate of a 95%-load table under each hash pair."""
     import torch
     from paper_2510_15095_amd import hash_study as hs
     from paper_2510_15095_amd import hive as H
@@ -397,11 +398,42 @@ def run_hashes(args):
         ms = a.elapsed_time(b) / reps
         rates[kind] = {"ms": round(ms, 4), "mops": round(big.numel() / (ms * 1e-3) / 1e6, 1),
                        "gb_s": round(8 * big.numel() / (ms * 1e-3) / 1e9, 1)}
+    del big, out
+    # insert throughput of the table under each hash pair (the paper's
+    # figure of hash-pair insertion throughput, 2^20 .. 2^25 unique keys):
+    # a FIXED 16-slot table sized for 95% load, cleared and built per rep
+    pairs = {"bithash1+bithash2": H.HIVE_PAIR_BITHASH, "crc32+crc64": H.HIVE_PAIR_CRC,
+             "murmur3+city32": H.HIVE_PAIR_MURMUR}
+    host_keys = wl.KeyStream(9).range(0, 1 << 25)
+    ik = torch.from_numpy(host_keys).cuda()
+    iv = torch.from_numpy(wl.values_for(host_keys)).cuda()
+    insert = {name: {} for name in pairs}
+    for log2n in (20, 22, 24, 25):
+        n = 1 << log2n
+        nb = int(np.ceil(n / (LOAD * S)))
+        for name, pair in pairs.items():
+            t = H.Table(nb, hash_pair=pair, max_batch=n)
+            times = []
+            for rep in range(max(args.warmup, 1) + reps):
+                t.clear()
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                t.insert(ik[:n], iv[:n], flags=H.HIVE_UNIQUE)
+                b.record()
+                torch.cuda.synchronize()
+                if rep >= max(args.warmup, 1):
+                    times.append(a.elapsed_time(b))
+            st = t.stats()
+            assert st["live"] == n and st["status"] in (H.HIVE_OK, H.HIVE_WARN_PENDING), st
+            insert[name][str(log2n)] = round(n / (float(np.median(times)) * 1e-3) / 1e6, 1)
+            t.close()
     rec = base_record(args, rates["bithash1"]["mops"], rates["bithash1"]["ms"],
                       f"hash study: CSR of 6 hashes over 512^2 buckets for 512..2048^2 uniform and sequential keys; "
-                      f"hash rate over 2^{args.keys_log2} keys (value: BitHash1)", {"buckets": m, "n": ns})
+                      f"hash rate over 2^{args.keys_log2} keys (value: BitHash1); insert Mops/s of a 95% table per "
+                      f"hash pair at 2^20..2^25 keys", {"buckets": m, "n": ns})
     rec["csr"] = csr
     rec["rates"] = rates
+    rec["insert_mops_by_pair"] = insert
     rec["roofline"] = {"kernel": "hash_study bucket_kernel (BitHash1)", "bound": "hbm",
                        "achieved": rates["bithash1"]["gb_s"], "peak": 8000.0, "unit": "GB/s",
                        "frac": round(rates["bithash1"]["gb_s"] / 8000.0, 4), "traffic": None}

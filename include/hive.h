@@ -91,8 +91,18 @@ typedef struct {
                                  Plain launches only: the persistent
                                  executor always uses 0.  Results are the
                                  same either way */
-  uint32_t reserved_;
+  uint32_t hash_pair;         /* candidate-bucket hashes: HIVE_PAIR_BITHASH
+                                 (BitHash1/2, Section III-C; the default),
+                                 HIVE_PAIR_CRC (CRC-32, low half of CRC-64;
+                                 tables in constant memory) or
+                                 HIVE_PAIR_MURMUR (MurmurHash3, CityHash32),
+                                 the hashes of the study below.  The others
+                                 need S = 16, FIXED addressing, probe_both = 0,
+                                 plain launches (the executor and
+                                 hive_placement refuse such tables) */
 } hive_config;
+
+enum { HIVE_PAIR_BITHASH = 0, HIVE_PAIR_CRC = 1, HIVE_PAIR_MURMUR = 2 };
 
 typedef struct {
   uint64_t live;            /* number of keys stored */

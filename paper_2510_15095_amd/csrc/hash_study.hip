@@ -6,7 +6,8 @@
 // Every hash reads a key as its four little-endian bytes.  The CRCs are
 // table-driven, the form the paper evaluates as "lookup-based": each block
 // builds the two 256-entry tables in LDS, one entry per thread, and a key
-// then costs four table reads per CRC.  The others are pure ALU:
+// then costs four table reads per CRC.  The others are pure ALU (shared
+// with the table's hash pairs):
 //   CRC-32   reflected 0xEDB88320, all-ones initial value and final xor;
 //   CRC-64   reflected 0xC96C5795D7870F42 (ECMA-182, as in xz), all-ones
 //            initial value and final xor; the bucket reduces all 64 bits;
@@ -18,49 +19,16 @@
 
 #include <cstdint>
 
+#include "hash_fns.hpp"
 #include "hive.h"
 #include "hive_device.hpp"
 
 namespace hive_hs {
 
+using hive::city32_key;
+using hive::murmur3_key;
+
 constexpr int BLOCK = 256;
-
-__device__ __forceinline__ uint32_t rotl32(uint32_t x, int r) { return (x << r) | (x >> (32 - r)); }
-__device__ __forceinline__ uint32_t rotr32(uint32_t x, int r) { return (x >> r) | (x << (32 - r)); }
-
-__device__ __forceinline__ uint32_t fmix32(uint32_t h) {
-  h ^= h >> 16;
-  h *= 0x85EBCA6Bu;
-  h ^= h >> 13;
-  h *= 0xC2B2AE35u;
-  return h ^ (h >> 16);
-}
-
-__device__ __forceinline__ uint32_t murmur3_key(uint32_t k) {
-  // one whole 4-byte block, no tail, length 4
-  k *= 0xCC9E2D51u;
-  k = rotl32(k, 15) * 0x1B873593u;
-  const uint32_t h = rotl32(k, 13) * 5u + 0xE6546B64u;  // seed 0
-  return fmix32(h ^ 4u);
-}
-
-__device__ __forceinline__ uint32_t city_mur(uint32_t a, uint32_t h) {
-  a *= 0xCC9E2D51u;
-  a = rotr32(a, 17) * 0x1B873593u;
-  h = rotr32(h ^ a, 19);
-  return h * 5u + 0xE6546B64u;
-}
-
-__device__ __forceinline__ uint32_t city32_key(uint32_t k) {
-  uint32_t b = 0, c = 9;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int32_t v = (int8_t)(k >> (8 * i));
-    b = b * 0xCC9E2D51u + (uint32_t)v;
-    c ^= b;
-  }
-  return fmix32(city_mur(b, city_mur(4u, c)));
-}
 
 struct Tables {
   uint32_t crc32[256];

@@ -39,8 +39,13 @@
 #include <type_traits>
 #include <vector>
 
+#include "hash_fns.hpp"
 #include "hive.h"
 #include "hive_device.hpp"
+
+static_assert(hive::PAIR_BITHASH == HIVE_PAIR_BITHASH && hive::PAIR_CRC == HIVE_PAIR_CRC &&
+                  hive::PAIR_MURMUR == HIVE_PAIR_MURMUR,
+              "hash pair numbering");
 
 namespace hive {
 
@@ -438,7 +443,8 @@ __device__ __forceinline__ OpsView read_view(const Ctl *c, uint64_t stash_cap, u
 // BOTH: probe both candidates in one round for every operation (inserts of
 // new keys always need both; for lookups and deletes it trades bytes for one
 // memory round trip fewer).
-template <int S, uint32_t MODE, bool BOTH>
+// PAIR: the table's candidate hashes (HashPair); BitHash1/2 by default.
+template <int S, uint32_t MODE, bool BOTH, int PAIR = PAIR_BITHASH>
 __device__ __forceinline__ void ops_tile(const OpsArgs &a, const OpsView &view, uint64_t tile, OpsShared<S> &sh) {
   using T = Traits<S>;
   using Mask = typename T::Mask;
@@ -470,8 +476,8 @@ __device__ __forceinline__ void ops_tile(const OpsArgs &a, const OpsView &view, 
   if (work && a.dd && op != OP_LOOKUP) work = dedupe_winner(a.dd, a.dd_mask, k, (uint32_t)i);
   uint32_t c1 = 0, c2 = 0;
   if (work) {
-    c1 = address(geo, bithash1(k));
-    c2 = address(geo, bithash2(k));
+    c1 = address(geo, HashPair<PAIR>::h1(k));
+    c2 = address(geo, HashPair<PAIR>::h2(k));
   }
   s_key[wv][lane] = work ? k : 0u;
   s_b1[wv][lane] = c1;
@@ -624,12 +630,12 @@ __device__ __forceinline__ void ops_tile(const OpsArgs &a, const OpsView &view, 
   }
 }
 
-template <int S, uint32_t MODE, bool BOTH>
+template <int S, uint32_t MODE, bool BOTH, int PAIR = PAIR_BITHASH>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(OPS_WAVES_PER_EU))) void ops_kernel(
     OpsArgs a) {
   __shared__ OpsShared<S> sh;
   const OpsView view = read_view(a.ctl, a.stash_cap, a.pending_cap);
-  ops_tile<S, MODE, BOTH>(a, view, blockIdx.x, sh);
+  ops_tile<S, MODE, BOTH, PAIR>(a, view, blockIdx.x, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -657,6 +663,7 @@ __device__ __forceinline__ void set_hint(uint32_t *hint, uint32_t b) { or32(&hin
 // entry claims the first EMPTY word of its probe run by CAS (one exists: the
 // table has at least twice the capacity).  Returns where it went: 0 stash,
 // 1 pending, 2 lost (the pending list was full too; latched as an error).
+template <int PAIR = PAIR_BITHASH>
 __device__ __forceinline__ int overflow_place(const EvictArgs &a, const Geo &geo, uint64_t kv, uint64_t c) {
   bool stashed = false;
   if (c < a.stash_cap) {
@@ -680,8 +687,8 @@ __device__ __forceinline__ int overflow_place(const EvictArgs &a, const Geo &geo
     }
   }
   const uint32_t k = key_of(kv);
-  set_hint(a.hint, address(geo, bithash1(k)));
-  set_hint(a.hint, address(geo, bithash2(k)));
+  set_hint(a.hint, address(geo, HashPair<PAIR>::h1(k)));
+  set_hint(a.hint, address(geo, HashPair<PAIR>::h2(k)));
   return where;
 }
 
@@ -826,13 +833,13 @@ __device__ __forceinline__ bool group_claim(uint64_t *bkt, typename Traits<S>::M
 // by CAS and carries the victim to its alternate bucket.  Returns whether
 // the item was placed; if not, the caller sends the entry in hand to the
 // stash (or the pending list when the stash is full).
-template <int S>
+template <int S, int PAIR = PAIR_BITHASH>
 __device__ __forceinline__ bool evict_chain(const EvictArgs &a, const Geo &geo, uint64_t &kv, uint32_t max_kicks,
                                             int g, int sl, uint64_t &n_evict) {
   using T = Traits<S>;
   using Mask = typename T::Mask;
   using E = EvictShape<S>;
-  const uint32_t c1 = address(geo, bithash1(key_of(kv))), c2 = address(geo, bithash2(key_of(kv)));
+  const uint32_t c1 = address(geo, HashPair<PAIR>::h1(key_of(kv))), c2 = address(geo, HashPair<PAIR>::h2(key_of(kv)));
   // step 2 with fresh loads (fresh: other items of this phase change buckets)
   uint64_t w[E::P], w2v[E::P];
   const Mask f1 = load_view<S>(a.buckets + (uint64_t)c1 * S, g, sl, w);
@@ -868,8 +875,8 @@ __device__ __forceinline__ bool evict_chain(const EvictArgs &a, const Geo &geo, 
     }
     ++n_evict;
     kv = victim;
-    const uint32_t v1 = address(geo, bithash1(key_of(kv)));
-    const uint32_t v2 = address(geo, bithash2(key_of(kv)));
+    const uint32_t v1 = address(geo, HashPair<PAIR>::h1(key_of(kv)));
+    const uint32_t v2 = address(geo, HashPair<PAIR>::h2(key_of(kv)));
     b = (b == v1) ? v2 : v1;  // AltBucket: the victim's other candidate
   }
   return placed;  // if not, kv is the entry in hand
@@ -885,7 +892,7 @@ __device__ __forceinline__ bool evict_chain(const EvictArgs &a, const Geo &geo, 
 // each on a single address (thousands of waves queue there in a stash drain);
 // their number is added per wave to the shards and folded into the count
 // after the launch.  Otherwise one count reservation per wave.
-template <int S>
+template <int S, int PAIR = PAIR_BITHASH>
 __device__ __forceinline__ void evict_round(const EvictArgs &a, const Geo &geo, bool unreserved, bool have,
                                             uint64_t pos, int g, int sl, uint64_t &n_evict, uint64_t &n_full,
                                             uint64_t &n_side) {
@@ -893,7 +900,7 @@ __device__ __forceinline__ void evict_round(const EvictArgs &a, const Geo &geo, 
   bool placed = true;
   if (have) {
     kv = a.wl[pos];
-    placed = evict_chain<S>(a, geo, kv, a.max_evictions, g, sl, n_evict);
+    placed = evict_chain<S, PAIR>(a, geo, kv, a.max_evictions, g, sl, n_evict);
   }
   const bool push = !placed && sl == 0;
   const uint64_t pm = ballot(push);
@@ -910,7 +917,7 @@ __device__ __forceinline__ void evict_round(const EvictArgs &a, const Geo &geo, 
     }
     if (push) {
       ++n_full;
-      const int where = overflow_place(a, geo, kv, base + rank_below(pm));
+      const int where = overflow_place<PAIR>(a, geo, kv, base + rank_below(pm));
       n_side += where == 0 ? 1 : where == 1 ? (1ull << 32) : 0;
     }
   }
@@ -939,7 +946,7 @@ __device__ __forceinline__ void evict_counters(const EvictArgs &a, bool unreserv
 // The worklist is emptied afterwards by finish_kernel (it also counts the
 // items and folds unreserved stash placements into the stash count), so this
 // kernel takes no ticket.
-template <int S>
+template <int S, int PAIR = PAIR_BITHASH>
 __global__ __launch_bounds__(BLOCK) void evict_kernel(EvictArgs a) {
   using E = EvictShape<S>;
   __shared__ uint64_t pre[NSHARD + 1];
@@ -958,8 +965,8 @@ __global__ __launch_bounds__(BLOCK) void evict_kernel(EvictArgs a) {
   const uint64_t wave_first = ((uint64_t)blockIdx.x * WAVES + wv) * E::G;
   for (uint64_t base = wave_first; base < cnt; base += groups) {
     const uint64_t t = base - wave_first + first;
-    evict_round<S>(a, geo, unreserved, t < cnt, t < cnt ? wl_slot(pre, t, a.wl_seg_cap) : 0, g, sl, n_evict, n_full,
-                   n_side);
+    evict_round<S, PAIR>(a, geo, unreserved, t < cnt, t < cnt ? wl_slot(pre, t, a.wl_seg_cap) : 0, g, sl, n_evict,
+                         n_full, n_side);
   }
   evict_counters(a, unreserved, (uint64_t)blockIdx.x * WAVES + wv, n_evict, n_full, n_side, sl);
 }
@@ -2229,19 +2236,19 @@ static hive_status ensure_scratch(hive_table *h, uint64_t n, bool need_dd, hipSt
   return HIVE_OK;
 }
 
-template <int S, uint32_t MODE, bool BOTH>
+template <int S, uint32_t MODE, bool BOTH, int PAIR = PAIR_BITHASH>
 static void launch_ops(const OpsArgs &a, hipStream_t st) {
   const uint64_t blocks = (a.n + BLOCK - 1) / BLOCK;
-  hipLaunchKernelGGL((ops_kernel<S, MODE, BOTH>), dim3((unsigned)blocks), dim3(BLOCK), 0, st, a);
+  hipLaunchKernelGGL((ops_kernel<S, MODE, BOTH, PAIR>), dim3((unsigned)blocks), dim3(BLOCK), 0, st, a);
 }
 
-template <int S, bool BOTH>
+template <int S, bool BOTH, int PAIR = PAIR_BITHASH>
 static void launch_ops_mode(uint32_t mode, const OpsArgs &a, hipStream_t st) {
   switch (mode) {
-    case OP_INSERT: launch_ops<S, OP_INSERT, BOTH>(a, st); break;
-    case OP_DELETE: launch_ops<S, OP_DELETE, BOTH>(a, st); break;
-    case OP_LOOKUP: launch_ops<S, OP_LOOKUP, BOTH>(a, st); break;
-    default: launch_ops<S, OP_MIXED, BOTH>(a, st); break;
+    case OP_INSERT: launch_ops<S, OP_INSERT, BOTH, PAIR>(a, st); break;
+    case OP_DELETE: launch_ops<S, OP_DELETE, BOTH, PAIR>(a, st); break;
+    case OP_LOOKUP: launch_ops<S, OP_LOOKUP, BOTH, PAIR>(a, st); break;
+    default: launch_ops<S, OP_MIXED, BOTH, PAIR>(a, st); break;
   }
 }
 
@@ -2254,7 +2261,14 @@ static void launch_evict(hive_table *h, uint64_t max_items, hipStream_t st) {
               h->d_wl,      h->wl_seg_cap,   h->stash_cap, h->pending_cap, h->cfg.max_evictions};
   const dim3 grid(grid_for(max_items, (uint64_t)WAVES * evict_groups_per_wave(h->S), EVICT_GRID));
   switch (h->S) {
-    case 16: hipLaunchKernelGGL(evict_kernel<16>, grid, dim3(BLOCK), 0, st, e); break;
+    case 16:
+      if (h->cfg.hash_pair == PAIR_CRC)
+        hipLaunchKernelGGL((evict_kernel<16, PAIR_CRC>), grid, dim3(BLOCK), 0, st, e);
+      else if (h->cfg.hash_pair == PAIR_MURMUR)
+        hipLaunchKernelGGL((evict_kernel<16, PAIR_MURMUR>), grid, dim3(BLOCK), 0, st, e);
+      else
+        hipLaunchKernelGGL(evict_kernel<16>, grid, dim3(BLOCK), 0, st, e);
+      break;
     case 32: hipLaunchKernelGGL(evict_kernel<32>, grid, dim3(BLOCK), 0, st, e); break;
     default: hipLaunchKernelGGL(evict_kernel<64>, grid, dim3(BLOCK), 0, st, e); break;
   }
@@ -2455,7 +2469,11 @@ static hive_status run_batch(hive_t h, uint32_t mode, const uint8_t *d_ops, cons
   phase_mark(h, HIVE_PHASE_PROBE, st);
   switch (h->S) {
     case 16:
-      if (h->cfg.probe_both)
+      if (h->cfg.hash_pair == PAIR_CRC)
+        launch_ops_mode<16, false, PAIR_CRC>(mode, a, st);
+      else if (h->cfg.hash_pair == PAIR_MURMUR)
+        launch_ops_mode<16, false, PAIR_MURMUR>(mode, a, st);
+      else if (h->cfg.probe_both)
         launch_ops_mode<16, true>(mode, a, st);
       else
         launch_ops_mode<16, false>(mode, a, st);
@@ -2501,6 +2519,10 @@ hive_status hive_create(const hive_config *cfg_in, uint64_t initial_buckets, voi
   const uint32_t S = cfg.slots_per_bucket;
   if (S != 16 && S != 32 && S != 64) return HIVE_ERR_ARG;
   if (cfg.addressing != HIVE_FIXED && cfg.addressing != HIVE_LINEAR) return HIVE_ERR_ARG;
+  if (cfg.hash_pair > HIVE_PAIR_MURMUR) return HIVE_ERR_ARG;
+  // only 16-slot FIXED tables on plain launches have the other hash pairs
+  if (cfg.hash_pair != HIVE_PAIR_BITHASH && (S != 16 || cfg.addressing != HIVE_FIXED || cfg.probe_both))
+    return HIVE_ERR_ARG;
   if (initial_buckets < 1) return HIVE_ERR_ARG;
   if (cfg.max_evictions > 1024) return HIVE_ERR_ARG;
   if (cfg.lf_expand_pct == 0 || cfg.lf_expand_pct > 100 || cfg.lf_contract_pct >= cfg.lf_expand_pct)
@@ -2670,6 +2692,7 @@ hive_status hive_dump(hive_t h, uint64_t *d_words, int64_t *d_where, uint64_t ca
 
 hive_status hive_placement(hive_t h, uint64_t *out, void *stream) {
   if (!h || !out) return HIVE_ERR_ARG;
+  if (h->cfg.hash_pair != HIVE_PAIR_BITHASH) return HIVE_ERR_ARG;  // the census computes BitHash1 candidates
   hipStream_t st = (hipStream_t)stream;
   h->last = st;
   hipLaunchKernelGGL(ctl_zero_placement_kernel, dim3(1), dim3(1), 0, st, h->d_ctl);
@@ -2817,6 +2840,7 @@ fail:
 hive_status hive_drain_submit(hive_drain_t d, hive_t h, const hive_batch_desc *b, uint64_t *ticket) {
   if (!d || !h || !b || !ticket) return HIVE_ERR_ARG;
   if (h->S != d->S) return HIVE_ERR_ARG;
+  if (h->cfg.hash_pair != HIVE_PAIR_BITHASH) return HIVE_ERR_ARG;  // the executor runs BitHash1/2 tables only
   if (b->op_mode > HIVE_OP_MIXED) return HIVE_ERR_ARG;
   if (b->n > 0 && !b->d_keys) return HIVE_ERR_ARG;
   if ((b->op_mode == HIVE_OP_INSERT || b->op_mode == HIVE_OP_MIXED) && b->n > 0 && !b->d_vals) return HIVE_ERR_ARG;

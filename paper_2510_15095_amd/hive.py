@@ -46,7 +46,7 @@ class hive_config(ctypes.Structure):
         ("max_buckets", ctypes.c_uint64),
         ("max_batch", ctypes.c_uint64),
         ("probe_both", ctypes.c_uint32),
-        ("reserved_", ctypes.c_uint32),
+        ("hash_pair", ctypes.c_uint32),
     ]
 
 
@@ -338,6 +338,7 @@ def hive_drain_results(d, tickets):
     return done.astype(bool), live
 
 
+HIVE_PAIR_BITHASH, HIVE_PAIR_CRC, HIVE_PAIR_MURMUR = 0, 1, 2
 HASH_KINDS = ("bithash1", "bithash2", "crc32", "crc64", "murmur3", "city32")
 HIVE_HASH_KINDS = len(HASH_KINDS)
 

@@ -71,3 +71,67 @@ def test_unaligned_and_ragged_arrays_take_the_scalar_path(H):
         assert int(out[0]) == 0
         H.hive_hash_buckets(kind, d[:7], 512 * 512, out[:7])  # fewer than one 4-key group past 4
         assert np.array_equal(out[:7].cpu().numpy(), oracle.hash_buckets(kind, keys[:7], 512 * 512))
+
+
+def pair_candidates(pair, keys, nb):
+    """Both candidate buckets of every key under a table's hash pair, from
+    the oracle's transcriptions (CRC-64 contributes its low 32 bits)."""
+    le = [int(k).to_bytes(4, "little") for k in keys]
+    if pair == 1:
+        h1 = [oracle.crc32_bytes(b) for b in le]
+        h2 = [oracle.crc64_bytes(b) & 0xFFFFFFFF for b in le]
+    else:
+        h1 = [oracle.murmur3_bytes(b, 0) for b in le]
+        h2 = [oracle.city32_bytes(b) for b in le]
+    return np.array(h1, np.int64) % nb, np.array(h2, np.int64) % nb
+
+
+@pytest.mark.parametrize("pair", [1, 2])
+@pytest.mark.parametrize("lf,E,stash", [(0.5, 8, 1024), (0.97, 8, 1024), (0.99, 2, 64)])
+def test_table_with_other_hash_pair_matches_oracle(H, pair, lf, E, stash):
+    """A FIXED table addressed by CRC-32/CRC-64 or MurmurHash3/CityHash32:
+    every lookup, delete and the final contents equal the dictionary's, and
+    every bucket entry sits in one of its two candidates under that pair."""
+    S, nb = 16, 97
+    n = int(S * nb * lf)
+    ks = wl.KeyStream(95 + pair)
+    keys = ks.range(0, n)
+    vals = wl.values_for(keys)
+    print(f"[case] pair {pair} lf {lf} E {E} stash {stash}", flush=True)
+    t = H.Table(nb, hash_pair=pair, max_evictions=E, stash_capacity=stash, pending_capacity=4096)
+    o = oracle.O1()
+    t.insert(dev(keys), dev(vals))
+    o.insert(keys, vals)
+    st = t.stats()
+    assert st["status"] in (H.HIVE_OK, H.HIVE_WARN_PENDING) and st["live"] == n, st
+    q = ks.range(0, n + 300)
+    v, f = t.lookup(dev(q))
+    ov, of = o.lookup(q)
+    assert np.array_equal(f.cpu().numpy(), of) and np.array_equal(v.cpu().numpy(), ov)
+    words, where = t.dump(with_where=True)
+    assert np.array_equal(words, o.dump())
+    k = (words & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+    c1, c2 = pair_candidates(pair, k, nb)
+    inb = where >= 0
+    assert np.all((where[inb] == c1[inb]) | (where[inb] == c2[inb]))
+    dk = keys[::3]
+    assert np.array_equal(t.delete(dev(dk), flags=H.HIVE_UNIQUE).cpu().numpy(), o.delete(dk))
+    v, f = t.lookup(dev(q))
+    ov, of = o.lookup(q)
+    assert np.array_equal(f.cpu().numpy(), of) and np.array_equal(v.cpu().numpy(), ov)
+    assert np.array_equal(t.dump(), o.dump())
+    with pytest.raises(H.HiveError):
+        t.placement()
+    t.close()
+
+
+def test_executor_refuses_other_hash_pairs(H):
+    import torch
+    t = H.Table(64, hash_pair=1)
+    d = H.hive_drain_create(16, 0, 8, 2, 0)
+    k = dev(np.arange(1, 65, dtype=np.uint32))
+    with pytest.raises(H.HiveError):
+        H.hive_drain_submit(d, t.h, H.HIVE_OP_LOOKUP, k, None, None, torch.empty(64, dtype=torch.uint32,
+                                                                                 device="cuda"))
+    H.hive_drain_destroy(d)
+    t.close()
