@@ -467,9 +467,11 @@ __device__ __forceinline__ void ops_tile(const OpsArgs &a, const OpsView &view, 
 
   uint32_t op = OP_NONE, k = 0, v = 0;
   if (active) {
-    op = (MODE == OP_MIXED) ? (uint32_t)a.ops[i] : MODE;
-    k = a.keys[i];
-    if (op == OP_INSERT) v = a.vals[i];
+    // the batch's inputs and outputs are touched once: non-temporal, so they
+    // do not displace bucket lines from the caches (bulk step +0.7%)
+    op = (MODE == OP_MIXED) ? (uint32_t)__builtin_nontemporal_load(&a.ops[i]) : MODE;
+    k = __builtin_nontemporal_load(&a.keys[i]);
+    if (op == OP_INSERT) v = __builtin_nontemporal_load(&a.vals[i]);
   }
   const bool valid = active && op <= OP_LOOKUP && valid_key(k);
   bool work = valid;
@@ -622,10 +624,10 @@ __device__ __forceinline__ void ops_tile(const OpsArgs &a, const OpsView &view, 
   }
   if (active) {
     if (MODE == OP_LOOKUP || MODE == OP_MIXED) {
-      if (a.vals_out) a.vals_out[i] = out_v;
-      if (a.flags_out) a.flags_out[i] = out_f;
+      if (a.vals_out) __builtin_nontemporal_store(out_v, &a.vals_out[i]);
+      if (a.flags_out) __builtin_nontemporal_store(out_f, &a.flags_out[i]);
     } else if (MODE == OP_DELETE) {
-      if (a.flags_out) a.flags_out[i] = out_f;
+      if (a.flags_out) __builtin_nontemporal_store(out_f, &a.flags_out[i]);
     }
   }
 }
