@@ -382,6 +382,14 @@ def test_bulk_95pct_full_size(H):
     print("bulk 2^26 stats:", st)
 
 
+def test_bulk_launches_striding_over_tiles_with_ragged_tails(H):
+    """Batches beyond the probe launch's block cap: each block strides over
+    two or more tiles of 256 operations and the last tile is partial (insert
+    and lookup 2 x 32,768 x 256 + 1,000 operations, delete half of that)."""
+    st = run_bulk(H, 2 * 32768 * 256 + 1000, seed=4)
+    print("bulk ragged stats:", st)
+
+
 def linear_table(H, nb, max_buckets, K, pre=1, post=1, lf_e=90, lf_c=25, stash=256):
     return H.Table(nb, addressing=H.HIVE_LINEAR, max_buckets=max_buckets, resize_k=K, pre_expand=pre,
                    post_policy=post, lf_expand_pct=lf_e, lf_contract_pct=lf_c, stash_capacity=stash,
