@@ -39,7 +39,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=("bulk", "mixed", "resize", "served", "breakdown", "hashes"),
+    ap.add_argument("--workload", choices=("bulk", "mixed", "resize", "served", "breakdown", "hashes", "gather"),
                     default="bulk")
     ap.add_argument("--executor", choices=("plain", "persistent"), default="plain",
                     help="mixed: one launch sequence per batch, or the persistent executor")
@@ -108,7 +108,7 @@ def main():
         args.resize_k = (tuned.get("resize") or {}).get("resize_k", 1024)
     args.blocks_per_cu = (tuned.get("executor") or {}).get("blocks_per_cu", 0)
     run = {"bulk": run_bulk, "mixed": run_mixed, "resize": run_resize, "served": run_served,
-           "breakdown": run_breakdown, "hashes": run_hashes}[args.workload]
+           "breakdown": run_breakdown, "hashes": run_hashes, "gather": run_gather}[args.workload]
     out = run(args) if pre is None else run(args, pre)
     if tuned:
         out["autotuned"] = {k: v for k, v in tuned.items() if v}
@@ -437,6 +437,42 @@ def run_hashes(args):
     rec["roofline"] = {"kernel": "hash_study bucket_kernel (BitHash1)", "bound": "hbm",
                        "achieved": rates["bithash1"]["gb_s"], "peak": 8000.0, "unit": "GB/s",
                        "frac": round(rates["bithash1"]["gb_s"] / 8000.0, 4), "traffic": None}
+    return rec
+
+
+def run_gather(args):
+    """Gather ceiling: random 128-byte line reads (the access pattern of
+    bucket probing, with the probe kernel's shape) over a table of the bulk
+    geometry (4,415,057 lines, 565 MB, larger than the 256 MB last-level
+    cache) and of the mixed geometry (1,103,765 lines, 141 MB, which fits
+    it); 2^26 uniform random line indices, HIP-event timing."""
+    import torch
+    from paper_2510_15095_amd import hive as H
+    n = 1 << args.keys_log2
+    res = {}
+    for name, lines in (("bulk_565MB", 4415057), ("mixed_141MB", 1103765)):
+        table = torch.randint(0, 2 ** 62, (lines * 16,), dtype=torch.int64, device="cuda").view(torch.uint64)
+        idx = torch.randint(0, lines, (n,), dtype=torch.int64, device="cuda").to(torch.uint32)
+        out = torch.empty(n, dtype=torch.uint64, device="cuda")
+        for _ in range(max(args.warmup, 1)):
+            H.hive_gather_lines(table, idx, out)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(max(args.steps, 1)):
+            H.hive_gather_lines(table, idx, out)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / max(args.steps, 1)
+        res[name] = {"ms": round(ms, 4), "line_gb_s": round(128 * n / (ms * 1e-3) / 1e9, 1),
+                     "all_gb_s": round(140 * n / (ms * 1e-3) / 1e9, 1)}
+        del table, idx, out
+    bulk = res["bulk_565MB"]
+    rec = base_record(args, n / (bulk["ms"] * 1e-3) / 1e6, bulk["ms"],
+                      f"gather ceiling: 2^{args.keys_log2} random 128-byte line reads over 565 MB and 141 MB "
+                      f"tables (value: lines per second over 565 MB, in millions)", {"lines_read": n})
+    rec["gather"] = res
+    rec["roofline"] = {"kernel": "gather_kernel (565 MB)", "bound": "hbm", "achieved": bulk["all_gb_s"],
+                       "peak": 8000.0, "unit": "GB/s", "frac": round(bulk["all_gb_s"] / 8000.0, 4), "traffic": None}
     return rec
 
 

@@ -257,6 +257,16 @@ hive_status hive_hash_buckets(uint32_t kind, const uint32_t *d_keys, uint64_t n,
 hive_status hive_hash_collisions(uint32_t kind, const uint32_t *d_keys, uint64_t n, uint64_t m, uint32_t *d_scratch,
                                  uint64_t *y_out, void *stream);
 
+/* ---- Gather ceiling (a measurement aid) ------------------------------------
+ * Random 128-byte line reads, the access pattern of bucket probing, with the
+ * probe kernel's shape and nothing else: d_out[i] = XOR of the 16 words of
+ * line d_idx[i] of d_table (n_lines lines of 16 words; an index >= n_lines
+ * reads nothing and gives 0).  All arrays are caller-owned device memory;
+ * stream-ordered, no synchronization.  HIVE_ERR_ARG for null arrays with
+ * n > 0, n_lines = 0 with n > 0, or n_lines > 2^32. */
+hive_status hive_gather_lines(const uint64_t *d_table, uint64_t n_lines, const uint32_t *d_idx, uint64_t n,
+                              uint64_t *d_out, void *stream);
+
 /* ---- Persistent executor ------------------------------------------------
  * One resident grid drains a queue of batches in one launch (a hipGraph
  * captured once and replayed).  Each batch runs the same phases and gives

@@ -18,7 +18,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 ARCH = "gfx950"
 
-HIP_SOURCES = ["hive.hip", "hash_study.hip"]
+HIP_SOURCES = ["hive.hip", "hash_study.hip", "gather.hip"]
 HIP_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-Wall", "-Wno-unused-function",

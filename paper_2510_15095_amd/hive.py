@@ -118,6 +118,7 @@ def _load():
         "hive_drain_results": ([p, p, u64, p, p], st),
         "hive_phase_timing": ([p, st], st),
         "hive_hash_buckets": ([u32, p, u64, u64, p, p], st),
+        "hive_gather_lines": ([p, u64, p, u64, p, p], st),
         "hive_hash_collisions": ([u32, p, u64, u64, p, p, p], st),
         "hive_phase_times": ([p, p], st),
         "hive_drain_stop": ([p, p], st),
@@ -360,6 +361,16 @@ def hive_hash_collisions(kind: str, keys, m: int, scratch, stream=None) -> int:
                                      _dev(scratch, torch.uint32, "scratch", 2 + (m + 31) // 32),
                                      ctypes.byref(y), _stream_ptr(stream)), "hive_hash_collisions")
     return int(y.value)
+
+
+def hive_gather_lines(table, idx, out, stream=None) -> None:
+    """out[i] = XOR of the 16 words of line idx[i] of table (uint64 GPU tensor
+    of n_lines x 16 words; idx uint32, out uint64 GPU tensors)."""
+    import torch
+    n = idx.numel()
+    _check(_lib.hive_gather_lines(_dev(table, torch.uint64, "table"), table.numel() // 16,
+                                  _dev(idx, torch.uint32, "idx"), n, _dev(out, torch.uint64, "out", n),
+                                  _stream_ptr(stream)), "hive_gather_lines")
 
 
 PHASE_KINDS = ("dedupe", "probe", "evict", "resize", "drain", "finish")

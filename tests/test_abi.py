@@ -116,6 +116,8 @@ def test_null_handle_and_arguments_rejected(H):
     assert lib.hive_hash_buckets(0, None, 0, (1 << 32) + 1, None, None) == H.HIVE_ERR_ARG
     assert lib.hive_hash_buckets(0, None, 0, 8, None, None) == H.HIVE_OK  # empty: nothing to launch
     assert lib.hive_hash_collisions(0, None, 0, 8, None, None, None) == H.HIVE_ERR_ARG
+    assert lib.hive_gather_lines(None, 16, None, 5, None, None) == H.HIVE_ERR_ARG
+    assert lib.hive_gather_lines(None, 0, None, 0, None, None) == H.HIVE_OK  # empty: nothing to launch
     assert lib.hive_status_string(H.HIVE_ERR_LOST).decode().startswith("pending")
 
 

@@ -135,3 +135,20 @@ def test_executor_refuses_other_hash_pairs(H):
                                                                                  device="cuda"))
     H.hive_drain_destroy(d)
     t.close()
+
+
+def test_gather_lines_xor_of_each_line(H):
+    """The gather-ceiling kernel: out[i] is the XOR of the 16 words of line
+    idx[i]; an index past the table gives 0; ragged lengths are covered."""
+    import torch
+    rng = np.random.default_rng(11)
+    n_lines = 5003
+    table = rng.integers(0, 2 ** 63, size=(n_lines, 16), dtype=np.int64).view(np.uint64)
+    idx = rng.integers(0, n_lines, size=100_003).astype(np.uint32)
+    idx[::997] = n_lines + 7  # past the table
+    out = torch.empty(idx.size, dtype=torch.uint64, device="cuda")
+    H.hive_gather_lines(dev(table.reshape(-1)), dev(idx), out)
+    safe = np.minimum(idx, n_lines - 1)
+    want = np.bitwise_xor.reduce(table[safe], axis=1)
+    want[idx >= n_lines] = 0
+    assert np.array_equal(out.cpu().numpy(), want)
