@@ -102,7 +102,8 @@ def test_uniform_random_buckets_agree_with_expectation():
     assert 0.95 < csr < 1.05
 
 
-@pytest.mark.parametrize("n,m", [(0, 7), (1, 7), (5, 1), (512, 512 * 512), (2048 * 2048, 512 * 512), (10 ** 6, 4415057)])
+@pytest.mark.parametrize("n,m", [(0, 7), (1, 7), (5, 1), (512, 512 * 512), (2048 * 2048, 512 * 512),
+                                 (10 ** 6, 4415057)])
 def test_package_expectation_equals_oracle(n, m):
     from paper_2510_15095_amd import hash_study as hs
     assert hs.expected_collisions(n, m) == pytest.approx(oracle.expected_collisions(n, m), rel=1e-12, abs=1e-9)
