@@ -250,7 +250,9 @@ def run_served(args, pre):
     from paper_2510_15095_amd import serve as sv
     specs, reqs = pre
     budget = sv.footprint_bytes(specs)
-    srv = sv.Server(specs, budget, max_request=1 << int(np.ceil(args.request_log2)), ring=1024, streams=8)
+    # the executor's blocks per CU: the autotuned value when cached, else one
+    srv = sv.Server(specs, budget, max_request=1 << int(np.ceil(args.request_log2)), ring=1024, streams=8,
+                    blocks_per_cu=args.blocks_per_cu or 1)
     res = {}
     for mode in ("plain", "persistent"):
         srv.load()
