@@ -106,7 +106,7 @@ def main():
         tuned = {"resize": autotune.load("resize"), "executor": autotune.load("executor")}
     if not args.resize_k:
         args.resize_k = (tuned.get("resize") or {}).get("resize_k", 1024)
-    args.blocks_per_cu = (tuned.get("executor") or {}).get("blocks_per_cu", 0)
+    args.blocks_per_cu = (tuned.get("executor") or {}).get("blocks_per_cu", 1)
     run = {"bulk": run_bulk, "mixed": run_mixed, "resize": run_resize, "served": run_served,
            "breakdown": run_breakdown, "hashes": run_hashes, "gather": run_gather}[args.workload]
     out = run(args) if pre is None else run(args, pre)

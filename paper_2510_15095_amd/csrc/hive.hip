@@ -1737,7 +1737,9 @@ __device__ uint32_t find_work(DrainQueue *q, uint64_t *req, uint32_t *phase, uin
   // retire the completed batches at the head of the ring
   {
     const uint64_t t = head + lane;
-    const bool done = t < ing && (__hip_atomic_load(&q->req[t % q->cap].state, __ATOMIC_ACQUIRE,
+    // relaxed: a retired entry is only skipped; an acquire load here would
+    // invalidate the XCD's L2 on every poll of every idle block
+    const bool done = t < ing && (__hip_atomic_load(&q->req[t % q->cap].state, __ATOMIC_RELAXED,
                                                     __HIP_MEMORY_SCOPE_AGENT) >> 56) == PH_DONE;
     const uint64_t dm = ballot(done);
     const int lead = (dm == ~0ull) ? 64 : __builtin_ctzll(~dm);
@@ -1751,7 +1753,7 @@ __device__ uint32_t find_work(DrainQueue *q, uint64_t *req, uint32_t *phase, uin
     }
   }
   if (head == ing) {
-    if (__hip_atomic_load(&q->final_seen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != 0 &&
+    if (__hip_atomic_load(&q->final_seen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 &&
         ld_ctl(&q->ingested) == ing)
       return 2;
     return 1;
@@ -1761,8 +1763,14 @@ __device__ uint32_t find_work(DrainQueue *q, uint64_t *req, uint32_t *phase, uin
   uint64_t st = 0;
   bool runnable = false;
   if (t < ing) {
-    st = __hip_atomic_load(&r->state, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    st = __hip_atomic_load(&r->state, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     runnable = (uint32_t)(st >> 56) != PH_DONE && (st & M28) < ((st >> 28) & M28);
+  }
+  // the descriptor read below must see what was written before the state
+  // was released; the acquire fence (an L2 invalidate) is paid only by a
+  // scan that found unclaimed chunks, never by an idle poll
+  if (ballot(runnable)) {
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     if (runnable) {
       const uint64_t slot = ld_ctl(&r->d.table_slot), seq = ld_ctl(&r->d.seq);
       runnable = ld_ctl(&q->table_next[slot]) == seq;
