@@ -613,7 +613,8 @@ def _mixed_batches(seed, n_batches, n_ops, universe, ks):
     return [wl.mixed_batch(seed, b, n_ops, universe, stream=ks, value_salt=b + 1) for b in range(n_batches)]
 
 
-def test_drain_matches_plain_and_oracle_mixed(H):
+@pytest.mark.parametrize("bpc", [0, 1])  # full occupancy, one resident block per CU
+def test_drain_matches_plain_and_oracle_mixed(H, bpc):
     """The persistent executor gives the same per-batch outputs and final
     contents as one plain launch sequence per batch, and as the dictionary."""
     import torch
@@ -627,7 +628,7 @@ def test_drain_matches_plain_and_oracle_mixed(H):
     for t in (plain, drained):
         t.insert(dev(pre), dev(wl.values_for(pre)), flags=H.HIVE_UNIQUE)
     o.insert(pre, wl.values_for(pre))
-    d = H.hive_drain_create(16, 0, 64, 8, 10_000_000)
+    d = H.hive_drain_create(16, bpc, 64, 8, 10_000_000)
     outs, tickets, keep = [], [], []
     for mb in batches:
         o_, k_, v_ = dev(mb["ops"]), dev(mb["keys"]), dev(mb["vals"])
@@ -636,7 +637,7 @@ def test_drain_matches_plain_and_oracle_mixed(H):
         keep += [o_, k_, v_]
         tickets.append(H.hive_drain_submit(d, drained.h, H.HIVE_OP_MIXED, k_, v_, o_, vo, fo))
         outs.append((vo, fo))
-    case("drain launch, 6 mixed batches")
+    case(f"drain launch, 6 mixed batches, {bpc} blocks per CU")
     H.hive_drain_launch(d, 0)
     torch.cuda.synchronize()
     assert all(H.hive_drain_poll(d, t) for t in tickets)
@@ -655,7 +656,8 @@ def test_drain_matches_plain_and_oracle_mixed(H):
     H.hive_drain_destroy(d)
 
 
-def test_drain_multi_table_linear_policies(H):
+@pytest.mark.parametrize("bpc", [0, 1])
+def test_drain_multi_table_linear_policies(H, bpc):
     """Interleaved batches on three LINEAR tables with pre-batch expansion
     and post-batch contraction: outputs equal the dictionary's and the
     geometry equals that of the same sequence run with plain launches."""
@@ -665,7 +667,7 @@ def test_drain_multi_table_linear_policies(H):
     tabs = {i: linear_table(H, nb0, mb_, 4) for i in names}
     refs = {i: linear_table(H, nb0, mb_, 4) for i in names}
     o1 = {i: oracle.O1() for i in names}
-    d = H.hive_drain_create(16, 0, 128, 8, 10_000_000)
+    d = H.hive_drain_create(16, bpc, 128, 8, 10_000_000)
     ks = {i: wl.KeyStream(70 + i) for i in names}
     plan = []
     for step in range(5):
@@ -688,7 +690,7 @@ def test_drain_multi_table_linear_policies(H):
         t = H.hive_drain_submit(d, tabs[i].h, mode, k_, v_, None, vo, fo, flags=H.HIVE_UNIQUE)
         assert t is not None
         outs.append((vo, fo))
-    case("drain launch, multi-table linear")
+    case(f"drain launch, multi-table linear, {bpc} blocks per CU")
     H.hive_drain_launch(d, 0)
     torch.cuda.synchronize()
     for (i, mode, keys), (vo, fo) in zip(plan, outs):
