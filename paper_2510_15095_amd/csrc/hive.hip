@@ -1515,7 +1515,7 @@ __device__ __forceinline__ uint32_t successor(volatile ReqState *r, const ReqDes
   volatile Ctl *c = d.t.ctl;
   const bool linear = d.t.addressing == ADDR_LINEAR;
   switch (ph) {
-    case PH_START: return PH_FILL;
+    case PH_START: return d.n ? PH_FILL : PH_DONE;  // an empty batch changes nothing, as in the plain path
     case PH_FILL: return PH_DEDUPE;
     case PH_DEDUPE: return PH_COUNT;
     case PH_COUNT:

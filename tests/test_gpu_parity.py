@@ -656,6 +656,41 @@ def test_drain_matches_plain_and_oracle_mixed(H, bpc):
     H.hive_drain_destroy(d)
 
 
+def test_drain_empty_batches_change_nothing(H):
+    """Empty batches of every mode complete through the executor and leave
+    the table as the plain entry points do (which return at once): a LINEAR
+    table grown by hand below its contraction threshold keeps its buckets."""
+    import torch
+    tabs = [linear_table(H, 8, 4096, 4) for _ in range(2)]
+    keys = wl.KeyStream(90).range(0, 600)
+    for t in tabs:
+        t.insert(dev(keys), dev(wl.values_for(keys)), flags=H.HIVE_UNIQUE)
+        t.resize(400)  # 600 keys in well over 400 buckets: far under 25%
+    drained, plain = tabs
+    before = drained.stats()
+    e = torch.empty(0, dtype=torch.uint32, device="cuda")
+    e8 = torch.empty(0, dtype=torch.uint8, device="cuda")
+    d = H.hive_drain_create(16, 1, 16, 2, 10_000_000)
+    tickets = [H.hive_drain_submit(d, drained.h, mode, e, e, e8, e, e8)
+               for mode in (H.HIVE_OP_INSERT, H.HIVE_OP_DELETE, H.HIVE_OP_LOOKUP, H.HIVE_OP_MIXED)]
+    tickets.append(H.hive_drain_submit(d, drained.h, H.HIVE_OP_LOOKUP, dev(keys), None, None, e.new_empty(600),
+                                       e8.new_empty(600)))
+    case("drain launch, empty batches")
+    H.hive_drain_launch(d, 0)
+    torch.cuda.synchronize()
+    done, _ = H.hive_drain_results(d, tickets)
+    assert done.all()
+    plain.insert(e, e)
+    plain.delete(e)
+    plain.lookup(e)
+    plain.mixed(e8, e, e)
+    after, ref = drained.stats(), plain.stats()
+    assert geometry(after) == geometry(before) == geometry(ref), (before, after, ref)
+    assert after["live"] == ref["live"] == keys.size
+    assert np.array_equal(drained.dump(), plain.dump())
+    H.hive_drain_destroy(d)
+
+
 @pytest.mark.parametrize("bpc", [0, 1])
 def test_drain_multi_table_linear_policies(H, bpc):
     """Interleaved batches on three LINEAR tables with pre-batch expansion
