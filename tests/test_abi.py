@@ -31,7 +31,7 @@ def declared_functions():
     return sorted(set(re.findall(r"\b(hive_[a-z0-9_]+)\s*\(", text)))
 
 
-def test_header_declares_the_north_star_calls():
+def test_header_declares_the_problem_statement_calls():
     names = declared_functions()
     for required in ("hive_create", "hive_insert_batch", "hive_lookup_batch", "hive_delete_batch",
                      "hive_resize", "hive_stats"):
