@@ -819,18 +819,20 @@ def _served_setup():
     return _SERVED["specs"], _SERVED["reqs"]
 
 
-def test_served_results_same_alone_and_in_the_mix(H):
+@pytest.mark.parametrize("bpc", [1, 0])  # the server's default, then full occupancy
+def test_served_results_same_alone_and_in_the_mix(H, bpc):
     """Each request's outputs are the same whether it runs alone (one at a
     time, in submission order) or in the mix served by the persistent
     executor or by plain per-request launches on several streams."""
     from paper_2510_15095_amd import serve as sv
     specs, reqs = _served_setup()
-    srv = sv.Server(specs, 2 * sv.footprint_bytes(specs), max_request=1 << 11, ring=64, streams=4)
+    srv = sv.Server(specs, 2 * sv.footprint_bytes(specs), max_request=1 << 11, ring=64, streams=4,
+                    blocks_per_cu=bpc)
     case("served: alone")
     srv.load()
     alone = srv.run_alone(reqs)
     for mode in ("persistent", "plain"):
-        case(f"served: {mode}")
+        case(f"served: {mode}, {bpc} blocks per CU")
         srv.load()
         res = srv.run(reqs, mode, outputs=True, timeout_s=60)
         for i, ((v1, f1), (v2, f2)) in enumerate(zip(alone, res["results"])):
