@@ -314,7 +314,9 @@ hive_status hive_drain_submit(hive_drain_t d, hive_t table, const hive_batch_des
  * until hive_drain_stop, and holds up no other stream meanwhile (device
  * memory the batches use must be allocated before the launch).  A resident
  * grid leaves one block's room per compute unit free, so that other kernels
- * of the process (copies included) can run while it waits. */
+ * of the process (copies included) can run while it waits; when the worker
+ * kernel's occupancy (queried at create) fits only one block per compute
+ * unit, a resident launch returns HIVE_ERR_BUDGET and starts nothing. */
 hive_status hive_drain_launch(hive_drain_t d, int resident, void *stream);
 
 /* *done = 1 once the batch's outputs and table updates are complete and

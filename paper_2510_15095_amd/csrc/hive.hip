@@ -1607,9 +1607,11 @@ __device__ __forceinline__ void phase_fold(ReqState *rs, const ReqDesc &d, uint3
 // SOLO_CHUNKS chunks is published already fully claimed, by this block: a
 // small batch runs phase after phase in one block, without a window scan
 // and without the acquires (L2 invalidations) of a handoff, since no other
-// block writes its data meanwhile.  The release before publishing stays
-// (later phases read buckets with coherent loads, which must see this
-// block's plain stores), and so does the full release when the batch is done.
+// block writes its data meanwhile.  Each such phase starts with an L1
+// invalidation instead (invalidate_l1: the block's own atomics of the last
+// phase are not in its L1).  The release before publishing stays (later
+// phases read buckets with coherent loads, which must see this block's plain
+// stores), and so does the full release when the batch is done.
 constexpr uint64_t SOLO_CHUNKS = 4;
 __device__ uint64_t advance(DrainQueue *q, ReqState *rs, const ReqDesc &d, uint32_t ph, bool own) {
   if (!own) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
@@ -1954,6 +1956,16 @@ __global__ void drain_reset_kernel(DrainQueue *q) { q->final_seen = 0; }
 // One reading of the constant-rate device clock (clock-rate calibration).
 __global__ void wall_clock_kernel(uint64_t *out) { *out = wall_clock64(); }
 
+// Invalidate this compute unit's vector L1 cache (the L2 is untouched).
+// An agent-scope acquire fence does this and also invalidates the XCD's L2
+// lines of non-coherent memory types; a block that runs consecutive phases of
+// one batch alone needs only the former: its own device-scope atomics
+// (claims, evictions, stash placements) were performed in its XCD's L2, but
+// lines its earlier plain loads brought into the L1 still hold the words
+// those atomics replaced, and the next phase's plain loads (split, merge,
+// stash drain, probe) would read them.
+__device__ __forceinline__ void invalidate_l1() { asm volatile("buffer_inv sc0" ::: "memory"); }
+
 // Occupancy target: 3 waves per SIMD (at most 168 VGPRs).  The 16-slot build
 // spills three registers of the control loop, none inside a phase; a cap of
 // 128 (4 waves) spills inside the phases and runs slower.
@@ -2010,6 +2022,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       load_desc(&desc, &r->d);
       __syncthreads();
+    } else {
+      invalidate_l1();
     }
     const ReqDesc d = uniform_desc(desc);
     const uint32_t phase = __builtin_amdgcn_readfirstlane(s_phase);
@@ -2099,6 +2113,7 @@ struct hive_drain {
   uint64_t cap = 0;
   uint32_t max_tables = 0;
   unsigned grid[2] = {0, 0};  // blocks of a launch: [0] draining, [1] resident
+  int fit_per_cu = 0;         // worker blocks that fit one CU (occupancy query)
   DrainQueue *d_q = nullptr;
   ReqState *d_req = nullptr;
   uint64_t *d_table_next = nullptr;
@@ -2222,7 +2237,17 @@ static uint64_t wl_seg_cap_for(uint64_t n) {
   return std::max<uint64_t>(1, (tiles + NSHARD - 1) / NSHARD) * BLOCK;
 }
 
-static hive_status ensure_scratch(hive_table *h, uint64_t n, bool need_dd, hipStream_t st) {
+// n_wl: operations (or drained entries) that may reach the eviction worklist;
+// n_dd: operations the dedupe set must hold (0: none).  The set is sized
+// from the whole batch, not from its inserts: a delete batch sends nothing
+// to the worklist but records every operation in the set.
+static uint64_t dd_words_for(uint64_t n) {
+  uint64_t want = 16;
+  while (want < 2 * n) want <<= 1;
+  return want;
+}
+
+static hive_status ensure_scratch(hive_table *h, uint64_t n, uint64_t n_dd, hipStream_t st) {
   if (n > h->wl_cap) {
     HIP_OK(hipStreamSynchronize(st));
     (void)hipFree(h->d_wl);
@@ -2236,9 +2261,8 @@ static hive_status ensure_scratch(hive_table *h, uint64_t n, bool need_dd, hipSt
     h->wl_cap = cap;
     h->wl_seg_cap = seg;
   }
-  if (need_dd) {
-    uint64_t want = 16;
-    while (want < 2 * n) want <<= 1;
+  if (n_dd > 0) {
+    const uint64_t want = dd_words_for(n_dd);
     if (want > h->dd_cap) {
       HIP_OK(hipStreamSynchronize(st));
       (void)hipFree(h->d_dd);
@@ -2409,12 +2433,13 @@ static hive_status wall_clock_rate(double *ticks_per_us) {
 // polling grid such a kernel cannot start until the grid exits.  So a
 // resident grid takes one block per CU fewer than fit (at least one).
 template <int S>
-static hive_status drain_grid(uint32_t blocks_per_cu, unsigned grid[2]) {
+static hive_status drain_grid(uint32_t blocks_per_cu, unsigned grid[2], int *fit_per_cu) {
   int dev = 0, cus = 0, per_cu = 0;
   HIP_OK(hipGetDevice(&dev));
   HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, drain_worker_kernel<S>, BLOCK, 0));
   if (per_cu < 1) return HIVE_ERR_HIP;
+  *fit_per_cu = per_cu;
   const unsigned want = blocks_per_cu ? blocks_per_cu : (unsigned)per_cu;
   grid[0] = (unsigned)cus * std::min<unsigned>(want, (unsigned)per_cu);
   grid[1] = (unsigned)cus * std::min<unsigned>(want, (unsigned)std::max(1, per_cu - 1));
@@ -2448,7 +2473,7 @@ static hive_status run_batch(hive_t h, uint32_t mode, const uint8_t *d_ops, cons
   const bool dedupe = !(flags & HIVE_UNIQUE) && mode != OP_LOOKUP;
   // only inserts reach the eviction worklist
   const uint64_t wl_need = (mode == OP_INSERT || mode == OP_MIXED) ? n : 0;
-  hive_status s = ensure_scratch(h, wl_need, dedupe, st);
+  hive_status s = ensure_scratch(h, wl_need, dedupe ? n : 0, st);
   if (s != HIVE_OK) return s;
   OpsArgs a{};
   a.buckets = h->d_buckets;
@@ -2468,8 +2493,7 @@ static hive_status run_batch(hive_t h, uint32_t mode, const uint8_t *d_ops, cons
   a.pending_cap = h->pending_cap;
   if (dedupe) {
     phase_mark(h, HIVE_PHASE_DEDUPE, st);
-    uint64_t cap = 16;
-    while (cap < 2 * n) cap <<= 1;
+    const uint64_t cap = dd_words_for(n);  // within dd_cap: ensure_scratch sized it from n
     if ((s = fill_u64(h->d_dd, cap, EMPTY, st)) != HIVE_OK) return s;
     hipLaunchKernelGGL(dedupe_build_kernel, dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, st, h->d_dd,
                        cap - 1, mode, d_ops, d_keys, n);
@@ -2579,7 +2603,7 @@ hive_status hive_create(const hive_config *cfg_in, uint64_t initial_buckets, voi
   // the worklist must hold a full stash + pending drain (after a split);
   // the drain walks the whole stash table
   const uint64_t min_wl = stash_slots_for(h->stash_cap) + h->pending_cap;
-  if ((s = ensure_scratch(h, std::max<uint64_t>(cfg.max_batch, min_wl), cfg.max_batch > 0, st)) != HIVE_OK) {
+  if ((s = ensure_scratch(h, std::max<uint64_t>(cfg.max_batch, min_wl), cfg.max_batch, st)) != HIVE_OK) {
     free_table(h);
     return s;
   }
@@ -2782,9 +2806,9 @@ hive_status hive_drain_create(uint32_t slots_per_bucket, uint32_t blocks_per_cu,
   d->max_tables = max_tables;
   hive_status s = HIVE_OK;
   switch (d->S) {
-    case 16: s = drain_grid<16>(blocks_per_cu, d->grid); break;
-    case 32: s = drain_grid<32>(blocks_per_cu, d->grid); break;
-    default: s = drain_grid<64>(blocks_per_cu, d->grid); break;
+    case 16: s = drain_grid<16>(blocks_per_cu, d->grid, &d->fit_per_cu); break;
+    case 32: s = drain_grid<32>(blocks_per_cu, d->grid, &d->fit_per_cu); break;
+    default: s = drain_grid<64>(blocks_per_cu, d->grid, &d->fit_per_cu); break;
   }
   if (s != HIVE_OK) {
     free_drain(d);
@@ -2876,19 +2900,16 @@ hive_status hive_drain_submit(hive_drain_t d, hive_t h, const hive_batch_desc *b
     d->n_tables++;
   }
   const bool dedupe = !(b->flags & HIVE_UNIQUE) && b->op_mode != HIVE_OP_LOOKUP;
-  uint64_t dd_size = 0;
-  if (dedupe && b->n > 0) {
-    dd_size = 16;
-    while (dd_size < 2 * b->n) dd_size <<= 1;
-  }
+  const uint64_t dd_size = (dedupe && b->n > 0) ? dd_words_for(b->n) : 0;
   // scratch is never reallocated under a running executor; only inserts
-  // reach the eviction worklist
+  // reach the eviction worklist, while the dedupe set holds every operation
   const uint64_t wl_need = (b->op_mode == HIVE_OP_INSERT || b->op_mode == HIVE_OP_MIXED) ? b->n : 0;
   if (wl_need > h->wl_cap || dd_size > h->dd_cap) {
     if (d->running) return HIVE_ERR_ARG;
-    hive_status s = ensure_scratch(h, wl_need, dedupe, h->last);
+    hive_status s = ensure_scratch(h, wl_need, dd_size ? b->n : 0, h->last);
     if (s != HIVE_OK) return s;
   }
+  if (wl_need > h->wl_cap || dd_size > h->dd_cap) return HIVE_ERR_OOM;  // cannot happen after a good grow
   ReqDesc r;
   memset(&r, 0, sizeof(r));
   r.t = TableDesc{h->d_buckets,    h->d_hint,  h->d_stash,   h->d_pending, h->d_ctl, h->d_wl, h->d_dd,
@@ -2919,6 +2940,15 @@ hive_status hive_drain_submit(hive_drain_t d, hive_t h, const hive_batch_desc *b
 hive_status hive_drain_launch(hive_drain_t d, int resident, void *stream) {
   if (!d || d->running) return HIVE_ERR_ARG;
   const int mode = resident ? 1 : 0;
+  // a resident grid that fills every CU leaves no room for the process's
+  // other kernels (HIP's own copy kernels included), which the host may wait
+  // on before its next submission: the grid then idles until its watchdog
+  // (the resident grid takes at most fit_per_cu - 1 blocks per CU)
+  if (resident && d->fit_per_cu < 2) {
+    fprintf(stderr, "hive: a resident executor grid needs room for a second block per compute unit "
+                    "(the worker fits %d per CU)\n", d->fit_per_cu);
+    return HIVE_ERR_BUDGET;
+  }
   hipStream_t user = (hipStream_t)stream;
   // a resident grid runs on the executor's own non-blocking stream, after the
   // work already enqueued on `stream`, so it holds up no other stream

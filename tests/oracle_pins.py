@@ -117,6 +117,46 @@ def pin_hash_inverses(L, n=3000, seed=1):
         assert int(L.o2_bithash2(bithash2_inverse(y))) == y
 
 
+# -------------------------------------------- hashes as the listing prints them
+def listing_bithash1(key: int) -> int:
+    """BitHash1 of the Section III-C listing, one statement per line as it is
+    printed, on a 32-bit unsigned key (every statement wraps mod 2^32); the
+    listing's final "% nBuckets" is left to the addressing."""
+    key = (~key + (key << 15)) & M32
+    key ^= key >> 12
+    key = (key + (key << 2)) & M32
+    key ^= key >> 4
+    key = (key * 2057) & M32
+    key ^= key >> 16
+    return key
+
+
+def listing_bithash2(key: int) -> int:
+    """BitHash2 of the Section III-C listing, statement by statement."""
+    key = ((key + 0x7ED55D16) + (key << 12)) & M32
+    key = ((key ^ 0xC761C23C) ^ (key >> 19)) & M32
+    key = ((key + 0x165667B1) + (key << 5)) & M32
+    key = ((key + 0xD3A2646C) ^ (key << 9)) & M32
+    key = ((key + 0xFD7046C5) + (key << 3)) & M32
+    key = ((key ^ 0xB55A4F09) ^ (key >> 16)) & M32
+    return key
+
+
+LISTING_EDGE_KEYS = [0, 1, 2, 3, 0x7FFF, 0x8000, 0xFFFF, 0x10000, 0x7FFFFFFF, 0x80000000, 0x80000001,
+                     0xFFFFFFFE, M32] + [1 << b for b in range(32)] + [M32 ^ (1 << b) for b in range(32)]
+
+
+def pin_bithash_as_printed(L, n=100_000, seed=9):
+    """The oracle's hashes equal the listing's statements evaluated as
+    printed (not the oracle's own restatement as affine and xor-shift maps),
+    on edge keys and n random keys."""
+    rng = random.Random(seed)
+    keys = LISTING_EDGE_KEYS + [rng.getrandbits(32) for _ in range(n)]
+    for k in keys:
+        assert int(L.o2_bithash1(k)) == listing_bithash1(k), f"BitHash1 differs from the listing at {k:#x}"
+        assert int(L.o2_bithash2(k)) == listing_bithash2(k), f"BitHash2 differs from the listing at {k:#x}"
+
+
 # ------------------------------------------------------ addressing pins
 def pin_fixed_addressing_is_modulo(L, seed=2):
     rng = random.Random(seed)
@@ -409,6 +449,7 @@ def pin_policy_post_contract(L):
 ALL_PINS = [
     pin_o1_matches_python_dict,
     pin_hash_inverses,
+    pin_bithash_as_printed,
     pin_fixed_addressing_is_modulo,
     pin_linear_addressing_textbook,
     pin_o2_matches_o1_fixed,

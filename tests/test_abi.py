@@ -2,7 +2,8 @@
 
 * the library loads and exports every entry point include/hive.h declares;
 * its host copies of the device hash and reduction agree with independent
-  definitions: the oracle's BitHash transcription and Python's `%`;
+  definitions: the BitHash listing evaluated as printed, the oracle's
+  transcription and Python's `%`;
 * argument errors are reported before any device work.
 """
 import ctypes
@@ -55,6 +56,16 @@ def test_device_hash_matches_oracle_transcription(H):
     for x in [0, 1, 2, 0xFFFFFFFF, 0x80000000] + [rng.getrandbits(32) for _ in range(20000)]:
         assert H.hive_bithash1(x) == oracle.bithash1(x)
         assert H.hive_bithash2(x) == oracle.bithash2(x)
+
+
+def test_device_hash_matches_listing_as_printed(H):
+    """The device hashes (host-compiled copy of the same source) against the
+    Section III-C listing evaluated statement by statement as printed."""
+    import oracle_pins as P
+    rng = random.Random(5)
+    for x in P.LISTING_EDGE_KEYS + [rng.getrandbits(32) for _ in range(100_000)]:
+        assert H.hive_bithash1(x) == P.listing_bithash1(x), hex(x)
+        assert H.hive_bithash2(x) == P.listing_bithash2(x), hex(x)
 
 
 def test_fastmod_equals_modulo(H):
