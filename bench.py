@@ -133,19 +133,14 @@ def base_record(args, value, ms_step, workload, extra_config):
     }
 
 
-def _gen_mixed(b, n_ops, universe):
-    from paper_2510_15095_amd import workload as wl
-    mb = wl.mixed_batch(3, b, n_ops, universe)
-    return mb["ops"], mb["keys"], mb["vals"]
-
-
 def gen_mixed(args):
-    """The mixed workload's batches (generated before the GPU is used)."""
+    """The mixed workload's batches (host arrays, the native generator)."""
     from paper_2510_15095_amd import workload as wl
     n_ops, nbat = 1 << args.batch_log2, args.batches
-    gen = wl.parallel_map(_gen_mixed, [(b, n_ops, 1 << 26) for b in range(nbat)], min(16, os.cpu_count() or 1))
+    ks = wl.KeyStream(3)
+    gen = wl.mixed_batches([dict(seed=3, batch=b, n_ops=n_ops, universe=1 << 26, stream=ks) for b in range(nbat)])
     print(f"[bench] generated {nbat} mixed batches", file=sys.stderr, flush=True)
-    return gen
+    return [(mb["ops"], mb["keys"], mb["vals"]) for mb in gen]
 
 
 def gen_served(args):
@@ -153,8 +148,7 @@ def gen_served(args):
     is used)."""
     from paper_2510_15095_amd import serve as sv
     specs = sv.make_specs(args.tables, 5, log2_min=12, log2_max=22)
-    reqs = sv.make_requests(specs, args.requests, 5, rate=0, log2_max_size=args.request_log2,
-                            workers=min(16, os.cpu_count() or 1))
+    reqs = sv.make_requests(specs, args.requests, 5, rate=0, log2_max_size=args.request_log2)
     print(f"[bench] {len(reqs)} requests on {len(specs)} tables generated", file=sys.stderr, flush=True)
     return specs, reqs
 

@@ -40,7 +40,7 @@ def build_workload() -> str:
     out = os.path.join(PKG, "libworkload_gen.so")
     tmp = out + ".tmp"
     _run(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=c11", "-Wall",
-          os.path.join(CSRC, "workload_gen.c"), "-o", tmp])
+          os.path.join(CSRC, "workload_gen.c"), "-lm", "-o", tmp])
     _atomic_replace(tmp, out)
     return out
 

@@ -76,19 +76,13 @@ class Request:
     vals: np.ndarray
 
 
-def _gen_request(args):
-    rid, spec_seed, universe, n, zipf = args
-    mb = wl.mixed_batch(spec_seed, rid, n, universe, frac_insert=0.25, frac_delete=0.25,
-                        zipf_s=0.99 if zipf else None, stream=wl.KeyStream(spec_seed), value_salt=rid + 1)
-    return mb["ops"], mb["keys"], mb["vals"]
-
-
-def make_requests(specs, n_req: int, seed: int, rate: float, log2_max_size: float = 16, workers: int = 8):
+def make_requests(specs, n_req: int, seed: int, rate: float, log2_max_size: float = 16):
     """Poisson arrivals at `rate` requests/s (rate <= 0: all at time 0);
     sizes floor(2^U(0, log2_max_size)), at most the table's initial key count;
     50% lookup / 25% insert / 25% delete; uniform or Zipf(0.99) keys by a
-    per-request coin; tables uniform.  With workers > 1, call before the
-    GPU is used (the generator runs in worker processes)."""
+    per-request coin; tables uniform.  Request r on table t is mixed batch r
+    of t's seed over t's key universe (the native generator, many requests
+    at once)."""
     rng = np.random.default_rng(wl.batch_seed(seed, 0x5E5))
     tables = rng.integers(0, len(specs), n_req)
     sizes = np.floor(2.0 ** rng.uniform(0, log2_max_size, n_req)).astype(np.int64)
@@ -96,13 +90,20 @@ def make_requests(specs, n_req: int, seed: int, rate: float, log2_max_size: floa
     gaps = rng.exponential(1.0 / rate, n_req) if rate > 0 else np.zeros(n_req)
     arrivals = np.cumsum(gaps) - (gaps[0] if n_req else 0)
     sizes = np.minimum(sizes, [specs[t].n_keys for t in tables])
-    jobs = [(r, specs[tables[r]].seed, specs[tables[r]].universe, int(sizes[r]), bool(zipf[r])) for r in range(n_req)]
-    # worker processes only before the GPU is used in this process
-    gen = wl.parallel_map(_gen_request, [(j,) for j in jobs], workers)
+    streams = {}
+    jobs = []
+    for r in range(n_req):
+        sp = specs[tables[r]]
+        if sp.seed not in streams:
+            streams[sp.seed] = wl.KeyStream(sp.seed)
+        jobs.append(dict(seed=sp.seed, batch=r, n_ops=int(sizes[r]), universe=sp.universe, frac_insert=0.25,
+                         frac_delete=0.25, zipf_s=0.99 if zipf[r] else None, stream=streams[sp.seed],
+                         value_salt=r + 1))
+    gen = wl.mixed_batches(jobs)
     out = []
-    for r, (ops, keys, vals) in enumerate(gen):
+    for r, mb in enumerate(gen):
         out.append(Request(r, int(tables[r]), float(arrivals[r]), int(sizes[r]),
-                           int((ops == wl.OP_INSERT).sum()), ops, keys, vals))
+                           int((mb["ops"] == wl.OP_INSERT).sum()), mb["ops"], mb["keys"], mb["vals"]))
     return out
 
 

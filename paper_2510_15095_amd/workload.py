@@ -45,13 +45,11 @@ OP_LOOKUP = 2
 
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libworkload_gen.so")
 _lib = None
-_native_touched = False  # the OpenMP generator may have run in this process
 
 
 def _native():
     """The compiled generator (csrc/workload_gen.c), or None if not built."""
-    global _lib, _native_touched
-    _native_touched = True
+    global _lib
     if _lib is None and os.path.exists(_LIB_PATH):
         lib = ctypes.CDLL(_LIB_PATH)
         p = ctypes.c_void_p
@@ -60,8 +58,8 @@ def _native():
         lib.wl_keys_range.argtypes = [p, i64, i64, i64, i64, p]
         lib.wl_index_of.argtypes = [p, i64, i64, p, i64, p]
         lib.wl_values.argtypes = [p, i64, p]
-        lib.wl_resolve_mixed.argtypes = [p, i64, p, p, i64]
-        lib.wl_resolve_mixed.restype = i64
+        lib.wl_mixed_many.argtypes = [i64] + [p] * 14
+        lib.wl_mixed_many.restype = ctypes.c_int
         lib.wl_domain_perm.argtypes = [p, i64, p, i64, p]
         lib.wl_domain_perm.restype = ctypes.c_int
         _lib = lib
@@ -328,6 +326,75 @@ def tiny_workload(seed: int = 1) -> dict:
     return bulk_workload(seed, 1 << 16)
 
 
+def _mixed_counts(n_ops: int, frac_insert: float, frac_delete: float) -> tuple[int, int]:
+    n_ins = int(round(n_ops * frac_insert))
+    n_del = int(round(n_ops * frac_delete))
+    if n_ins + n_del > n_ops:
+        raise ValueError("op fractions exceed 1")
+    return n_ins, n_del
+
+
+def mixed_batches(jobs) -> list[dict]:
+    """Many mixed batches at once (csrc/workload_gen.c, one thread per batch).
+
+    `jobs` holds dicts of `mixed_batch`'s arguments.  Each batch's random
+    numbers come from one SplitMix64 stream seeded with batch_seed(seed,
+    batch), consumed in this order: a Fisher-Yates shuffle of the op codes
+    (exact counts), one rank per op (Zipf(s) by rejection-inversion, or
+    uniform over 1..universe when zipf_s is None), then the ranks that the
+    per-type disjointness rule redraws (see `mixed_batch_reference`).  The
+    results are views into shared arrays, one dict per job."""
+    lib = _native()
+    if lib is None:
+        raise RuntimeError("the native generator (libworkload_gen.so) is not built")
+    jobs = [dict(j) for j in jobs]
+    count = len(jobs)
+    n = np.array([int(j["n_ops"]) for j in jobs], np.int64)
+    off = np.zeros(count, np.int64)
+    if count:
+        off[1:] = np.cumsum(n)[:-1]
+    total = int(n.sum())
+    seeds = np.empty(count, np.uint64)
+    n_ins = np.empty(count, np.int64)
+    n_del = np.empty(count, np.int64)
+    uni = np.empty(count, np.int64)
+    zs = np.empty(count, np.float64)
+    rk = np.empty(4 * count, np.uint32)
+    ab = np.empty(2 * count, np.int64)
+    salt = np.empty(count, np.uint32)
+    for c, j in enumerate(jobs):
+        stream = j.get("stream") or KeyStream(j["seed"])
+        seeds[c] = batch_seed(j["seed"], j["batch"])
+        n_ins[c], n_del[c] = _mixed_counts(int(n[c]), j.get("frac_insert", 0.4), j.get("frac_delete", 0.4))
+        uni[c] = int(j["universe"])
+        if n_del[c] > uni[c] or uni[c] < 1 or uni[c] > KeyStream.N_VALID:
+            raise ValueError("the universe must hold the batch's distinct delete keys and fit the key stream")
+        z = j.get("zipf_s", 0.99)
+        if z is not None and (z <= 0 or z == 1.0):
+            raise ValueError("need zipf_s > 0, != 1 (or None for uniform)")
+        zs[c] = -1.0 if z is None else float(z)
+        rk[4 * c:4 * c + 4] = stream._rk_arr
+        ab[2 * c], ab[2 * c + 1] = stream._a, stream._b
+        salt[c] = int(j.get("value_salt", 0)) & M32
+    ops = np.empty(total, np.uint8)
+    keys = np.empty(total, np.uint32)
+    vals = np.empty(total, np.uint32)
+    ranks = np.empty(total, np.int64)
+    if count:
+        rc = lib.wl_mixed_many(count, _ptr(seeds), _ptr(n), _ptr(off), _ptr(n_ins), _ptr(n_del), _ptr(uni),
+                               _ptr(zs), _ptr(rk), _ptr(ab), _ptr(salt), _ptr(ops), _ptr(keys), _ptr(vals),
+                               _ptr(ranks))
+        if rc == -1:
+            raise RuntimeError("mixed batch: key universe too small for per-type disjoint keys")
+        if rc != 0:
+            raise MemoryError("mixed batch generator could not allocate")
+    out = []
+    for c in range(count):
+        sl = slice(int(off[c]), int(off[c] + n[c]))
+        out.append({"ops": ops[sl], "keys": keys[sl], "vals": vals[sl], "ranks": ranks[sl]})
+    return out
+
+
 def mixed_batch(seed: int, batch: int, n_ops: int, universe: int,
                 frac_insert: float = 0.4, frac_delete: float = 0.4,
                 zipf_s: float | None = 0.99, stream: KeyStream | None = None,
@@ -341,62 +408,55 @@ def mixed_batch(seed: int, batch: int, n_ops: int, universe: int,
     Inserts may repeat a key (last occurrence wins); lookups may repeat.
     value_salt != 0 makes insert values differ from value(k) (replace tests).
     """
-    stream = stream or KeyStream(seed)
-    rng = np.random.default_rng(batch_seed(seed, batch))
-    n_ins = int(round(n_ops * frac_insert))
-    n_del = int(round(n_ops * frac_delete))
-    n_look = n_ops - n_ins - n_del
-    if n_look < 0:
-        raise ValueError("op fractions exceed 1")
-    ops = np.concatenate([np.full(n_ins, OP_INSERT, np.uint8), np.full(n_del, OP_DELETE, np.uint8),
-                          np.full(n_look, OP_LOOKUP, np.uint8)])
-    rng.shuffle(ops)
-    zipf = Zipf(universe, zipf_s) if zipf_s is not None else None
+    return mixed_batches([dict(seed=seed, batch=batch, n_ops=n_ops, universe=universe, frac_insert=frac_insert,
+                               frac_delete=frac_delete, zipf_s=zipf_s, stream=stream, value_salt=value_salt)])[0]
 
-    def draw(count):
-        if zipf is not None:
-            return zipf.sample(rng, count)
-        return rng.integers(1, universe + 1, size=count, dtype=np.int64)
 
-    if n_del > universe:
-        raise ValueError("the universe is smaller than the number of distinct delete keys")
-    ranks = draw(n_ops)
-    lib = _native()
-    if lib is not None:
-        pool_n = max(1024, n_ops)
+def mixed_batch_reference(seed: int, batch: int, n_ops: int, universe: int,
+                          frac_insert: float = 0.4, frac_delete: float = 0.4,
+                          zipf_s: float | None = 0.99, stream: KeyStream | None = None,
+                          value_salt: int = 0) -> dict:
+    """Pure-Python statement of `mixed_batch` (small batches only): the same
+    SplitMix64 stream, shuffle, rank draws and disjointness rule, written
+    with Python integers and the math module."""
+    import math
+    stream = stream or KeyStream(seed, native=False)
+    state = [batch_seed(seed, batch)]
+
+    def nxt() -> int:
+        state[0] = (state[0] + 0x9E3779B97F4A7C15) & M64
+        z = state[0]
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M64
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M64
+        return z ^ (z >> 31)
+
+    def below(m: int) -> int:
+        return (nxt() * m) >> 64
+
+    if zipf_s is not None:
+        q = 1.0 - zipf_s
+        H = lambda x: math.expm1(q * math.log(x)) / q  # noqa: E731
+        Hinv = lambda y: math.exp(math.log1p(q * y) / q)  # noqa: E731
+        lo, hi = H(1.5) - 1.0, H(universe + 0.5)
+
+    def rank() -> int:
+        if zipf_s is None:
+            return 1 + below(universe)
         while True:
-            if pool_n > 64 * max(n_ops, 1024):
-                raise RuntimeError("mixed batch: key universe too small for per-type disjoint keys")
-            pool = draw(pool_n)
-            r = ranks.copy()
-            used = lib.wl_resolve_mixed(_ptr(ops), n_ops, _ptr(r), _ptr(pool), pool_n)
-            if used >= 0:
-                ranks = r
-                break
-            if used < -1:
-                raise MemoryError("mixed batch resolver could not allocate")
-            pool_n *= 2
-    else:
-        ranks = resolve_mixed_reference(ops, ranks, draw)
-    keys = stream.keys(ranks - 1)
-    vals = values_for(keys)
-    if value_salt:
-        vals = (vals ^ np.uint32(value_salt & M32)).astype(np.uint32)
-    return {"ops": ops, "keys": keys, "vals": vals, "ranks": ranks}
+            u = lo + ((nxt() >> 11) * 2.0 ** -53) * (hi - lo)
+            k = min(max(math.floor(Hinv(u) + 0.5), 1), universe)
+            if u >= H(k + 0.5) - math.pow(k, -zipf_s):
+                return k
 
-
-def resolve_mixed_reference(ops: np.ndarray, ranks: np.ndarray, draw) -> np.ndarray:
-    """Pure-Python statement of the disjointness rule (small batches only).
-
-    Ops are visited in index order; op i keeps its rank unless that rank is
-    owned by another type or is a delete rank already used, in which case it
-    takes the next draw.  The first op to take a rank owns it."""
+    n_ins, n_del = _mixed_counts(n_ops, frac_insert, frac_delete)
+    ops = [OP_INSERT] * n_ins + [OP_DELETE] * n_del + [OP_LOOKUP] * (n_ops - n_ins - n_del)
+    for i in range(n_ops - 1, 0, -1):
+        j = below(i + 1)
+        ops[i], ops[j] = ops[j], ops[i]
+    ranks = [rank() for _ in range(n_ops)]
     owner: dict[int, int] = {}
-    out = ranks.copy()
-    pool = list(draw(max(1024, 4 * len(ops))))
-    for i in range(len(ops)):
-        r = int(out[i])
-        t = int(ops[i])
+    for i, t in enumerate(ops):
+        r = ranks[i]
         while True:
             o = owner.get(r)
             if o is None:
@@ -404,28 +464,9 @@ def resolve_mixed_reference(ops: np.ndarray, ranks: np.ndarray, draw) -> np.ndar
                 break
             if o == t and t != OP_DELETE:
                 break
-            if not pool:
-                pool = list(draw(max(1024, len(ops))))
-            r = int(pool.pop(0))
-        out[i] = r
-    return out
-
-
-def parallel_map(fn, jobs, workers: int):
-    """[fn(*job) for job in jobs] in `workers` forked worker processes.
-
-    The native generator runs OpenMP, and a process forked after its thread
-    pool exists can deadlock in it, so workers are forked only while this
-    process has not touched the native generator; otherwise the jobs run
-    here, one after another.  Call it before the GPU is used in this
-    process."""
-    import multiprocessing as mp
-    import sys
-    jobs = list(jobs)
-    if workers <= 1 or len(jobs) <= 1 or _native_touched:
-        if workers > 1 and len(jobs) > 1:
-            print("workload: native generator already used in this process; generating without workers",
-                  file=sys.stderr, flush=True)
-        return [fn(*j) for j in jobs]
-    with mp.get_context("fork").Pool(min(workers, len(jobs))) as pool:
-        return pool.starmap(fn, jobs, chunksize=1)
+            r = rank()
+        ranks[i] = r
+    ranks = np.array(ranks, np.int64)
+    keys = stream.keys(ranks - 1)
+    vals = values_for(keys, native=False) ^ np.uint32(value_salt & M32)
+    return {"ops": np.array(ops, np.uint8), "keys": keys, "vals": vals.astype(np.uint32), "ranks": ranks}

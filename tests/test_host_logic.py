@@ -35,7 +35,7 @@ def test_table_specs_sizes_and_reservations(sv):
 
 def test_requests_shape_mix_and_determinism(sv):
     specs = sv.make_specs(16, 3, log2_min=10, log2_max=13)
-    reqs = sv.make_requests(specs, 400, 3, rate=1000.0, log2_max_size=12, workers=0)
+    reqs = sv.make_requests(specs, 400, 3, rate=1000.0, log2_max_size=12)
     assert len(reqs) == 400
     arr = np.array([r.arrival for r in reqs])
     assert arr[0] == 0.0 and np.all(np.diff(arr) >= 0)
@@ -55,7 +55,7 @@ def test_requests_shape_mix_and_determinism(sv):
         counts += [(r.ops == o).sum() for o in (wl.OP_INSERT, wl.OP_DELETE, wl.OP_LOOKUP)]
     frac = counts / counts.sum()
     assert abs(frac[0] - 0.25) < 0.03 and abs(frac[1] - 0.25) < 0.03 and abs(frac[2] - 0.5) < 0.03
-    again = sv.make_requests(specs, 400, 3, rate=1000.0, log2_max_size=12, workers=0)
+    again = sv.make_requests(specs, 400, 3, rate=1000.0, log2_max_size=12)
     for a, b in zip(reqs, again):
         assert a.table == b.table and a.n == b.n and np.array_equal(a.keys, b.keys)
         assert np.array_equal(a.ops, b.ops) and np.array_equal(a.vals, b.vals)
@@ -63,7 +63,7 @@ def test_requests_shape_mix_and_determinism(sv):
 
 def test_requests_all_at_once_when_rate_is_zero(sv):
     specs = sv.make_specs(4, 1, log2_min=10, log2_max=11)
-    reqs = sv.make_requests(specs, 50, 1, rate=0, log2_max_size=8, workers=0)
+    reqs = sv.make_requests(specs, 50, 1, rate=0, log2_max_size=8)
     assert all(r.arrival == 0.0 for r in reqs)
 
 

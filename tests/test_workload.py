@@ -113,39 +113,37 @@ def test_mixed_batch_counts_and_disjointness(zipf_s):
     assert np.unique(del_ranks).size == del_ranks.size
 
 
-def test_mixed_batch_native_resolver_matches_reference():
-    ops = np.array([0, 1, 2, 1, 0, 2, 1, 1, 0], np.uint8)
-    ranks = np.array([5, 5, 5, 7, 7, 8, 9, 9, 9], np.int64)
-    pool = np.array([5, 11, 12, 7, 13, 14, 15, 16, 17, 18, 19, 20], np.int64)
-
-    def draw_from(src):
-        it = iter(src.tolist())
-
-        def draw(count):
-            return np.array([next(it) for _ in range(count)], np.int64)
-        return draw
-
-    lib = wl._native()
-    r = ranks.copy()
-    used = lib.wl_resolve_mixed(wl._ptr(ops), ops.size, wl._ptr(r), wl._ptr(pool), pool.size)
-    assert used >= 0
-    ref = wl.resolve_mixed_reference(ops, ranks, lambda c: pool[:c] if c <= pool.size else
-                                     np.concatenate([pool, np.arange(100, 100 + c - pool.size)]))
-    assert np.array_equal(r, ref)
-    # hand-traced: op1 (delete) cannot take 5 (insert-owned) -> 5 again -> 11;
-    # op2 (lookup) -> 12; op3 delete takes 7; op4 insert cannot take 7 -> 13;
-    # op5 lookup takes 8; op6 delete takes 9; op7 repeated delete 9 -> 14;
-    # op8 insert cannot take 9 -> 15
-    assert r.tolist() == [5, 11, 12, 7, 13, 8, 9, 14, 15]
+@pytest.mark.parametrize("zipf_s", [0.99, 0.5, 1.2, None])
+def test_mixed_batch_native_equals_reference(zipf_s):
+    """The C generator equals the pure-Python statement of the same steps
+    (stream, shuffle, rank draws, disjointness redraws, keys, values),
+    including universes small enough that many ranks are redrawn."""
+    for seed, b, n, u in [(3, 0, 5000, 1 << 16), (7, 2, 3000, 4000), (11, 1, 1, 5), (5, 5, 20000, 1 << 26),
+                          (9, 3, 600, 700)]:
+        a = wl.mixed_batch(seed, b, n, u, zipf_s=zipf_s, value_salt=b)
+        r = wl.mixed_batch_reference(seed, b, n, u, zipf_s=zipf_s, value_salt=b)
+        for f in ("ops", "keys", "vals", "ranks"):
+            assert np.array_equal(a[f], r[f]), (seed, b, n, u, f)
 
 
-def test_parallel_map_equals_sequential():
-    """Generation in worker processes gives the same draws as in-process
-    generation (once the native generator has run in this process,
-    parallel_map runs the jobs in-process instead of forking)."""
-    jobs = [(4, b, 4096, 1 << 16) for b in range(4)]
-    par = wl.parallel_map(wl.mixed_batch, jobs, 2)
-    for j, p in zip(jobs, par):
-        q = wl.mixed_batch(*j)
-        for f in ("ops", "keys", "vals"):
-            assert np.array_equal(p[f], q[f])
+def test_mixed_batches_equal_one_at_a_time():
+    jobs = [dict(seed=4, batch=b, n_ops=n, universe=1 << 16, zipf_s=z)
+            for b, (n, z) in enumerate([(4096, 0.99), (0, None), (77, None), (9000, 0.99)])]
+    many = wl.mixed_batches(jobs)
+    for j, m in zip(jobs, many):
+        one = wl.mixed_batch(**j)
+        for f in ("ops", "keys", "vals", "ranks"):
+            assert np.array_equal(m[f], one[f])
+
+
+def test_mixed_batch_ranks_follow_zipf():
+    """All-insert batches (no disjointness redraws): the native sampler's
+    ranks follow the Zipf pmf (chi-square over the first ranks + the tail)."""
+    n, N = 400_000, 1000
+    r = wl.mixed_batch(21, 0, n, N, frac_insert=1.0, frac_delete=0.0)["ranks"]
+    pmf = wl.Zipf(N, 0.99).pmf(np.arange(1, N + 1))
+    head = 50
+    obs = np.concatenate([np.bincount(r, minlength=N + 1)[1:head + 1], [np.sum(r > head)]])
+    exp = np.concatenate([pmf[:head], [pmf[head:].sum()]]) * n
+    chi2 = float(((obs - exp) ** 2 / exp).sum())
+    assert chi2 < 100.0, chi2  # 50 degrees of freedom: p < 1e-4 beyond ~ 95
