@@ -39,13 +39,23 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=("bulk", "mixed", "resize", "served", "breakdown", "hashes", "gather"),
-                    default="bulk")
+    ap.add_argument("--workload", choices=("suite", "bulk", "mixed", "resize", "served", "breakdown", "hashes",
+                                           "gather"), default="suite",
+                    help="suite (default): the bulk step as the headline, with the mixed and served "
+                         "configurations as sub-records")
     ap.add_argument("--executor", choices=("plain", "persistent"), default="plain",
                     help="mixed: one launch sequence per batch, or the persistent executor")
+    ap.add_argument("--no-mixed", action="store_true", help="suite: skip the mixed sub-record")
+    ap.add_argument("--no-served", action="store_true", help="suite: skip the served sub-record")
+    ap.add_argument("--mixed-steps", type=int, default=2, help="suite: timed passes over the mixed batches")
     ap.add_argument("--tables", type=int, default=256, help="served: tables")
-    ap.add_argument("--requests", type=int, default=4000, help="served: requests")
-    ap.add_argument("--request-log2", type=float, default=16, help="served: largest request (log2 ops)")
+    ap.add_argument("--table-log2-max", type=float, default=24, help="served: largest table (log2 keys)")
+    ap.add_argument("--requests", type=int, default=20000, help="served: requests")
+    ap.add_argument("--request-log2", type=float, default=20, help="served: largest request (log2 ops)")
+    ap.add_argument("--lambda-sweep", default="0.35,0.7,1.0",
+                    help="served: Poisson rates as fractions of the plain-launch saturation rate")
+    ap.add_argument("--validate", action="store_true",
+                    help="mixed/served: also compare every output with the CPU dictionary (untimed, slow)")
     ap.add_argument("--keys-log2", type=int, default=26)
     ap.add_argument("--batches", type=int, default=64, help="mixed/resize: insert batches")
     ap.add_argument("--batch-log2", type=int, default=22, help="mixed/resize: operations per batch")
@@ -95,24 +105,36 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
-    # inputs generated in forked worker processes come first, before this
-    # process uses the GPU or runs the native generator itself
-    pre = {"mixed": gen_mixed, "served": gen_served}.get(args.workload, lambda a: None)(args)
     tuned = {}
-    if args.workload in ("mixed", "resize", "served"):
+    if args.workload in ("suite", "mixed", "resize", "served"):
         from paper_2510_15095_amd import autotune
         if args.autotune:
-            autotune.tune(args.workload)
+            autotune.tune(args.workload if args.workload != "suite" else "mixed")
         tuned = {"resize": autotune.load("resize"), "executor": autotune.load("executor")}
     if not args.resize_k:
         args.resize_k = (tuned.get("resize") or {}).get("resize_k", 1024)
     args.blocks_per_cu = (tuned.get("executor") or {}).get("blocks_per_cu", 1)
-    run = {"bulk": run_bulk, "mixed": run_mixed, "resize": run_resize, "served": run_served,
+    run = {"suite": run_suite, "bulk": run_bulk, "mixed": run_mixed, "resize": run_resize, "served": run_served,
            "breakdown": run_breakdown, "hashes": run_hashes, "gather": run_gather}[args.workload]
-    out = run(args) if pre is None else run(args, pre)
+    out = run(args)
     if tuned:
         out["autotuned"] = {k: v for k, v in tuned.items() if v}
     print(json.dumps(out), flush=True)
+
+
+def run_suite(args):
+    """The bulk step is the headline record; the mixed contended and served
+    configurations are measured after it and reported as sub-records."""
+    out = run_bulk(args)
+    print("[bench] bulk done", file=sys.stderr, flush=True)
+    if not args.no_mixed:
+        out["mixed"] = mixed_subrecord(args)
+        print("[bench] mixed done", file=sys.stderr, flush=True)
+    if not args.no_served:
+        rec = run_served(args)
+        out["served"] = {"config": rec["config"], **rec["served"], "ms_per_step": rec["ms_per_step"]}
+        print("[bench] served done", file=sys.stderr, flush=True)
+    return out
 
 
 def base_record(args, value, ms_step, workload, extra_config):
@@ -133,62 +155,60 @@ def base_record(args, value, ms_step, workload, extra_config):
     }
 
 
-def gen_mixed(args):
-    """The mixed workload's batches (host arrays, the native generator)."""
-    from paper_2510_15095_amd import workload as wl
-    n_ops, nbat = 1 << args.batch_log2, args.batches
-    ks = wl.KeyStream(3)
-    gen = wl.mixed_batches([dict(seed=3, batch=b, n_ops=n_ops, universe=1 << 26, stream=ks) for b in range(nbat)])
-    print(f"[bench] generated {nbat} mixed batches", file=sys.stderr, flush=True)
-    return [(mb["ops"], mb["keys"], mb["vals"]) for mb in gen]
+MIXED_UNIVERSE, MIXED_PRE, MIXED_NB0 = 1 << 26, 1 << 24, 1103765
 
 
-def gen_served(args):
-    """The served workload's tables and requests (generated before the GPU
-    is used)."""
-    from paper_2510_15095_amd import serve as sv
-    specs = sv.make_specs(args.tables, 5, log2_min=12, log2_max=22)
-    reqs = sv.make_requests(specs, args.requests, 5, rate=0, log2_max_size=args.request_log2)
-    print(f"[bench] {len(reqs)} requests on {len(specs)} tables generated", file=sys.stderr, flush=True)
-    return specs, reqs
-
-
-def run_mixed(args, gen):
-    """Mixed contended workload: a LINEAR table pre-filled with 2^24 keys
-    (uniform sample of a 2^26-key Zipf universe) at 95% load, then `batches`
-    batches of 2^22 operations (40% insert incl. repeats, 40% delete, 20%
-    lookup; Zipf(0.99) keys; per-batch disjoint key sets per type), each one
-    hive_mixed_batch call with dedupe; post-batch load-factor rule at 95%."""
+def mixed_setup(args):
+    """The mixed contended configuration's inputs, on the device: a 2^24-key
+    prefill (uniform sample of a 2^26-key Zipf universe) and `batches`
+    batches of 2^batch_log2 operations (40% insert incl. repeats, 40%
+    delete, 20% lookup; Zipf(0.99); per-batch disjoint key sets per type)."""
     import torch
     from paper_2510_15095_amd import hive as H
     from paper_2510_15095_amd import workload as wl
-    universe, n_pre = 1 << 26, 1 << 24
     n_ops, nbat = 1 << args.batch_log2, args.batches
-    nb0 = 1103765
     ks = wl.KeyStream(3)
-    pre_ranks = wl.DomainPerm(wl.batch_seed(3, 0xBEEF), universe).sample(n_pre)
-    pre_keys = ks.keys(pre_ranks)
+    gen = wl.mixed_batches([dict(seed=3, batch=b, n_ops=n_ops, universe=MIXED_UNIVERSE, stream=ks)
+                            for b in range(nbat)])
+    pre_keys = ks.keys(wl.DomainPerm(wl.batch_seed(3, 0xBEEF), MIXED_UNIVERSE).sample(MIXED_PRE))
     dev = torch.device("cuda:0")
-    pk = torch.from_numpy(pre_keys).to(dev)
-    pv = torch.from_numpy(wl.values_for(pre_keys)).to(dev)
-    batches = [tuple(torch.from_numpy(a).to(dev) for a in g) for g in gen]
-    del gen
-    vout = torch.empty(n_ops, dtype=torch.uint32, device=dev)
-    fout = torch.empty(n_ops, dtype=torch.uint8, device=dev)
-    t = H.Table(nb0, addressing=H.HIVE_LINEAR, max_buckets=4 * nb0, lf_expand_pct=95, post_policy=1,
-                resize_k=args.resize_k, max_batch=n_ops)
+    st = {
+        "host": gen,
+        "pre_keys": pre_keys,
+        "pk": torch.from_numpy(pre_keys).to(dev),
+        "pv": torch.from_numpy(wl.values_for(pre_keys)).to(dev),
+        "batches": [tuple(torch.from_numpy(a).to(dev) for a in (mb["ops"], mb["keys"], mb["vals"])) for mb in gen],
+        "vout": torch.empty(n_ops, dtype=torch.uint32, device=dev),
+        "fout": torch.empty(n_ops, dtype=torch.uint8, device=dev),
+        "table": H.Table(MIXED_NB0, addressing=H.HIVE_LINEAR, max_buckets=4 * MIXED_NB0, lf_expand_pct=95,
+                         post_policy=1, resize_k=args.resize_k, max_batch=n_ops),
+    }
+    print(f"[bench] mixed inputs ready: {nbat} batches of {n_ops} ops", file=sys.stderr, flush=True)
+    return st
 
-    def prefill():
-        t.clear()
-        t.insert(pk, pv, flags=H.HIVE_UNIQUE)
-        torch.cuda.synchronize()
 
-    drain = (H.hive_drain_create(16, args.blocks_per_cu, max(64, nbat), 4, 0) if args.executor == "persistent"
-             else None)
+def mixed_prefill(st):
+    import torch
+    from paper_2510_15095_amd import hive as H
+    t = st["table"]
+    t.clear()
+    t.insert(st["pk"], st["pv"], flags=H.HIVE_UNIQUE)
+    torch.cuda.synchronize()
+
+
+def mixed_time(args, st, executor, steps, warmup):
+    """Per-batch times (ms) of `steps` passes over the batches, each after a
+    fresh prefill: plain launches are timed per batch; the persistent
+    executor drains all batches in one launch (its mean per batch is
+    reported for every batch)."""
+    import torch
+    from paper_2510_15095_amd import hive as H
+    t, batches, vout, fout = st["table"], st["batches"], st["vout"], st["fout"]
+    nbat = len(batches)
+    drain = H.hive_drain_create(16, args.blocks_per_cu, max(64, nbat), 4, 0) if executor == "persistent" else None
 
     def run(evs):
         if drain is not None:
-            # every batch is queued, then one launch (a replayed graph) drains them
             evs[0].record()
             for (o, k, v) in batches:
                 H.hive_drain_submit(drain, t.h, H.HIVE_OP_MIXED, k, v, o, vout, fout)
@@ -201,81 +221,227 @@ def run_mixed(args, gen):
         evs[-1].record()
 
     mk = lambda: [torch.cuda.Event(enable_timing=True) for _ in range(nbat + 1)]  # noqa: E731
-    for _ in range(args.warmup):
-        prefill()
+    for _ in range(warmup):
+        mixed_prefill(st)
         run(mk())
     times = []
-    for step in range(args.steps):
-        prefill()
+    for step in range(steps):
+        mixed_prefill(st)
         ev = mk()
         run(ev)
         torch.cuda.synchronize()
-        print(f"[bench] mixed step {step} done", file=sys.stderr, flush=True)
+        print(f"[bench] mixed {executor} step {step} done", file=sys.stderr, flush=True)
         if drain is not None:
             times.append([ev[0].elapsed_time(ev[-1]) / nbat] * nbat)
         else:
             times.append([ev[j].elapsed_time(ev[j + 1]) for j in range(nbat)])
-    ms = np.array(times)
     if drain is not None:
         H.hive_drain_destroy(drain)
-    st = t.stats()
+    return np.array(times)
+
+
+def mixed_census(args, st):
+    """One untimed plain pass: each batch's outcomes (lookups and deletes that
+    found their key, new and replaced insert keys) and the fraction of
+    entries in their second candidate after the prefill, from which the
+    batch's algorithmic bytes follow; with --validate every output is also
+    compared with the CPU dictionary."""
+    import torch
+    from paper_2510_15095_amd import hive as H
+    from paper_2510_15095_amd import workload as wl
+    t = st["table"]
+    mixed_prefill(st)
+    first, second, overflow = t.placement()
+    f2 = second / max(1, first + second + overflow)
+    o1 = None
+    if args.validate:
+        import oracle
+        o1 = oracle.O1(1 << 25)
+        o1.insert(st["pre_keys"], wl.values_for(st["pre_keys"]))
+    live = t.stats()["live"]
+    rows, mismatches = [], 0
+    for (o, k, v), mb in zip(st["batches"], st["host"]):
+        H.hive_mixed_batch(t.h, o, k, v, st["vout"], st["fout"])
+        torch.cuda.synchronize()
+        f = st["fout"][:mb["ops"].size].cpu().numpy()
+        ops = mb["ops"]
+        if o1 is not None:
+            ov, of = o1.apply(ops, mb["keys"], mb["vals"])
+            vo = st["vout"][:ops.size].cpu().numpy()
+            mismatches += int(not (np.array_equal(f, of) and np.array_equal(vo, ov)))
+        s2 = t.stats()
+        lh = int(f[ops == wl.OP_LOOKUP].sum())
+        dh = int(f[ops == wl.OP_DELETE].sum())
+        u = int(np.unique(mb["keys"][ops == wl.OP_INSERT]).size)
+        new = s2["live"] - live + dh
+        rows.append({"n": int(ops.size), "look": int((ops == wl.OP_LOOKUP).sum()), "look_hit": lh,
+                     "del": int((ops == wl.OP_DELETE).sum()), "del_hit": dh,
+                     "ins": int((ops == wl.OP_INSERT).sum()), "ins_distinct": u, "ins_new": new,
+                     "status": s2["status"]})
+        live = s2["live"]
+    final = t.stats()
+    return {"f2": f2, "rows": rows, "mismatched_batches": mismatches if o1 is not None else None,
+            "final": {k: final[k] for k in ("live", "n_buckets", "stash_count", "pending_count", "evictions",
+                                            "evict_items", "status")}}
+
+
+def mixed_bytes(row, f2):
+    """Algorithmic bytes of one mixed batch (16-slot buckets, one touch =
+    128 B): a lookup or delete that finds its key touches 1 + f2 buckets on
+    average and a miss touches both candidates; an insert of a new key reads
+    both candidates and claims a slot (8-byte CAS); a replace reads 1 + f2
+    buckets and stores 8 bytes; a delete that finds its key stores 8 bytes;
+    every insert and delete records itself in the dedupe set (one 128-byte
+    line); every operation reads 9 B (op, key, value) and writes 5 B."""
+    hit = BUCKET_BYTES * (1 + f2)
+    miss = 2 * BUCKET_BYTES
+    look = row["look_hit"] * hit + (row["look"] - row["look_hit"]) * miss
+    dele = row["del_hit"] * (hit + 8) + (row["del"] - row["del_hit"]) * miss
+    ins = row["ins_new"] * (miss + 8) + (row["ins_distinct"] - row["ins_new"]) * (hit + 8)
+    dedupe = (row["ins"] + row["del"]) * BUCKET_BYTES
+    return look + dele + ins + dedupe + 14 * row["n"]
+
+
+def mixed_label(args):
+    return (f"mixed contended: prefill 2^24 of a 2^26-key Zipf universe at 95% load (LINEAR, {MIXED_NB0} x "
+            f"16-slot buckets, post-batch expansion at 95%), {args.batches} batches of 2^{args.batch_log2} ops "
+            f"40/40/20 insert/delete/lookup, Zipf(0.99), per-type disjoint, dedupe on")
+
+
+def run_mixed(args):
+    """The mixed contended configuration through one executor (--executor)."""
+    st = mixed_setup(args)
+    ms = mixed_time(args, st, args.executor, args.steps, args.warmup)
+    nbat, n_ops = args.batches, 1 << args.batch_log2
     ms_step = float(ms.sum(axis=1).mean())
     rec = base_record(args, nbat * n_ops / (ms_step * 1e-3) / 1e6, ms_step,
-                      f"mixed contended, {args.executor} executor: prefill 2^24 of a 2^26-key Zipf universe at 95% load "
-                      f"(LINEAR, {nb0} x 16-slot buckets), {nbat} batches of 2^{args.batch_log2} ops "
-                      f"40/40/20 insert/delete/lookup, Zipf(0.99), per-type disjoint, dedupe on",
+                      mixed_label(args) + f"; {args.executor} executor",
                       {"ops_per_step": nbat * n_ops, "batches": nbat, "resize_k": args.resize_k})
     rec["batch_ms"] = {"mean": round(float(ms.mean()), 4), "p50": round(float(np.percentile(ms, 50)), 4),
                        "p99": round(float(np.percentile(ms, 99)), 4)}
-    rec["final_stats"] = {k: st[k] for k in ("live", "n_buckets", "stash_count", "pending_count", "evictions",
-                                             "evict_items", "status")}
-    t.close()
+    if args.validate:
+        rec["census"] = mixed_census(args, st)
+    st["table"].close()
     return rec
 
 
-def run_served(args, pre):
+def mixed_subrecord(args):
+    """Both executors on the mixed configuration, with the whole-batch
+    roofline (algorithmic bytes of every batch over its time, against
+    8 TB/s)."""
+    st = mixed_setup(args)
+    steps, warmup = max(1, args.mixed_steps), 1
+    out = {"config": {"workload": mixed_label(args), "batches": args.batches,
+                      "ops_per_batch": 1 << args.batch_log2, "resize_k": args.resize_k,
+                      "persistent_blocks_per_cu": args.blocks_per_cu, "steps": steps, "warmup": warmup}}
+    times = {}
+    for ex in ("plain", "persistent"):
+        ms = mixed_time(args, st, ex, steps, warmup)
+        times[ex] = ms
+        total = ms.sum(axis=1).mean()
+        out[ex] = {"mops": round(args.batches * (1 << args.batch_log2) / (total * 1e-3) / 1e6, 1),
+                   "ms_per_batch": round(float(ms.mean()), 4),
+                   "batch_ms_p50": round(float(np.percentile(ms, 50)), 4),
+                   "batch_ms_p99": round(float(np.percentile(ms, 99)), 4)}
+    cen = mixed_census(args, st)
+    byts = np.array([mixed_bytes(r, cen["f2"]) for r in cen["rows"]])
+    for ex in ("plain", "persistent"):
+        per_batch_ms = times[ex].mean(axis=0)
+        achieved = byts.sum() / (per_batch_ms.sum() * 1e-3) / 1e9
+        out[ex]["roofline"] = {"kernel": "whole batch (all phases)", "bound": "hbm", "achieved": round(achieved, 1),
+                               "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                               "traffic": None, "algorithmic_bytes_per_batch": round(float(byts.mean()))}
+    rows = cen["rows"]
+    out["census"] = {"f2": round(cen["f2"], 4), "final": cen["final"],
+                     "per_batch_mean": {k: round(float(np.mean([r[k] for r in rows])), 1)
+                                        for k in ("look_hit", "del_hit", "ins", "ins_distinct", "ins_new")},
+                     "statuses": sorted({r["status"] for r in rows})}
+    if cen["mismatched_batches"] is not None:
+        out["census"]["batches_differing_from_dictionary"] = cen["mismatched_batches"]
+    st["table"].close()
+    return out
+
+
+def served_label(args):
+    return (f"served multi-table loop: {args.tables} LINEAR tables of 2^U(12,{args.table_log2_max:g}) keys at 85% "
+            f"load (HBM budget = reservations incl. 25% headroom), {args.requests} mixed requests (50% lookup, "
+            f"25% insert, 25% delete; uniform or Zipf(0.99) keys) of 2^U(0,{args.request_log2:g}) ops on random "
+            f"tables; persistent executor vs per-request launches on 8 streams; Poisson arrivals at "
+            f"{args.lambda_sweep} x the plain-launch saturation rate")
+
+
+def run_served(args):
     """Served multi-table loop: many LINEAR tables (log-uniform sizes,
-    created at 85% load, 25% HBM headroom each), mixed requests (50% lookup,
-    25% insert, 25% delete; uniform or Zipf(0.99) keys; log-uniform sizes)
-    aimed at random tables.  First all requests arrive at once (saturation
-    throughput of each mode), then Poisson arrivals at 70% of the slower
-    mode's saturation rate (p50/p99 latency of each mode)."""
+    created at 85% load, 25% HBM headroom each), mixed requests of
+    log-uniform sizes aimed at random tables.  First all requests arrive at
+    once (saturation throughput of each mode), then Poisson arrivals at
+    fractions of the plain-launch saturation rate (p50/p99 latency of each
+    mode)."""
     import torch
     from paper_2510_15095_amd import serve as sv
-    specs, reqs = pre
+    specs = sv.make_specs(args.tables, 5, log2_min=12, log2_max=args.table_log2_max)
+    reqs = sv.make_requests(specs, args.requests, 5, rate=0, log2_max_size=args.request_log2)
+    print(f"[bench] {len(reqs)} requests on {len(specs)} tables generated", file=sys.stderr, flush=True)
     budget = sv.footprint_bytes(specs)
-    # the executor's blocks per CU: the autotuned value when cached, else one
     srv = sv.Server(specs, budget, max_request=1 << int(np.ceil(args.request_log2)), ring=1024, streams=8,
                     blocks_per_cu=args.blocks_per_cu or 1)
     res = {}
+    validate = {}
+    expect = served_expectation(specs, reqs) if args.validate else None
     for mode in ("plain", "persistent"):
         srv.load()
         srv.run(reqs[: min(200, len(reqs))], mode)  # warm-up
         srv.load()
-        res[mode + "_saturation"] = srv.run(reqs, mode)
+        r = srv.run(reqs, mode, outputs=expect is not None, timeout_s=600)
+        if expect is not None:
+            bad = sum(not (np.array_equal(f, of) and np.array_equal(v, ov))
+                      for (v, f), (ov, of) in zip(r.pop("results"), expect))
+            validate[mode] = {"requests_differing_from_dictionary": bad}
+        res[mode + "_saturation"] = r
         print(f"[bench] served {mode} saturation run done", file=sys.stderr, flush=True)
     mean_ops = float(np.mean([r.n for r in reqs]))
-    sat_rate = min(res["plain_saturation"]["mops"], res["persistent_saturation"]["mops"]) * 1e6 / mean_ops
-    rate = 0.7 * sat_rate
-    gaps = np.random.default_rng(55).exponential(1.0 / rate, len(reqs))
-    arrivals = np.cumsum(gaps) - gaps[0]
-    for r, a in zip(reqs, arrivals):
-        r.arrival = float(a)
-    for mode in ("plain", "persistent"):
-        srv.load()
-        res[mode + "_poisson"] = srv.run(reqs, mode)
+    sat_rate = res["plain_saturation"]["mops"] * 1e6 / mean_ops
+    for frac in [float(x) for x in args.lambda_sweep.split(",") if x]:
+        rate = frac * sat_rate
+        gaps = np.random.default_rng(55).exponential(1.0 / rate, len(reqs))
+        arrivals = np.cumsum(gaps) - gaps[0]
+        for r, a in zip(reqs, arrivals):
+            r.arrival = float(a)
+        for mode in ("plain", "persistent"):
+            srv.load()
+            res[f"{mode}_poisson_{frac:g}"] = srv.run(reqs, mode, timeout_s=600)
+            res[f"{mode}_poisson_{frac:g}"]["rate_req_per_s"] = round(rate, 1)
+            print(f"[bench] served {mode} at {frac:g} x saturation done", file=sys.stderr, flush=True)
     srv.close()
     torch.cuda.synchronize()
-    p = res["persistent_poisson"]
-    rec = base_record(args, res["persistent_saturation"]["mops"], res["persistent_saturation"]["span_s"] * 1e3,
-                      f"served multi-table loop: {args.tables} LINEAR tables of 2^U(12,22) keys at 85% load "
-                      f"(HBM budget = reservations incl. 25% headroom), {args.requests} mixed requests of "
-                      f"2^U(0,{args.request_log2}) ops, persistent executor vs per-request launches on 8 streams",
+    p = res["persistent_saturation"]
+    rec = base_record(args, p["mops"], p["span_s"] * 1e3, served_label(args),
                       {"ops_per_step": p["ops"], "tables": args.tables, "requests": args.requests,
-                       "poisson_rate_req_per_s": round(rate, 1)})
+                       "mean_request_ops": round(mean_ops, 1),
+                       "plain_saturation_req_per_s": round(sat_rate, 1)})
     rec["served"] = {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                      for k, v in res.items()}
+    if validate:
+        rec["served"]["validate"] = validate
     return rec
+
+
+def served_expectation(specs, reqs):
+    """Every request's outputs from the CPU dictionary: each table's
+    requests replayed in submission order through a dictionary loaded with
+    that table's keys."""
+    import oracle
+    from paper_2510_15095_amd import workload as wl
+    dicts, out = {}, []
+    for r in reqs:
+        if r.table not in dicts:
+            sp = specs[r.table]
+            keys = wl.KeyStream(sp.seed).range(0, sp.n_keys)
+            dicts[r.table] = oracle.O1(2 * sp.n_keys)
+            dicts[r.table].insert(keys, wl.values_for(keys))
+        out.append(dicts[r.table].apply(r.ops, r.keys, r.vals))
+    print("[bench] served: dictionary answers ready", file=sys.stderr, flush=True)
+    return out
 
 
 BREAKDOWN_LF = (0.55, 0.65, 0.75, 0.85, 0.90, 0.95, 0.97)
@@ -472,6 +638,83 @@ def run_gather(args):
     return rec
 
 
+def resize_geometry(nb, live, extra, initial, max_b, K, lf_e=90):
+    """Bucket count after the expansion rule of Section IV-C (K pairs at a
+    time while live + extra exceeds lf_e% of the slots)."""
+    while (live + extra) * 100 > lf_e * nb * S and nb < max_b:
+        nb = min(nb + K, max_b)
+    return nb
+
+
+def resize_validate(args, t, keys, vals, dkeys, ks, nb0, max_b):
+    """Untimed validation of the resize cycle: after every insert and delete
+    batch the table is dumped, every stored key is mapped back to its
+    generator index and checked against a bitmap of the indices that must be
+    live (each exactly once, with its value); the geometry after each insert
+    batch equals the expansion rule's, and after each delete batch the table
+    is not over the expansion threshold and stops contracting only at its
+    initial size or at a merge pair that does not fit (Section IV-C-2)."""
+    import torch
+    from paper_2510_15095_amd import hive as H
+    from paper_2510_15095_amd import workload as wl
+    nbat, nb_ops = args.batches, 1 << args.batch_log2
+    n = nbat * nb_ops
+    n_del = dkeys.numel()
+    didx = ks.index_of(dkeys.cpu().numpy())
+    words = torch.empty(n + 1, dtype=torch.uint64, device="cuda")
+    where = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+    live_bm = np.zeros(n, bool)
+    t.clear()
+    t0 = time.perf_counter()
+    nb, failures, checks = nb0, [], 0
+
+    def check(label, want_geometry=None):
+        nonlocal checks
+        st = t.stats()
+        cnt = H.hive_dump(t.h, words, where)
+        w = words[:cnt].cpu().numpy()
+        k = (w & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+        idx = ks.index_of(k)
+        seen = np.zeros(n, bool)
+        seen[idx] = True
+        ok = (cnt == st["live"] and int(seen.sum()) == cnt and np.array_equal(seen, live_bm)
+              and np.array_equal((w >> np.uint64(32)).astype(np.uint32), wl.values_for(k)))
+        if want_geometry is not None:
+            ok = ok and st["n_buckets"] == want_geometry
+        else:
+            ok = ok and st["live"] * 100 <= 90 * st["n_buckets"] * S
+            if ok and st["live"] * 100 < 25 * st["n_buckets"] * S and st["n_buckets"] > nb0:
+                im, sp = st["index_mask"], st["split_ptr"]
+                if sp == 0:
+                    im, sp = im >> 1, (im >> 1) + 1
+                lo, hi = sp - 1, sp + im
+                wh = where[:cnt].cpu().numpy()
+                ok = int((wh == hi).sum()) > S - int((wh == lo).sum())
+        checks += 1
+        if not ok:
+            failures.append(label)
+        return st
+
+    for b in range(nbat):
+        st0 = t.stats()
+        want = resize_geometry(st0["n_buckets"], st0["live"], nb_ops, nb0, max_b, args.resize_k)
+        t.insert(keys[b * nb_ops:(b + 1) * nb_ops], vals[b * nb_ops:(b + 1) * nb_ops], flags=H.HIVE_UNIQUE)
+        live_bm[b * nb_ops:(b + 1) * nb_ops] = True
+        want = resize_geometry(want, (b + 1) * nb_ops, 0, nb0, max_b, args.resize_k)
+        check(f"insert batch {b}", want)
+        print(f"[bench] resize validation: insert batch {b} checked", file=sys.stderr, flush=True)
+    dout = torch.empty(nb_ops, dtype=torch.uint8, device="cuda")
+    for b in range((n_del + nb_ops - 1) // nb_ops):
+        lo_, hi_ = b * nb_ops, min(n_del, (b + 1) * nb_ops)
+        H.hive_delete_batch(t.h, dkeys[lo_:hi_], dout[:hi_ - lo_], H.HIVE_UNIQUE)
+        if not bool(dout[:hi_ - lo_].all()):
+            failures.append(f"delete batch {b}: a delete missed its key")
+        live_bm[didx[lo_:hi_]] = False
+        check(f"delete batch {b}")
+        print(f"[bench] resize validation: delete batch {b} checked", file=sys.stderr, flush=True)
+    return {"batches_checked": checks, "failures": failures, "seconds": round(time.perf_counter() - t0, 1)}
+
+
 def run_resize(args):
     """Dynamic resize cycle: a LINEAR table of 2^16 buckets (2^20 slots)
     takes `batches` batches of 2^22 unique uniform inserts with pre-batch
@@ -497,6 +740,7 @@ def run_resize(args):
                 lf_contract_pct=25, resize_k=args.resize_k, max_batch=nb_ops)
     dout = torch.empty(nb_ops, dtype=torch.uint8, device=dev)
     n_del_batches = (n_del + nb_ops - 1) // nb_ops
+    validation = resize_validate(args, t, keys, vals, dkeys, ks, nb0, max_b) if args.validate else None
 
     def run(ev):
         t.clear()
@@ -535,6 +779,8 @@ def run_resize(args):
                          "delete_with_contraction": round(n_del / (ms[:, 1].mean() * 1e-3) / 1e6, 1)}
     rec["peak_buckets"] = peak
     rec["final_stats"] = {k: st[k] for k in ("live", "n_buckets", "stash_count", "pending_count", "status")}
+    if validation is not None:
+        rec["validation"] = validation
     t.close()
     return rec
 

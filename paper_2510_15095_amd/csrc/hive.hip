@@ -558,8 +558,12 @@ __device__ __forceinline__ void ops_tile(const OpsArgs &a, const OpsView &view, 
       // claims only fill EMPTY slots, and a batch gives each key one such
       // operation), so that CAS cannot fail and one 64-bit store does the
       // same: the whole entry is replaced at once and nothing waits for an
-      // atomic's return.
-      *slot = (op == OP_INSERT) ? kv : EMPTY;
+      // atomic's return.  The store is an agent-scope atomic one: claims of
+      // other XCDs change the same bucket lines in this phase, and a plain
+      // store leaves the line dirty in this XCD's L2, whose write-back
+      // carries this XCD's stale copy of the neighbouring slots and
+      // overwrote such claims (keys inserted by a mixed batch went missing).
+      __hip_atomic_store(slot, (op == OP_INSERT) ? kv : EMPTY, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (op == OP_DELETE) {
         out_f = 1;
         dl = -1;
@@ -668,23 +672,32 @@ __device__ __forceinline__ void set_hint(uint32_t *hint, uint32_t b) { or32(&hin
 // is full.  Room is reserved by a fetch-add on the count, one per wave for
 // all of its pushes (the counts may pass their capacities; every reader
 // clamps them); given its reserved position c (c >= capacity: pending), the
-// entry claims the first EMPTY word of its probe run by CAS (one exists: the
-// table has at least twice the capacity).  Returns where it went: 0 stash,
-// 1 pending, 2 lost (the pending list was full too; latched as an error).
+// entry claims the first EMPTY or TOMB word of its probe run by CAS (an
+// EMPTY one exists: the table has at least twice the capacity).  A TOMB word
+// is reused: it already counts as used, and searches pass it, so the entry
+// is found at the first free word of its run either way (no key is stashed
+// twice: items here are keys absent from the table, and a word taken by
+// another placement meanwhile holds a live entry).  Returns where it went:
+// 0 stash (an EMPTY word), 3 stash (a TOMB word), 1 pending, 2 lost (the
+// pending list was full too; latched as an error).
 template <int PAIR = PAIR_BITHASH>
 __device__ __forceinline__ int overflow_place(const EvictArgs &a, const Geo &geo, uint64_t kv, uint64_t c) {
-  bool stashed = false;
+  int where = -1;
   if (c < a.stash_cap) {
     const uint64_t mask = stash_slots_for(a.stash_cap) - 1;
     for (uint64_t i = 0, p = mix32(key_of(kv)) & mask; i <= mask; ++i, p = (p + 1) & mask) {
-      if (cas64(a.stash + p, EMPTY, kv) == EMPTY) {
-        stashed = true;
+      const uint64_t cur = cas64(a.stash + p, EMPTY, kv);
+      if (cur == EMPTY) {
+        where = 0;
+        break;
+      }
+      if (cur == TOMB && cas64(a.stash + p, TOMB, kv) == TOMB) {
+        where = 3;
         break;
       }
     }
   }
-  int where = 0;
-  if (!stashed) {
+  if (where < 0) {
     const uint64_t p = add64(&a.ctl->pending_count, 1);
     if (p < a.pending_cap) {
       __hip_atomic_store(a.pending + p, kv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -903,7 +916,7 @@ __device__ __forceinline__ bool evict_chain(const EvictArgs &a, const Geo &geo, 
 template <int S, int PAIR = PAIR_BITHASH>
 __device__ __forceinline__ void evict_round(const EvictArgs &a, const Geo &geo, bool unreserved, bool have,
                                             uint64_t pos, int g, int sl, uint64_t &n_evict, uint64_t &n_full,
-                                            uint64_t &n_side) {
+                                            uint64_t &n_side, uint64_t &n_fresh) {
   uint64_t kv = 0;
   bool placed = true;
   if (have) {
@@ -926,7 +939,8 @@ __device__ __forceinline__ void evict_round(const EvictArgs &a, const Geo &geo, 
     if (push) {
       ++n_full;
       const int where = overflow_place<PAIR>(a, geo, kv, base + rank_below(pm));
-      n_side += where == 0 ? 1 : where == 1 ? (1ull << 32) : 0;
+      n_side += (where == 0 || where == 3) ? 1 : where == 1 ? (1ull << 32) : 0;
+      n_fresh += where == 0;
     }
   }
 }
@@ -934,16 +948,19 @@ __device__ __forceinline__ void evict_round(const EvictArgs &a, const Geo &geo, 
 // Chain statistics of a wave (per group, held by its lane 0) added to the
 // wave's shard.  Every lane of the wave calls it.  n_side counts the lane's
 // stash placements in its low half and pending ones in its high half (a
-// wave places far fewer than 2^32 entries).
+// wave places far fewer than 2^32 entries); n_fresh counts the stash
+// placements that took an EMPTY word, the ones that add a used word to the
+// count (when the launch reserved no room, they are added after it).
 __device__ __forceinline__ void evict_counters(const EvictArgs &a, bool unreserved, uint64_t unit, uint64_t n_evict,
-                                               uint64_t n_full, uint64_t n_side, int sl) {
+                                               uint64_t n_full, uint64_t n_side, uint64_t n_fresh, int sl) {
   const uint64_t e = wave_sum64(sl == 0 ? n_evict : 0), f = wave_sum64(n_full), sd = wave_sum64(n_side);
+  const uint64_t fr = wave_sum64(n_fresh);
   if ((threadIdx.x & 63) == 0 && (e | f)) {
     Shard *sh = shard_of(a.ctl, unit % NSHARD);
     if (e) add64(&sh->evictions, e);
     if (f) add64(&sh->full_chains, f);
     if ((uint32_t)sd) add64(&sh->stash_inserts, (uint32_t)sd);
-    if ((uint32_t)sd && unreserved) add64(&sh->stash_unreserved, (uint32_t)sd);
+    if (fr && unreserved) add64(&sh->stash_unreserved, fr);
     if (sd >> 32) add64(&sh->pending_inserts, sd >> 32);
   }
 }
@@ -967,16 +984,16 @@ __global__ __launch_bounds__(BLOCK) void evict_kernel(EvictArgs a) {
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = lane / E::L, sl = lane % E::L;
   const uint64_t groups = (uint64_t)gridDim.x * WAVES * E::G;
-  uint64_t n_evict = 0, n_full = 0, n_side = 0;
+  uint64_t n_evict = 0, n_full = 0, n_side = 0, n_fresh = 0;
   const uint64_t first = ((uint64_t)blockIdx.x * WAVES + wv) * E::G + g;
   // a uniform trip count per wave: every lane reaches the wave-wide steps
   const uint64_t wave_first = ((uint64_t)blockIdx.x * WAVES + wv) * E::G;
   for (uint64_t base = wave_first; base < cnt; base += groups) {
     const uint64_t t = base - wave_first + first;
     evict_round<S, PAIR>(a, geo, unreserved, t < cnt, t < cnt ? wl_slot(pre, t, a.wl_seg_cap) : 0, g, sl, n_evict,
-                         n_full, n_side);
+                         n_full, n_side, n_fresh);
   }
-  evict_counters(a, unreserved, (uint64_t)blockIdx.x * WAVES + wv, n_evict, n_full, n_side, sl);
+  evict_counters(a, unreserved, (uint64_t)blockIdx.x * WAVES + wv, n_evict, n_full, n_side, n_fresh, sl);
 }
 
 // ---------------------------------------------------------------------------
@@ -1909,12 +1926,12 @@ __device__ __forceinline__ void run_chunk(ReqState *r, const ReqDesc &d, uint32_
       const uint64_t items = pre[NSHARD];
       const int eg = lane / E::L, esl = lane % E::L;
       const uint64_t egpb = (uint64_t)WAVES * E::G, egib = (uint64_t)wv * E::G + eg;
-      uint64_t n_evict = 0, n_full = 0, n_side = 0;
+      uint64_t n_evict = 0, n_full = 0, n_side = 0, n_fresh = 0;
       const uint64_t t = c * egpb + egib;
       const bool unreserved = ld_ctl(&d.t.ctl->stash_count) + items <= d.t.stash_cap;
       evict_round<S>(ea, geo, unreserved, t < items, t < items ? wl_slot(pre, t, d.t.wl_seg_cap) : 0, eg, esl, n_evict,
-                     n_full, n_side);
-      evict_counters(ea, unreserved, c * WAVES + wv, n_evict, n_full, n_side, esl);
+                     n_full, n_side, n_fresh);
+      evict_counters(ea, unreserved, c * WAVES + wv, n_evict, n_full, n_side, n_fresh, esl);
       break;
     }
     case PH_OPS: {
@@ -2475,6 +2492,7 @@ static hive_status run_batch(hive_t h, uint32_t mode, const uint8_t *d_ops, cons
   const uint64_t wl_need = (mode == OP_INSERT || mode == OP_MIXED) ? n : 0;
   hive_status s = ensure_scratch(h, wl_need, dedupe ? n : 0, st);
   if (s != HIVE_OK) return s;
+  uint64_t *dd = h->d_dd;
   OpsArgs a{};
   a.buckets = h->d_buckets;
   a.hint = h->d_hint;
@@ -2494,11 +2512,11 @@ static hive_status run_batch(hive_t h, uint32_t mode, const uint8_t *d_ops, cons
   if (dedupe) {
     phase_mark(h, HIVE_PHASE_DEDUPE, st);
     const uint64_t cap = dd_words_for(n);  // within dd_cap: ensure_scratch sized it from n
-    if ((s = fill_u64(h->d_dd, cap, EMPTY, st)) != HIVE_OK) return s;
-    hipLaunchKernelGGL(dedupe_build_kernel, dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, st, h->d_dd,
+    if ((s = fill_u64(dd, cap, EMPTY, st)) != HIVE_OK) return s;
+    hipLaunchKernelGGL(dedupe_build_kernel, dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, st, dd,
                        cap - 1, mode, d_ops, d_keys, n);
     if ((s = launch_check()) != HIVE_OK) return s;
-    a.dd = h->d_dd;
+    a.dd = dd;
     a.dd_mask = cap - 1;
   }
   const bool linear = h->cfg.addressing == HIVE_LINEAR;

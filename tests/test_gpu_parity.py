@@ -184,6 +184,41 @@ def test_dedupe_last_insert_wins_first_delete_reports(H):
     t.close()
 
 
+@pytest.mark.parametrize("path", ["plain", "persistent"])
+def test_dedupe_delete_batch_sized_from_the_batch(H, path):
+    """A delete batch with repeats (no HIVE_UNIQUE) on a table whose scratch
+    was never grown by a deduped insert (max_batch = 0, inserts with
+    HIVE_UNIQUE): the dedupe set must be sized from the whole batch, which
+    sends nothing to the eviction worklist."""
+    import torch
+    rng = np.random.default_rng(19)
+    keys = wl.KeyStream(19).range(0, 12000)
+    t = H.Table(2048)
+    o = oracle.O1()
+    t.insert(dev(keys), dev(wl.values_for(keys)), flags=H.HIVE_UNIQUE)
+    o.insert(keys, wl.values_for(keys))
+    dkeys = np.concatenate([keys[rng.integers(0, keys.size, 15000)], wl.KeyStream(20).range(0, 3000)])
+    case(f"dedupe-sized delete batch of {dkeys.size}, {path}")
+    if path == "plain":
+        d = host(t.delete(dev(dkeys)))
+    else:
+        dr = H.hive_drain_create(16, 1, 16, 2, 10_000_000)
+        k_ = dev(dkeys)
+        fo = torch.full((dkeys.size,), 9, dtype=torch.uint8, device="cuda")
+        vo = torch.empty(dkeys.size, dtype=torch.uint32, device="cuda")
+        tk = H.hive_drain_submit(dr, t.h, H.HIVE_OP_DELETE, k_, None, None, vo, fo)
+        H.hive_drain_launch(dr, 0)
+        torch.cuda.synchronize()
+        assert H.hive_drain_poll(dr, tk)
+        d = host(fo)
+        H.hive_drain_destroy(dr)
+    assert np.array_equal(d, o.delete(dkeys))
+    st = t.stats()
+    assert st["status"] == H.HIVE_OK and st["live"] == len(o)
+    assert np.array_equal(t.dump(), o.dump())
+    t.close()
+
+
 @pytest.mark.parametrize("E,stash,lf", [(8, 1024, 0.97), (2, 64, 0.99), (1, 8, 0.995), (0, 4, 0.99)])
 def test_eviction_stash_pending_heavy(H, E, stash, lf):
     """Small tables near capacity: eviction chains, the stash and the pending
@@ -219,6 +254,47 @@ def test_eviction_stash_pending_heavy(H, E, stash, lf):
     o.insert(keys[::2], v2[::2])
     dk = keys[1::3]
     assert np.array_equal(host(t.delete(dev(dk), flags=H.HIVE_UNIQUE)), o.delete(dk))
+    v, f = t.lookup(dev(q))
+    ov, of = o.lookup(q)
+    assert np.array_equal(host(f), of) and np.array_equal(host(v), ov)
+    assert np.array_equal(t.dump(), o.dump())
+    t.close()
+
+
+def test_stash_churn_reuses_deleted_words(H):
+    """Insert/delete churn on a FIXED table at 97% load: deleted stash
+    entries leave TOMB words, which later placements reuse, so the stash's
+    used words (TOMB included) stay below the number of entries it has
+    taken; every round matches the dictionary."""
+    S, nb, cap = 16, 512, 4096
+    n = int(S * nb * 0.97)
+    ks = wl.KeyStream(44)
+    t = H.Table(nb, max_evictions=2, stash_capacity=cap, pending_capacity=cap)
+    o = oracle.O1()
+    keys = ks.range(0, n)
+    t.insert(dev(keys), dev(wl.values_for(keys)), flags=H.HIVE_UNIQUE)
+    o.insert(keys, wl.values_for(keys))
+    rng = np.random.default_rng(44)
+    present = list(keys)
+    nxt = n
+    for r in range(40):
+        case(f"stash churn round {r}")
+        pick = rng.choice(len(present), 200, replace=False)
+        dk = np.array([present[i] for i in pick], np.uint32)
+        for i in sorted(pick.tolist(), reverse=True):
+            present[i] = present[-1]
+            present.pop()
+        assert np.array_equal(host(t.delete(dev(dk), flags=H.HIVE_UNIQUE)), o.delete(dk))
+        ik = ks.range(nxt, nxt + 200)
+        nxt += 200
+        present += list(ik)
+        t.insert(dev(ik), dev(wl.values_for(ik)), flags=H.HIVE_UNIQUE)
+        o.insert(ik, wl.values_for(ik))
+        st = t.stats()
+        assert st["status"] in (H.HIVE_OK, H.HIVE_WARN_PENDING), st
+        assert st["live"] == len(o) and st["stash_count"] <= cap
+    assert st["stash_count"] < st["stash_inserts"], st
+    q = ks.range(0, nxt + 100)
     v, f = t.lookup(dev(q))
     ov, of = o.lookup(q)
     assert np.array_equal(host(f), of) and np.array_equal(host(v), ov)
@@ -809,33 +885,52 @@ _SERVED = {}
 
 
 def _served_setup():
-    """Specs and requests are generated before any GPU work of this module's
-    serving tests (the generator forks worker processes)."""
+    """Tables, requests and the dictionary's answers, made once: 32 LINEAR
+    tables of 2^U(12,18) keys at 85% load, 2,000 mixed requests (50% lookup,
+    25% insert, 25% delete, uniform or Zipf keys) of 2^U(0,16) operations on
+    random tables.  The expected outputs replay each table's requests, in
+    submission order, through a dictionary loaded with that table's keys."""
     if not _SERVED:
         from paper_2510_15095_amd import serve as sv
-        specs = sv.make_specs(12, 9, log2_min=10, log2_max=14)
-        reqs = sv.make_requests(specs, 300, 9, rate=20000.0, log2_max_size=11, workers=0)
-        _SERVED.update(specs=specs, reqs=reqs)
-    return _SERVED["specs"], _SERVED["reqs"]
+        specs = sv.make_specs(32, 9, log2_min=12, log2_max=18)
+        reqs = sv.make_requests(specs, 2000, 9, rate=20000.0, log2_max_size=16)
+        dicts, expect = {}, []
+        for r in reqs:
+            if r.table not in dicts:
+                sp = specs[r.table]
+                keys = wl.KeyStream(sp.seed).range(0, sp.n_keys)
+                dicts[r.table] = oracle.O1(2 * sp.n_keys)
+                dicts[r.table].insert(keys, wl.values_for(keys))
+            expect.append(dicts[r.table].apply(r.ops, r.keys, r.vals))
+        _SERVED.update(specs=specs, reqs=reqs, expect=expect,
+                       final={t: o.dump() for t, o in dicts.items()})
+    return _SERVED
 
 
 @pytest.mark.parametrize("bpc", [1, 0])  # the server's default, then full occupancy
-def test_served_results_same_alone_and_in_the_mix(H, bpc):
-    """Each request's outputs are the same whether it runs alone (one at a
-    time, in submission order) or in the mix served by the persistent
-    executor or by plain per-request launches on several streams."""
+def test_served_results_equal_the_dictionary_alone_and_in_the_mix(H, bpc):
+    """Each request's outputs equal the dictionary's, whether it runs alone
+    (one at a time, in submission order) or in the mix served by the
+    persistent executor or by plain per-request launches on several streams;
+    after each run every table holds the dictionary's final contents."""
     from paper_2510_15095_amd import serve as sv
-    specs, reqs = _served_setup()
-    srv = sv.Server(specs, 2 * sv.footprint_bytes(specs), max_request=1 << 11, ring=64, streams=4,
+    d = _served_setup()
+    specs, reqs, expect = d["specs"], d["reqs"], d["expect"]
+    srv = sv.Server(specs, 2 * sv.footprint_bytes(specs), max_request=1 << 16, ring=256, streams=4,
                     blocks_per_cu=bpc)
-    case("served: alone")
-    srv.load()
-    alone = srv.run_alone(reqs)
-    for mode in ("persistent", "plain"):
+    runs = []
+    for mode in ("alone", "persistent", "plain"):
         case(f"served: {mode}, {bpc} blocks per CU")
         srv.load()
-        res = srv.run(reqs, mode, outputs=True, timeout_s=60)
-        for i, ((v1, f1), (v2, f2)) in enumerate(zip(alone, res["results"])):
-            assert np.array_equal(f1, f2) and np.array_equal(v1, v2), f"{mode}: request {i} differs"
-        print(mode, {k: v for k, v in res.items() if k != "results"})
+        if mode == "alone":
+            runs.append((mode, srv.run_alone(reqs)))
+        else:
+            res = srv.run(reqs, mode, outputs=True, timeout_s=120)
+            print(mode, {k: v for k, v in res.items() if k != "results"})
+            runs.append((mode, res["results"]))
+        for t, words in d["final"].items():
+            assert np.array_equal(srv.tables[t].dump(), words), f"{mode}: table {t} contents differ"
+    for mode, results in runs:
+        for i, ((v, f), (ov, of)) in enumerate(zip(results, expect)):
+            assert np.array_equal(f, of) and np.array_equal(v, ov), f"{mode}: request {i} differs"
     srv.close()
