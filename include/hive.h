@@ -164,6 +164,24 @@ hive_status hive_mixed_batch(hive_t h, const uint8_t *d_ops, const uint32_t *d_k
                              uint64_t n, uint32_t flags, uint32_t *d_vals_out, uint8_t *d_flags_out,
                              void *stream);
 
+/* hive_mixed_batch for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same operation, outputs and contract, with no hipMalloc,
+ * hipFree or other allocating call.  The batch's dedupe set (needed unless
+ * `flags` has HIVE_UNIQUE) lives in a 64 MiB array of device memory that the
+ * library holds on each GPU it runs on until the process ends, so with
+ * dedupe a call takes at most 2^22 operations; the eviction worklist is the
+ * table's own, preallocated at create, so n may not exceed
+ * max(hive_config.max_batch, the table's stash + pending capacity).  Beyond
+ * either limit the call returns HIVE_ERR_BUDGET (with a line on stderr) and
+ * enqueues nothing.  Every call on one GPU shares that GPU's array: calls
+ * whose work overlaps on the device (other streams, other host threads, other
+ * tables) race on it and must be ordered by the caller.  Phase timing
+ * (hive_phase_timing) is not recorded for these calls. */
+hive_status hive_mixed_batch_noalloc(hive_t h, const uint8_t *d_ops, const uint32_t *d_keys,
+                                     const uint32_t *d_vals, uint64_t n, uint32_t flags, uint32_t *d_vals_out,
+                                     uint8_t *d_flags_out, void *stream);
+
 /* Linear-hashing resize (Section IV-C), LINEAR tables only.
  * delta > 0: split up to delta buckets, K at a time (Section IV-C-1), then
  * re-insert the stash and pending entries; delta < 0: merge up to -delta

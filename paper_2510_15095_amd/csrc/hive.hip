@@ -34,6 +34,7 @@
 #include <cstddef>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <thread>
 #include <type_traits>
@@ -2476,23 +2477,83 @@ static void launch_drain_any(hive_drain *d, int mode, hipStream_t st) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Scratch for callers that cannot allocate (hive_mixed_batch_noalloc): the
+// dedupe set of one batch lives in this array instead of the table's
+// grow-on-demand buffer.  Each GPU holds its own copy for the life of the
+// process; host code reaches it only through the per-device address that
+// hipGetSymbolAddress returns (the array's name is a host-side stand-in).
+// ---------------------------------------------------------------------------
+constexpr uint64_t NOALLOC_DD_WORDS = 1ull << 23;           // 64 MiB
+constexpr uint64_t NOALLOC_MAX_BATCH = NOALLOC_DD_WORDS / 2;  // dd_words_for(n) <= NOALLOC_DD_WORDS
+static __device__ __align__(256) uint64_t scratch[NOALLOC_DD_WORDS];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static uint64_t *g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// The current device's copy of `scratch`, looked up once per device.
+static hive_status noalloc_scratch(uint64_t **out) {
+  int dev = 0;
+  HIP_OK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return HIVE_ERR_HIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    HIP_OK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[dev] = (uint64_t *)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return HIVE_OK;
+}
+
+// no_alloc: take the dedupe set from `scratch` and refuse a batch that would
+// grow the table's worklist, so that the call allocates nothing; phase
+// timing (which creates events) is skipped for such a call.
 static hive_status run_batch(hive_t h, uint32_t mode, const uint8_t *d_ops, const uint32_t *d_keys,
                              const uint32_t *d_vals, uint64_t n, uint32_t flags, uint32_t *d_vals_out,
-                             uint8_t *d_flags_out, void *stream) {
+                             uint8_t *d_flags_out, void *stream, bool no_alloc = false) {
   if (!h || (n > 0 && !d_keys)) return HIVE_ERR_ARG;
   if (n >= 0xFFFFFFFFull) return HIVE_ERR_ARG;  // batch indices are 32-bit in the dedupe set
   if (mode == OP_INSERT && n > 0 && !d_vals) return HIVE_ERR_ARG;
   if (mode == OP_MIXED && n > 0 && !d_ops) return HIVE_ERR_ARG;
   if (flags & ~(uint32_t)HIVE_UNIQUE) return HIVE_ERR_ARG;
   hipStream_t st = (hipStream_t)stream;
-  h->last = st;
-  if (n == 0) return HIVE_OK;
   const bool dedupe = !(flags & HIVE_UNIQUE) && mode != OP_LOOKUP;
   // only inserts reach the eviction worklist
   const uint64_t wl_need = (mode == OP_INSERT || mode == OP_MIXED) ? n : 0;
-  hive_status s = ensure_scratch(h, wl_need, dedupe ? n : 0, st);
-  if (s != HIVE_OK) return s;
-  uint64_t *dd = h->d_dd;
+  uint64_t *dd = nullptr;
+  if (no_alloc) {
+    if (wl_need > h->wl_cap) {
+      fprintf(stderr, "hive: a batch of %llu operations needs a larger worklist than the table's (%llu); "
+              "create the table with max_batch >= n for allocation-free calls\n",
+              (unsigned long long)n, (unsigned long long)h->wl_cap);
+      return HIVE_ERR_BUDGET;
+    }
+    if (dedupe && n > NOALLOC_MAX_BATCH) {
+      fprintf(stderr, "hive: allocation-free batches with dedupe hold at most %llu operations (got %llu)\n",
+              (unsigned long long)NOALLOC_MAX_BATCH, (unsigned long long)n);
+      return HIVE_ERR_BUDGET;
+    }
+    if (dedupe) {
+      hive_status s = noalloc_scratch(&dd);
+      if (s != HIVE_OK) return s;
+    }
+  }
+  h->last = st;
+  if (n == 0) return HIVE_OK;
+  hive_status s = HIVE_OK;
+  if (!no_alloc) {
+    if ((s = ensure_scratch(h, wl_need, dedupe ? n : 0, st)) != HIVE_OK) return s;
+    dd = h->d_dd;
+  }
+  // phase timing creates events on demand: off for an allocation-free call
+  struct TimingOff {
+    hive_table *h;
+    bool was;
+    ~TimingOff() { h->timing = was; }
+  } timing_guard{h, h->timing};
+  if (no_alloc) h->timing = false;
   OpsArgs a{};
   a.buckets = h->d_buckets;
   a.hint = h->d_hint;
@@ -2511,7 +2572,9 @@ static hive_status run_batch(hive_t h, uint32_t mode, const uint8_t *d_ops, cons
   a.pending_cap = h->pending_cap;
   if (dedupe) {
     phase_mark(h, HIVE_PHASE_DEDUPE, st);
-    const uint64_t cap = dd_words_for(n);  // within dd_cap: ensure_scratch sized it from n
+    // within the buffer: ensure_scratch sized the table's from n, and the
+    // allocation-free path checked n against NOALLOC_MAX_BATCH
+    const uint64_t cap = dd_words_for(n);
     if ((s = fill_u64(dd, cap, EMPTY, st)) != HIVE_OK) return s;
     hipLaunchKernelGGL(dedupe_build_kernel, dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, st, dd,
                        cap - 1, mode, d_ops, d_keys, n);
@@ -2688,6 +2751,13 @@ hive_status hive_mixed_batch(hive_t h, const uint8_t *d_ops, const uint32_t *d_k
                              uint64_t n, uint32_t flags, uint32_t *d_vals_out, uint8_t *d_flags_out, void *stream) {
   if (h && n > 0 && !d_vals) return HIVE_ERR_ARG;  // inserts read their values
   return run_batch(h, OP_MIXED, d_ops, d_keys, d_vals, n, flags, d_vals_out, d_flags_out, stream);
+}
+
+hive_status hive_mixed_batch_noalloc(hive_t h, const uint8_t *d_ops, const uint32_t *d_keys, const uint32_t *d_vals,
+                                     uint64_t n, uint32_t flags, uint32_t *d_vals_out, uint8_t *d_flags_out,
+                                     void *stream) {
+  if (h && n > 0 && !d_vals) return HIVE_ERR_ARG;
+  return run_batch(h, OP_MIXED, d_ops, d_keys, d_vals, n, flags, d_vals_out, d_flags_out, stream, true);
 }
 
 hive_status hive_resize(hive_t h, int64_t delta, void *stream) {

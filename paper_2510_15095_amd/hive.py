@@ -98,6 +98,7 @@ def _load():
         "hive_lookup_batch": ([p, p, u64, p, p, p], st),
         "hive_delete_batch": ([p, p, u64, u32, p, p], st),
         "hive_mixed_batch": ([p, p, p, p, u64, u32, p, p, p], st),
+        "hive_mixed_batch_noalloc": ([p, p, p, p, u64, u32, p, p, p], st),
         "hive_resize": ([p, i64, p], st),
         "hive_stats": ([p, ctypes.POINTER(hive_stats_t), p], st),
         "hive_dump": ([p, p, p, u64, ctypes.POINTER(u64), p], st),
@@ -220,6 +221,17 @@ def hive_mixed_batch(h, ops, keys, vals, vals_out=None, flags_out=None, flags: i
                                  _dev(vals_out, torch.uint32, "vals_out", n, optional=True),
                                  _dev(flags_out, torch.uint8, "flags_out", n, optional=True),
                                  _stream_ptr(stream)), "hive_mixed_batch")
+
+
+def hive_mixed_batch_noalloc(h, ops, keys, vals, vals_out=None, flags_out=None, flags: int = 0,
+                             stream=None) -> None:
+    import torch
+    n = keys.numel()
+    _check(_lib.hive_mixed_batch_noalloc(h, _dev(ops, torch.uint8, "ops", n), _dev(keys, torch.uint32, "keys"),
+                                         _dev(vals, torch.uint32, "vals", n), n, flags,
+                                         _dev(vals_out, torch.uint32, "vals_out", n, optional=True),
+                                         _dev(flags_out, torch.uint8, "flags_out", n, optional=True),
+                                         _stream_ptr(stream)), "hive_mixed_batch_noalloc")
 
 
 def hive_resize(h, delta: int, stream=None) -> None:
