@@ -95,8 +95,11 @@ def cpu_baseline(log2n: int) -> dict:
     o.lookup(w["query_keys"])
     dt = time.perf_counter() - t0
     ops = 3.5 * n
+    host_cores = os.cpu_count()
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else host_cores
     return {"value": round(ops / dt / 1e6, 3), "unit": "Mops/s", "cores": 1, "kind": "oracle",
-            "sample": f"same sequence at 2^{log2n} keys ({nb} buckets, 95% load), {dt:.1f} s single-threaded"}
+            "sample": f"same sequence at 2^{log2n} keys ({nb} buckets, 95% load), {dt:.1f} s single-threaded",
+            "host_cores": host_cores, "host_cores_usable": usable}
 
 
 def main():
