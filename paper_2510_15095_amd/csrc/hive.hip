@@ -208,15 +208,11 @@ __global__ __launch_bounds__(BLOCK) void fill_u32_kernel(uint32_t *p, uint64_t n
   for (uint64_t t = (uint64_t)blockIdx.x * BLOCK + threadIdx.x; t < n; t += (uint64_t)gridDim.x * BLOCK) p[t] = v;
 }
 
-// Record operation i (of type `op`) in the set.  Plain loads come first:
-// a key already present costs no CAS, and an index that cannot win costs no
-// max/min atomic (a stale load is only ever an older value, which would
-// already beat i, so the skip is safe).
-__device__ __forceinline__ void dedupe_insert(uint64_t *dd, uint64_t mask, uint32_t op, const uint32_t *keys,
-                                              uint64_t i) {
-  const uint32_t k = keys[i];
-  if (!valid_key(k)) return;
-  const uint64_t e = ((uint64_t)k << 32) | (uint32_t)i;
+// Record entry e = (k << 32 | index) of an operation of type `op` in the
+// set.  Plain loads come first: a key already present costs no CAS, and an
+// index that cannot win costs no max/min atomic (a stale load is only ever
+// an older value, which would already beat the index, so the skip is safe).
+__device__ __forceinline__ void dedupe_record(uint64_t *dd, uint64_t mask, uint32_t op, uint32_t k, uint64_t e) {
   uint64_t s = mix32(k) & mask;
   for (uint64_t probe = 0; probe <= mask; ++probe) {
     uint64_t cur = dd[s];
@@ -236,6 +232,12 @@ __device__ __forceinline__ void dedupe_insert(uint64_t *dd, uint64_t mask, uint3
   }
 }
 
+__device__ __forceinline__ void dedupe_insert(uint64_t *dd, uint64_t mask, uint32_t op, const uint32_t *keys,
+                                              uint64_t i) {
+  const uint32_t k = keys[i];
+  if (valid_key(k)) dedupe_record(dd, mask, op, k, ((uint64_t)k << 32) | (uint32_t)i);
+}
+
 // Thread t records operation n-1-t if it is an insert and operation t if it
 // is a delete: blocks start roughly in order, so inserts arrive in falling
 // index order (the winner, the last, comes first) and deletes in rising
@@ -249,9 +251,74 @@ __device__ __forceinline__ void dedupe_thread(uint64_t *dd, uint64_t mask, uint3
   if (mode == OP_DELETE || (mode == OP_MIXED && ops[t] == OP_DELETE)) dedupe_insert(dd, mask, OP_DELETE, keys, t);
 }
 
+// The plain path's build collapses repeated keys in LDS first: a block takes
+// a chunk of DD_CHUNK operations of one type (inserts or deletes), keeps per
+// key the largest insert index or the smallest delete index in an LDS table
+// of twice the chunk's size, then records each distinct key of the chunk in
+// the set once.  A hot key (the first Zipf(0.99) rank is about 5% of the
+// operations) then costs one global atomic per chunk instead of one per
+// occurrence.  Insert chunks are taken from the end of the batch down,
+// delete chunks from the start up, so that the winning occurrence of a key
+// tends to be recorded first and the other chunks' records skip their
+// atomics (as in dedupe_thread).
+constexpr int DD_PER_THREAD = 8;
+constexpr uint64_t DD_CHUNK = (uint64_t)BLOCK * DD_PER_THREAD;
+constexpr int DD_LDS = 2 * (int)DD_CHUNK;
+
 __global__ __launch_bounds__(BLOCK) void dedupe_build_kernel(uint64_t *dd, uint64_t mask, uint32_t mode,
                                                              const uint8_t *ops, const uint32_t *keys, uint64_t n) {
-  dedupe_thread(dd, mask, mode, ops, keys, n, (uint64_t)blockIdx.x * BLOCK + threadIdx.x);
+  __shared__ uint64_t tab[DD_LDS];
+  const uint64_t nch = (n + DD_CHUNK - 1) / DD_CHUNK;
+  // blocks [0, nch): insert chunks, last chunk first; [nch, 2 nch): delete
+  // chunks, first chunk first (single-type batches launch only their half)
+  uint32_t op;
+  uint64_t chunk;
+  if (mode == OP_DELETE) {
+    op = OP_DELETE;
+    chunk = blockIdx.x;
+  } else if (blockIdx.x < nch) {
+    op = OP_INSERT;
+    chunk = nch - 1 - blockIdx.x;
+  } else {
+    op = OP_DELETE;
+    chunk = blockIdx.x - nch;
+  }
+  for (int j = threadIdx.x; j < DD_LDS; j += BLOCK) tab[j] = EMPTY;
+  __syncthreads();
+  const uint64_t base = chunk * DD_CHUNK;
+#pragma unroll
+  for (int j = 0; j < DD_PER_THREAD; ++j) {
+    const uint64_t i = base + (uint64_t)j * BLOCK + threadIdx.x;
+    if (i >= n || (mode == OP_MIXED && ops[i] != op)) continue;
+    const uint32_t k = keys[i];
+    if (!valid_key(k)) continue;
+    const uint64_t e = ((uint64_t)k << 32) | (uint32_t)i;
+    for (uint32_t s = mix32(k) & (DD_LDS - 1);; s = (s + 1) & (DD_LDS - 1)) {
+      uint64_t cur = tab[s];
+      if (cur == EMPTY) {
+        cur = atomicCAS((unsigned long long *)&tab[s], (unsigned long long)EMPTY, (unsigned long long)e);
+        if (cur == EMPTY) break;
+      }
+      if ((uint32_t)(cur >> 32) == k) {
+        if (op == OP_INSERT)
+          atomicMax((unsigned long long *)&tab[s], (unsigned long long)e);
+        else
+          atomicMin((unsigned long long *)&tab[s], (unsigned long long)e);
+        break;
+      }
+    }
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < DD_LDS; j += BLOCK) {
+    const uint64_t e = tab[j];
+    if (e != EMPTY) dedupe_record(dd, mask, op, (uint32_t)(e >> 32), e);
+  }
+}
+
+// Blocks of the plain path's dedupe build for a batch of n operations.
+static inline uint64_t dedupe_blocks(uint32_t mode, uint64_t n) {
+  const uint64_t nch = (n + DD_CHUNK - 1) / DD_CHUNK;
+  return mode == OP_MIXED ? 2 * nch : nch;
 }
 
 __device__ __forceinline__ bool dedupe_winner(const uint64_t *dd, uint64_t mask, uint32_t k, uint32_t i) {
@@ -1109,18 +1176,28 @@ __device__ __forceinline__ void plan_start(volatile Ctl *c, const ResizeArgs &a,
   plan_next(c);
 }
 
-__global__ __launch_bounds__(BLOCK) void resize_plan_kernel(ResizeArgs a, uint32_t mode, uint64_t amount,
-                                                            const uint8_t *ops) {
-  __shared__ unsigned long long n_ins;
-  if (threadIdx.x == 0) n_ins = 0;
+// Insert operations of a mixed batch, for its pre-batch plan: one add per
+// block to Ctl::plan_inserts, which the plan kernel reads and clears.
+__global__ __launch_bounds__(BLOCK) void count_inserts_kernel(Ctl *c, const uint8_t *ops, uint64_t n) {
+  __shared__ unsigned long long block_sum;
+  if (threadIdx.x == 0) block_sum = 0;
   __syncthreads();
+  unsigned long long mine = 0;
+  for (uint64_t i = (uint64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (uint64_t)gridDim.x * BLOCK)
+    mine += ops[i] == OP_INSERT;
+  mine = wave_sum64(mine);
+  if ((threadIdx.x & 63) == 0 && mine) atomicAdd(&block_sum, mine);
+  __syncthreads();
+  if (threadIdx.x == 0 && block_sum) add64(&c->plan_inserts, block_sum);
+}
+
+__global__ void resize_plan_kernel(ResizeArgs a, uint32_t mode, uint64_t amount) {
+  uint64_t n = amount;
   if (mode == PLAN_PRE_MIXED) {
-    unsigned long long mine = 0;
-    for (uint64_t i = threadIdx.x; i < amount; i += BLOCK) mine += ops[i] == OP_INSERT;
-    atomicAdd(&n_ins, mine);
-    __syncthreads();
+    n = ld_ctl(&a.ctl->plan_inserts);
+    __hip_atomic_store(&a.ctl->plan_inserts, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  if (threadIdx.x == 0) plan_start(a.ctl, a, mode, mode == PLAN_PRE_MIXED ? n_ins : amount);
+  plan_start(a.ctl, a, mode, n);
 }
 
 // Ticket for "the last block of this launch": every block has finished its
@@ -2381,7 +2458,10 @@ static hive_status resize_sequence(hive_table *h, uint32_t mode, uint64_t amount
   ResizeArgs ra{h->d_buckets, h->d_hint, h->d_ctl, h->S, h->cfg.resize_k, h->cfg.lf_expand_pct,
                 h->cfg.lf_contract_pct};
   phase_mark(h, HIVE_PHASE_RESIZE, st);
-  hipLaunchKernelGGL(resize_plan_kernel, dim3(1), dim3(BLOCK), 0, st, ra, mode, amount, d_ops);
+  if (mode == PLAN_PRE_MIXED)
+    hipLaunchKernelGGL(count_inserts_kernel, dim3(grid_for(amount, BLOCK * 16ull, 1024)), dim3(BLOCK), 0, st, h->d_ctl,
+                       d_ops, amount);
+  hipLaunchKernelGGL(resize_plan_kernel, dim3(1), dim3(1), 0, st, ra, mode, amount);
   const int rounds = resize_rounds(h);
   switch (h->S) {
     case 16: launch_resize_passes<16>(ra, rounds, st); break;
@@ -2576,7 +2656,7 @@ static hive_status run_batch(hive_t h, uint32_t mode, const uint8_t *d_ops, cons
     // allocation-free path checked n against NOALLOC_MAX_BATCH
     const uint64_t cap = dd_words_for(n);
     if ((s = fill_u64(dd, cap, EMPTY, st)) != HIVE_OK) return s;
-    hipLaunchKernelGGL(dedupe_build_kernel, dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, st, dd,
+    hipLaunchKernelGGL(dedupe_build_kernel, dim3((unsigned)dedupe_blocks(mode, n)), dim3(BLOCK), 0, st, dd,
                        cap - 1, mode, d_ops, d_keys, n);
     if ((s = launch_check()) != HIVE_OK) return s;
     a.dd = dd;

@@ -72,7 +72,8 @@ struct alignas(128) Ctl {
   uint64_t split_happened; // a split ran since the last stash drain
   uint64_t initial_buckets;
   uint64_t max_buckets;
-  uint64_t pad2_[8];
+  uint64_t plan_inserts;   // insert operations of a mixed batch, counted for its pre-batch plan
+  uint64_t pad2_[7];
   // line 3: maintenance kernels (dump, placement census)
   uint64_t dump_count;
   uint64_t place_first;
