@@ -457,10 +457,10 @@ def run_breakdown(args):
     buckets) is built in slices, from empty to 55% load and then to 65, 75,
     85, 90, 95 and 97%, one hive_insert_batch of unique uniform keys per
     slice, with phase timing on: steps 1 and 2 (replace, claim-then-commit)
-    run in the probe launch, steps 3 and 4 (bounded cuckoo chains, then stash
-    or pending) in the eviction launch.  Per slice: both times, the eviction
-    share, items sent to eviction, displacements and stash placements;
-    medians over the timed builds."""
+    run in the probe launch, step 3 (bounded cuckoo chains) in the eviction
+    launch and step 4 (stash or pending) in a launch of its own.  Per slice:
+    the three times and their shares, items sent to eviction, displacements
+    and stash placements; medians over the timed builds."""
     import torch
     from paper_2510_15095_amd import hive as H
     from paper_2510_15095_amd import workload as wl
@@ -487,7 +487,7 @@ def run_breakdown(args):
             t.insert(dk[a:b], dv[a:b], flags=H.HIVE_UNIQUE)
             ph = H.hive_phase_times(t.h)
             st = t.stats()
-            rows.append({"inserts": b - a, **{k: ph[k] for k in ("probe", "evict", "finish")},
+            rows.append({"inserts": b - a, **{k: ph[k] for k in ("probe", "evict", "stash", "finish")},
                          **{f: st[f] - prev[f] for f in fields}})
             prev = st
         assert st["status"] in (H.HIVE_OK, H.HIVE_WARN_PENDING) and st["live"] == bounds[-1], st
@@ -501,20 +501,23 @@ def run_breakdown(args):
     for i, hi in enumerate(BREAKDOWN_LF):
         probe = float(np.median([r[i]["probe"] for r in runs]))
         evict = float(np.median([r[i]["evict"] for r in runs]))
+        stash = float(np.median([r[i]["stash"] for r in runs]))
         fin = float(np.median([r[i]["finish"] for r in runs]))
         last = runs[-1][i]
+        steps = probe + evict + stash
         out_rows.append({"load_from": lo, "load_to": hi, "inserts": last["inserts"],
-                         "steps12_ms": round(probe, 4), "steps34_ms": round(evict, 4), "finish_ms": round(fin, 4),
-                         "steps34_share": round(evict / (probe + evict), 4),
+                         "steps12_ms": round(probe, 4), "step3_ms": round(evict, 4), "step4_ms": round(stash, 4),
+                         "finish_ms": round(fin, 4), "steps12_share": round(probe / steps, 4),
+                         "step3_share": round(evict / steps, 4), "step4_share": round(stash / steps, 4),
                          "to_eviction": last["evict_items"], "displacements": last["evictions"],
                          "stash": last["stash_inserts"], "pending": last["pending_inserts"],
-                         "mops": round(last["inserts"] / ((probe + evict + fin) * 1e-3) / 1e6, 1)})
+                         "mops": round(last["inserts"] / ((steps + fin) * 1e-3) / 1e6, 1)})
         lo = hi
-    total_ms = sum(r["steps12_ms"] + r["steps34_ms"] + r["finish_ms"] for r in out_rows)
+    total_ms = sum(r["steps12_ms"] + r["step3_ms"] + r["step4_ms"] + r["finish_ms"] for r in out_rows)
     rec = base_record(args, bounds[-1] / (total_ms * 1e-3) / 1e6, total_ms,
                       f"insert time by step: FIXED {nb} x {S}-slot buckets built from empty to 97% load in "
-                      f"{len(BREAKDOWN_LF)} slices of unique uniform keys, probe launch (steps 1-2) and eviction "
-                      f"launch (steps 3-4) timed apart",
+                      f"{len(BREAKDOWN_LF)} slices of unique uniform keys, probe launch (steps 1-2), eviction "
+                      f"launch (step 3) and stash launch (step 4) timed apart",
                       {"slices": len(BREAKDOWN_LF), "max_evictions": 8})
     rec["breakdown"] = out_rows
     t.close()
@@ -568,7 +571,7 @@ def run_hashes(args):
     # figure of hash-pair insertion throughput, 2^20 .. 2^25 unique keys):
     # a FIXED 16-slot table sized for 95% load, cleared and built per rep
     pairs = {"bithash1+bithash2": H.HIVE_PAIR_BITHASH, "crc32+crc64": H.HIVE_PAIR_CRC,
-             "murmur3+city32": H.HIVE_PAIR_MURMUR}
+             "murmur3+city32": H.HIVE_PAIR_MURMUR, "bithash1+bithash2+city32 (three candidates)": H.HIVE_PAIR_TRIPLE}
     host_keys = wl.KeyStream(9).range(0, 1 << 25)
     ik = torch.from_numpy(host_keys).cuda()
     iv = torch.from_numpy(wl.values_for(host_keys)).cuda()

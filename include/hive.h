@@ -96,13 +96,19 @@ typedef struct {
                                  HIVE_PAIR_CRC (CRC-32, low half of CRC-64;
                                  tables in constant memory) or
                                  HIVE_PAIR_MURMUR (MurmurHash3, CityHash32),
-                                 the hashes of the study below.  The others
+                                 the hashes of the study below, or
+                                 HIVE_PAIR_TRIPLE: three candidate buckets
+                                 (BitHash1, BitHash2, CityHash32; lookups
+                                 probe them in that order, inserts take the
+                                 emptiest, ties to the lower hash, and an
+                                 evicted entry moves to its next candidate in
+                                 that order, cyclically).  The others
                                  need S = 16, FIXED addressing, probe_both = 0,
                                  plain launches (the executor and
                                  hive_placement refuse such tables) */
 } hive_config;
 
-enum { HIVE_PAIR_BITHASH = 0, HIVE_PAIR_CRC = 1, HIVE_PAIR_MURMUR = 2 };
+enum { HIVE_PAIR_BITHASH = 0, HIVE_PAIR_CRC = 1, HIVE_PAIR_MURMUR = 2, HIVE_PAIR_TRIPLE = 3 };
 
 typedef struct {
   uint64_t live;            /* number of keys stored */
@@ -222,8 +228,10 @@ const char *hive_status_string(hive_status s);
 /* ---- Phase timing (a measurement aid; off by default) --------------------
  * While enabled, every batch call records HIP events on its stream at the
  * boundaries of its phase groups (Section IV-A's insert steps map onto
- * them: steps 1 and 2 run in the probe launch, steps 3 and 4 in the
- * eviction launch).  hive_phase_times waits for the recorded events and
+ * them: steps 1 and 2 run in the probe launch, step 3 in the eviction
+ * launch and step 4 in a launch of its own, which exists only while timing
+ * is on; without timing the eviction launch also places the stash
+ * entries).  hive_phase_times waits for the recorded events and
  * writes, per group, the milliseconds spent since the previous
  * hive_phase_times call, then starts over: ms_out is a caller-owned host
  * array of HIVE_PHASE_KINDS doubles.  The events are ordered on each call's
@@ -231,11 +239,15 @@ const char *hive_status_string(hive_status s);
 enum {
   HIVE_PHASE_DEDUPE = 0,  /* dedupe set fill and build */
   HIVE_PHASE_PROBE = 1,   /* probe launch: replace, claim (steps 1-2), lookup, delete */
-  HIVE_PHASE_EVICT = 2,   /* eviction chains and stash/pending placement (steps 3-4) */
+  HIVE_PHASE_EVICT = 2,   /* eviction chains (step 3); with 16-slot buckets and
+                             the BitHash pair, step 4 is timed apart below,
+                             otherwise it is included here */
   HIVE_PHASE_RESIZE = 3,  /* load-factor plans and split/merge passes */
   HIVE_PHASE_DRAIN = 4,   /* stash drain after splits and its re-placement */
   HIVE_PHASE_FINISH = 5,  /* counter folds after a batch */
-  HIVE_PHASE_KINDS = 6
+  HIVE_PHASE_STASH = 6,   /* stash or pending placement of entries whose chain ran
+                             out (step 4; 16-slot BitHash tables) */
+  HIVE_PHASE_KINDS = 7
 };
 hive_status hive_phase_timing(hive_t h, int enable);
 hive_status hive_phase_times(hive_t h, double *ms_out);

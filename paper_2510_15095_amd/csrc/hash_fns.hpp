@@ -14,7 +14,8 @@
 // A hash pair names the two candidate-bucket hashes of a table:
 //   PAIR_BITHASH  BitHash1 and BitHash2 (the paper's choice, the default);
 //   PAIR_CRC      CRC-32 and the low 32 bits of CRC-64;
-//   PAIR_MURMUR   MurmurHash3 and CityHash32.
+//   PAIR_MURMUR   MurmurHash3 and CityHash32;
+//   PAIR_TRIPLE   three candidates: BitHash1, BitHash2 and CityHash32.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -24,7 +25,7 @@
 
 namespace hive {
 
-enum : int { PAIR_BITHASH = 0, PAIR_CRC = 1, PAIR_MURMUR = 2 };
+enum : int { PAIR_BITHASH = 0, PAIR_CRC = 1, PAIR_MURMUR = 2, PAIR_TRIPLE = 3 };
 
 struct CrcTables {
   uint32_t t32[256];
@@ -120,6 +121,21 @@ template <>
 struct HashPair<PAIR_MURMUR> {
   __device__ static __forceinline__ uint32_t h1(uint32_t k) { return murmur3_key(k); }
   __device__ static __forceinline__ uint32_t h2(uint32_t k) { return city32_key(k); }
+};
+
+// Three candidate buckets: BitHash1, BitHash2 and CityHash32 (the paper's
+// third-hash configuration in its hash-function comparison, Section V-B).
+template <>
+struct HashPair<PAIR_TRIPLE> {
+  __device__ static __forceinline__ uint32_t h1(uint32_t k) { return bithash1(k); }
+  __device__ static __forceinline__ uint32_t h2(uint32_t k) { return bithash2(k); }
+  __device__ static __forceinline__ uint32_t h3(uint32_t k) { return city32_key(k); }
+};
+
+// Candidate buckets per key under a hash choice.
+template <int PAIR>
+struct PairArity {
+  static constexpr int D = PAIR == PAIR_TRIPLE ? 3 : 2;
 };
 
 }  // namespace hive

@@ -45,7 +45,7 @@
 #include "hive_device.hpp"
 
 static_assert(hive::PAIR_BITHASH == HIVE_PAIR_BITHASH && hive::PAIR_CRC == HIVE_PAIR_CRC &&
-                  hive::PAIR_MURMUR == HIVE_PAIR_MURMUR,
+                  hive::PAIR_MURMUR == HIVE_PAIR_MURMUR && hive::PAIR_TRIPLE == HIVE_PAIR_TRIPLE,
               "hash pair numbering");
 
 namespace hive {
@@ -484,17 +484,18 @@ __device__ __forceinline__ void compact_second(bool need2, uint64_t need2_mask, 
 // P1: hash, probe, and replace / lookup / delete / claim.
 // ---------------------------------------------------------------------------
 // LDS of one block of the probe phase (per wave: 64 operations).
-template <int S>
+// D: candidate buckets per key (a round of results per candidate).
+template <int S, int D = 2>
 struct OpsShared {
   using Mask = typename Traits<S>::Mask;
   uint32_t key[WAVES][64];
   uint32_t b1[WAVES][64];
-  uint32_t k2[WAVES][64];  // round 2, compacted: key, bucket, owner
+  uint32_t k2[WAVES][64];  // rounds 2 (and 3), compacted: key, bucket, owner
   uint32_t b2[WAVES][64];
   uint8_t list[WAVES][64];
-  Mask m[2][WAVES][64];
-  Mask e[2][WAVES][64];
-  uint64_t w[2][WAVES][64];
+  Mask m[D][WAVES][64];
+  Mask e[D][WAVES][64];
+  uint64_t w[D][WAVES][64];
 };
 
 // The table state a probe tile needs, read once per launch (or per chunk of
@@ -517,10 +518,14 @@ __device__ __forceinline__ OpsView read_view(const Ctl *c, uint64_t stash_cap, u
 // new keys always need both; for lookups and deletes it trades bytes for one
 // memory round trip fewer).
 // PAIR: the table's candidate hashes (HashPair); BitHash1/2 by default.
+// With three candidates (PAIR_TRIPLE) the third is probed in a third round
+// by the operations that found their key in neither of the first two.
 template <int S, uint32_t MODE, bool BOTH, int PAIR = PAIR_BITHASH>
-__device__ __forceinline__ void ops_tile(const OpsArgs &a, const OpsView &view, uint64_t tile, OpsShared<S> &sh) {
+__device__ __forceinline__ void ops_tile(const OpsArgs &a, const OpsView &view, uint64_t tile,
+                                         OpsShared<S, PairArity<PAIR>::D> &sh) {
   using T = Traits<S>;
   using Mask = typename T::Mask;
+  constexpr bool D3 = PairArity<PAIR>::D == 3;
   auto &s_key = sh.key;
   auto &s_b1 = sh.b1;
   auto &s_k2 = sh.k2;
@@ -549,10 +554,11 @@ __device__ __forceinline__ void ops_tile(const OpsArgs &a, const OpsView &view, 
   const bool valid = active && op <= OP_LOOKUP && valid_key(k);
   bool work = valid;
   if (work && a.dd && op != OP_LOOKUP) work = dedupe_winner(a.dd, a.dd_mask, k, (uint32_t)i);
-  uint32_t c1 = 0, c2 = 0;
+  uint32_t c1 = 0, c2 = 0, c3 = 0;
   if (work) {
     c1 = address(geo, HashPair<PAIR>::h1(k));
     c2 = address(geo, HashPair<PAIR>::h2(k));
+    if constexpr (D3) c3 = address(geo, HashPair<PAIR>::h3(k));
   }
   s_key[wv][lane] = work ? k : 0u;
   s_b1[wv][lane] = c1;
@@ -594,6 +600,23 @@ __device__ __forceinline__ void ops_tile(const OpsArgs &a, const OpsView &view, 
   // result irrelevant; otherwise the second round ran only without one
   const Mask m2 = (need2 && m1 == 0) ? s_m[1][wv][lane] : (Mask)0;
   const Mask e2 = need2 ? s_e[1][wv][lane] : (Mask)0;
+  Mask m3 = 0, e3 = 0;
+  bool need3 = false;
+  if constexpr (D3) {
+    // round 3: the third candidate of the operations without a match so far
+    need3 = work && m1 == 0 && m2 == 0 && c3 != c1 && c3 != c2;
+    const uint64_t need3_mask = ballot(need3);
+    const int n3 = __popcll(need3_mask);
+    compact_second(need3, need3_mask, n3, k, c3, c1, lane, s_k2[wv], s_b2[wv], s_list[wv]);
+    wave_lds_sync();
+    if (n3 > 0)
+      probe_round<S>(a.buckets, s_k2[wv], s_b2[wv], s_list[wv], n3, s_m[2][wv], s_e[2][wv], s_w[2][wv], g, sl);
+    wave_lds_sync();
+    if (need3) {
+      m3 = s_m[2][wv][lane];
+      e3 = s_e[2][wv][lane];
+    }
+  }
 
   uint32_t out_v = NO_VALUE;
   uint8_t out_f = 0;
@@ -611,7 +634,11 @@ __device__ __forceinline__ void ops_tile(const OpsArgs &a, const OpsView &view, 
       slot = a.buckets + (uint64_t)c2 * S + ctz_mask(m2);
       word = s_w[1][wv][lane];
       in_bucket = true;
-    } else if (overflow_used && hinted(a.hint, c1, c2)) {
+    } else if (D3 && m3) {
+      slot = a.buckets + (uint64_t)c3 * S + ctz_mask(m3);
+      word = s_w[D3 ? 2 : 0][wv][lane];
+      in_bucket = true;
+    } else if (overflow_used && (hinted(a.hint, c1, c2) || (D3 && hinted(a.hint, c3, c3)))) {
       slot = overflow_find(a.stash, a.stash_cap, n_stash, a.pending, n_pend, k, &word, false);
     }
     if (op == OP_LOOKUP) {
@@ -655,6 +682,7 @@ __device__ __forceinline__ void ops_tile(const OpsArgs &a, const OpsView &view, 
     } else if (op == OP_INSERT) {
       // claim-then-commit (Algorithm 2) in the candidate with more empty
       // slots first, ties to the first hash: bucketed two-choice placement
+      // (three-choice with three candidates)
       dl = 1;
       Mask f_first = e1, f_second = (c2 != c1) ? e2 : (Mask)0;
       uint32_t b_first = c1, b_second = c2;
@@ -665,12 +693,35 @@ __device__ __forceinline__ void ops_tile(const OpsArgs &a, const OpsView &view, 
         b_first = c2;
         b_second = c1;
       }
+      Mask f_third = 0;
+      uint32_t b_third = c3;
+      if constexpr (D3) {
+        f_third = need3 ? e3 : (Mask)0;
+        if (popc_mask(f_third) > popc_mask(f_second)) {
+          const Mask tm = f_second;
+          f_second = f_third;
+          f_third = tm;
+          b_third = b_second;
+          b_second = c3;
+          if (popc_mask(f_second) > popc_mask(f_first)) {
+            const Mask t2 = f_first;
+            f_first = f_second;
+            f_second = t2;
+            const uint32_t bt = b_first;
+            b_first = b_second;
+            b_second = bt;
+          }
+        }
+      }
       bool placed = false;
-      while (!placed && (f_first | f_second)) {
+      while (!placed && (f_first | f_second | f_third)) {
         if (f_first == 0) {
           f_first = f_second;
-          f_second = 0;
           b_first = b_second;
+          f_second = f_third;
+          b_second = b_third;
+          f_third = 0;
+          continue;
         }
         const int s = ctz_mask(f_first);
         if (cas64(a.buckets + (uint64_t)b_first * S + s, EMPTY, kv) == EMPTY)
@@ -712,7 +763,7 @@ __device__ __forceinline__ void ops_tile(const OpsArgs &a, const OpsView &view, 
 template <int S, uint32_t MODE, bool BOTH, int PAIR = PAIR_BITHASH>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(OPS_WAVES_PER_EU))) void ops_kernel(
     OpsArgs a) {
-  __shared__ OpsShared<S> sh;
+  __shared__ OpsShared<S, PairArity<PAIR>::D> sh;
   const OpsView view = read_view(a.ctl, a.stash_cap, a.pending_cap);
   const uint64_t ntiles = (a.n + BLOCK - 1) / BLOCK;
   for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) ops_tile<S, MODE, BOTH, PAIR>(a, view, tile, sh);
@@ -727,7 +778,7 @@ struct EvictArgs {
   uint64_t *stash;
   uint64_t *pending;
   Ctl *ctl;
-  const uint64_t *wl;
+  uint64_t *wl;
   uint64_t wl_seg_cap;
   uint64_t stash_cap;
   uint64_t pending_cap;
@@ -778,6 +829,7 @@ __device__ __forceinline__ int overflow_place(const EvictArgs &a, const Geo &geo
   const uint32_t k = key_of(kv);
   set_hint(a.hint, address(geo, HashPair<PAIR>::h1(k)));
   set_hint(a.hint, address(geo, HashPair<PAIR>::h2(k)));
+  if constexpr (PairArity<PAIR>::D == 3) set_hint(a.hint, address(geo, HashPair<PAIR>::h3(k)));
   return where;
 }
 
@@ -934,12 +986,36 @@ __device__ __forceinline__ bool evict_chain(const EvictArgs &a, const Geo &geo, 
   const Mask f1 = load_view<S>(a.buckets + (uint64_t)c1 * S, g, sl, w);
   const Mask f2 = load_view<S>(a.buckets + (uint64_t)c2 * S, g, sl, w2v) & (Mask)((c2 != c1) ? ~0ull : 0ull);
   bool placed;
-  if (popc_mask(f2) > popc_mask(f1))
-    placed = group_claim<S>(a.buckets + (uint64_t)c2 * S, f2, kv, g, sl) ||
-             group_claim<S>(a.buckets + (uint64_t)c1 * S, f1, kv, g, sl);
-  else
-    placed = group_claim<S>(a.buckets + (uint64_t)c1 * S, f1, kv, g, sl) ||
-             group_claim<S>(a.buckets + (uint64_t)c2 * S, f2, kv, g, sl);
+  if constexpr (PairArity<PAIR>::D == 3) {
+    // three-choice: the emptiest candidate first, ties to the lower hash
+    const uint32_t c3 = address(geo, HashPair<PAIR>::h3(key_of(kv)));
+    const Mask f3 = load_view<S>(a.buckets + (uint64_t)c3 * S, g, sl, w) &
+                    (Mask)((c3 != c1 && c3 != c2) ? ~0ull : 0ull);
+    Mask f[3] = {f1, f2, f3};
+    uint32_t c[3] = {c1, c2, c3};
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2 - x; ++y)
+        if (popc_mask(f[y + 1]) > popc_mask(f[y])) {
+          const Mask tf = f[y];
+          f[y] = f[y + 1];
+          f[y + 1] = tf;
+          const uint32_t tc = c[y];
+          c[y] = c[y + 1];
+          c[y + 1] = tc;
+        }
+    placed = group_claim<S>(a.buckets + (uint64_t)c[0] * S, f[0], kv, g, sl) ||
+             group_claim<S>(a.buckets + (uint64_t)c[1] * S, f[1], kv, g, sl) ||
+             group_claim<S>(a.buckets + (uint64_t)c[2] * S, f[2], kv, g, sl);
+  } else {
+    if (popc_mask(f2) > popc_mask(f1))
+      placed = group_claim<S>(a.buckets + (uint64_t)c2 * S, f2, kv, g, sl) ||
+               group_claim<S>(a.buckets + (uint64_t)c1 * S, f1, kv, g, sl);
+    else
+      placed = group_claim<S>(a.buckets + (uint64_t)c1 * S, f1, kv, g, sl) ||
+               group_claim<S>(a.buckets + (uint64_t)c2 * S, f2, kv, g, sl);
+  }
   uint32_t b = c1;  // chains start at the first candidate
   for (uint32_t kick = 1; kick <= max_kicks && !placed; ++kick) {
     uint64_t *bkt = a.buckets + (uint64_t)b * S;
@@ -966,7 +1042,13 @@ __device__ __forceinline__ bool evict_chain(const EvictArgs &a, const Geo &geo, 
     kv = victim;
     const uint32_t v1 = address(geo, HashPair<PAIR>::h1(key_of(kv)));
     const uint32_t v2 = address(geo, HashPair<PAIR>::h2(key_of(kv)));
-    b = (b == v1) ? v2 : v1;  // AltBucket: the victim's other candidate
+    if constexpr (PairArity<PAIR>::D == 3) {
+      // the victim's next candidate after b, in hash order, cyclically
+      const uint32_t v3 = address(geo, HashPair<PAIR>::h3(key_of(kv)));
+      b = (b == v1) ? v2 : (b == v2) ? v3 : v1;
+    } else {
+      b = (b == v1) ? v2 : v1;  // AltBucket: the victim's other candidate
+    }
   }
   return placed;  // if not, kv is the entry in hand
 }
@@ -981,7 +1063,11 @@ __device__ __forceinline__ bool evict_chain(const EvictArgs &a, const Geo &geo, 
 // each on a single address (thousands of waves queue there in a stash drain);
 // their number is added per wave to the shards and folded into the count
 // after the launch.  Otherwise one count reservation per wave.
-template <int S, int PAIR = PAIR_BITHASH>
+//
+// DEFER (phase timing of the plain path): step 4 is left to its own launch,
+// stash_kernel, so that steps 3 and 4 are timed apart; the item's worklist
+// word is overwritten with the entry still in hand, or EMPTY once placed.
+template <int S, int PAIR = PAIR_BITHASH, bool DEFER = false>
 __device__ __forceinline__ void evict_round(const EvictArgs &a, const Geo &geo, bool unreserved, bool have,
                                             uint64_t pos, int g, int sl, uint64_t &n_evict, uint64_t &n_full,
                                             uint64_t &n_side, uint64_t &n_fresh) {
@@ -990,6 +1076,13 @@ __device__ __forceinline__ void evict_round(const EvictArgs &a, const Geo &geo, 
   if (have) {
     kv = a.wl[pos];
     placed = evict_chain<S, PAIR>(a, geo, kv, a.max_evictions, g, sl, n_evict);
+  }
+  if constexpr (DEFER) {
+    if (have && sl == 0) {
+      a.wl[pos] = placed ? EMPTY : kv;
+      n_full += !placed;
+    }
+    return;
   }
   const bool push = !placed && sl == 0;
   const uint64_t pm = ballot(push);
@@ -1023,7 +1116,7 @@ __device__ __forceinline__ void evict_counters(const EvictArgs &a, bool unreserv
                                                uint64_t n_full, uint64_t n_side, uint64_t n_fresh, int sl) {
   const uint64_t e = wave_sum64(sl == 0 ? n_evict : 0), f = wave_sum64(n_full), sd = wave_sum64(n_side);
   const uint64_t fr = wave_sum64(n_fresh);
-  if ((threadIdx.x & 63) == 0 && (e | f)) {
+  if ((threadIdx.x & 63) == 0 && (e | f | sd)) {
     Shard *sh = shard_of(a.ctl, unit % NSHARD);
     if (e) add64(&sh->evictions, e);
     if (f) add64(&sh->full_chains, f);
@@ -1039,7 +1132,7 @@ __device__ __forceinline__ void evict_counters(const EvictArgs &a, bool unreserv
 // The worklist is emptied afterwards by finish_kernel (it also counts the
 // items and folds unreserved stash placements into the stash count), so this
 // kernel takes no ticket.
-template <int S, int PAIR = PAIR_BITHASH>
+template <int S, int PAIR = PAIR_BITHASH, bool DEFER = false>
 __global__ __launch_bounds__(BLOCK) void evict_kernel(EvictArgs a) {
   using E = EvictShape<S>;
   __shared__ uint64_t pre[NSHARD + 1];
@@ -1058,10 +1151,48 @@ __global__ __launch_bounds__(BLOCK) void evict_kernel(EvictArgs a) {
   const uint64_t wave_first = ((uint64_t)blockIdx.x * WAVES + wv) * E::G;
   for (uint64_t base = wave_first; base < cnt; base += groups) {
     const uint64_t t = base - wave_first + first;
-    evict_round<S, PAIR>(a, geo, unreserved, t < cnt, t < cnt ? wl_slot(pre, t, a.wl_seg_cap) : 0, g, sl, n_evict,
-                         n_full, n_side, n_fresh);
+    evict_round<S, PAIR, DEFER>(a, geo, unreserved, t < cnt, t < cnt ? wl_slot(pre, t, a.wl_seg_cap) : 0, g, sl,
+                                n_evict, n_full, n_side, n_fresh);
   }
   evict_counters(a, unreserved, (uint64_t)blockIdx.x * WAVES + wv, n_evict, n_full, n_side, n_fresh, sl);
+}
+
+// Step 4 as its own launch (after evict_kernel<.., DEFER>): every worklist
+// word that still holds an entry goes to the stash or the pending list, one
+// entry per lane, with the same room reservation as the fused path.
+template <int PAIR = PAIR_BITHASH>
+__global__ __launch_bounds__(BLOCK) void stash_kernel(EvictArgs a) {
+  __shared__ uint64_t pre[NSHARD + 1];
+  wl_prefix(a.ctl, pre);
+  const uint64_t cnt = pre[NSHARD];
+  if (cnt == 0) return;
+  const Geo geo = read_geo(a.ctl);
+  const bool unreserved = ld_ctl(&a.ctl->stash_count) + cnt <= a.stash_cap;
+  const int lane = threadIdx.x & 63;
+  const uint64_t stride = (uint64_t)gridDim.x * BLOCK;
+  uint64_t n_side = 0, n_fresh = 0;
+  for (uint64_t base = (uint64_t)blockIdx.x * BLOCK + (threadIdx.x & ~63u); base < cnt; base += stride) {
+    const uint64_t t = base + lane;
+    const uint64_t kv = t < cnt ? a.wl[wl_slot(pre, t, a.wl_seg_cap)] : EMPTY;
+    const bool push = kv != EMPTY;
+    const uint64_t pm = ballot(push);
+    if (!pm) continue;
+    const int leader = __builtin_ctzll(pm);
+    uint64_t room = 0;
+    if (!unreserved) {
+      if (lane == leader) {
+        const uint64_t n = (uint64_t)__popcll(pm);
+        room = load_fresh(&a.ctl->stash_count) < a.stash_cap ? add64(&a.ctl->stash_count, n) : a.stash_cap;
+      }
+      room = read_lane64(room, leader);
+    }
+    if (push) {
+      const int where = overflow_place<PAIR>(a, geo, kv, room + rank_below(pm));
+      n_side += (where == 0 || where == 3) ? 1 : where == 1 ? (1ull << 32) : 0;
+      n_fresh += where == 0;
+    }
+  }
+  evict_counters(a, unreserved, (uint64_t)blockIdx.x * WAVES + (threadIdx.x >> 6), 0, 0, n_side, n_fresh, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -2391,16 +2522,29 @@ static void launch_ops_mode(uint32_t mode, const OpsArgs &a, hipStream_t st) {
 // latency-bound, so items run side by side rather than one after another in
 // a group); `max_items` bounds the worklist (the batch's inserts, or the
 // stash and pending capacity for a drain).
-static void launch_evict(hive_table *h, uint64_t max_items, hipStream_t st) {
+static void phase_mark(hive_table *h, int kind, hipStream_t st);
+
+// split_steps (phase timing of a 16-slot BitHash table): steps 3 and 4 in
+// two launches, the second timed as its own phase.
+static void launch_evict(hive_table *h, uint64_t max_items, hipStream_t st, bool split_steps = false) {
   EvictArgs e{h->d_buckets, h->d_hint,       h->d_stash,   h->d_pending,   h->d_ctl,
               h->d_wl,      h->wl_seg_cap,   h->stash_cap, h->pending_cap, h->cfg.max_evictions};
   const dim3 grid(grid_for(max_items, (uint64_t)WAVES * evict_groups_per_wave(h->S), EVICT_GRID));
+  if (split_steps && h->S == 16 && h->cfg.hash_pair == PAIR_BITHASH) {
+    hipLaunchKernelGGL((evict_kernel<16, PAIR_BITHASH, true>), grid, dim3(BLOCK), 0, st, e);
+    phase_mark(h, HIVE_PHASE_STASH, st);
+    hipLaunchKernelGGL(stash_kernel<PAIR_BITHASH>, dim3(grid_for(max_items, BLOCK, EVICT_GRID)), dim3(BLOCK), 0, st,
+                       e);
+    return;
+  }
   switch (h->S) {
     case 16:
       if (h->cfg.hash_pair == PAIR_CRC)
         hipLaunchKernelGGL((evict_kernel<16, PAIR_CRC>), grid, dim3(BLOCK), 0, st, e);
       else if (h->cfg.hash_pair == PAIR_MURMUR)
         hipLaunchKernelGGL((evict_kernel<16, PAIR_MURMUR>), grid, dim3(BLOCK), 0, st, e);
+      else if (h->cfg.hash_pair == PAIR_TRIPLE)
+        hipLaunchKernelGGL((evict_kernel<16, PAIR_TRIPLE>), grid, dim3(BLOCK), 0, st, e);
       else
         hipLaunchKernelGGL(evict_kernel<16>, grid, dim3(BLOCK), 0, st, e);
       break;
@@ -2674,6 +2818,8 @@ static hive_status run_batch(hive_t h, uint32_t mode, const uint8_t *d_ops, cons
         launch_ops_mode<16, false, PAIR_CRC>(mode, a, st);
       else if (h->cfg.hash_pair == PAIR_MURMUR)
         launch_ops_mode<16, false, PAIR_MURMUR>(mode, a, st);
+      else if (h->cfg.hash_pair == PAIR_TRIPLE)
+        launch_ops_mode<16, false, PAIR_TRIPLE>(mode, a, st);
       else if (h->cfg.probe_both)
         launch_ops_mode<16, true>(mode, a, st);
       else
@@ -2685,7 +2831,7 @@ static hive_status run_batch(hive_t h, uint32_t mode, const uint8_t *d_ops, cons
   if ((s = launch_check()) != HIVE_OK) return s;
   if (mode == OP_INSERT || mode == OP_MIXED) {
     phase_mark(h, HIVE_PHASE_EVICT, st);
-    launch_evict(h, n, st);
+    launch_evict(h, n, st, h->timing);
   }
   if (mode != OP_LOOKUP) {
     phase_mark(h, HIVE_PHASE_FINISH, st);
@@ -2720,7 +2866,7 @@ hive_status hive_create(const hive_config *cfg_in, uint64_t initial_buckets, voi
   const uint32_t S = cfg.slots_per_bucket;
   if (S != 16 && S != 32 && S != 64) return HIVE_ERR_ARG;
   if (cfg.addressing != HIVE_FIXED && cfg.addressing != HIVE_LINEAR) return HIVE_ERR_ARG;
-  if (cfg.hash_pair > HIVE_PAIR_MURMUR) return HIVE_ERR_ARG;
+  if (cfg.hash_pair > HIVE_PAIR_TRIPLE) return HIVE_ERR_ARG;
   // only 16-slot FIXED tables on plain launches have the other hash pairs
   if (cfg.hash_pair != HIVE_PAIR_BITHASH && (S != 16 || cfg.addressing != HIVE_FIXED || cfg.probe_both))
     return HIVE_ERR_ARG;

@@ -351,7 +351,7 @@ def hive_drain_results(d, tickets):
     return done.astype(bool), live
 
 
-HIVE_PAIR_BITHASH, HIVE_PAIR_CRC, HIVE_PAIR_MURMUR = 0, 1, 2
+HIVE_PAIR_BITHASH, HIVE_PAIR_CRC, HIVE_PAIR_MURMUR, HIVE_PAIR_TRIPLE = 0, 1, 2, 3
 HASH_KINDS = ("bithash1", "bithash2", "crc32", "crc64", "murmur3", "city32")
 HIVE_HASH_KINDS = len(HASH_KINDS)
 
@@ -385,7 +385,7 @@ def hive_gather_lines(table, idx, out, stream=None) -> None:
                                   _stream_ptr(stream)), "hive_gather_lines")
 
 
-PHASE_KINDS = ("dedupe", "probe", "evict", "resize", "drain", "finish")
+PHASE_KINDS = ("dedupe", "probe", "evict", "resize", "drain", "finish", "stash")
 
 
 def hive_phase_timing(h, enable: bool) -> None:

@@ -88,9 +88,9 @@ def test_config_defaults(H):
 @pytest.mark.parametrize("bad", [
     dict(slots_per_bucket=15), dict(slots_per_bucket=0), dict(addressing=7), dict(lf_expand_pct=0),
     dict(lf_expand_pct=101), dict(lf_contract_pct=95), dict(max_evictions=5000),
-    # hash pairs other than BitHash1/2: 16-slot FIXED tables, plain probing only
-    dict(hash_pair=3), dict(hash_pair=1, addressing=1), dict(hash_pair=2, slots_per_bucket=32),
-    dict(hash_pair=1, probe_both=1),
+    # hash choices other than BitHash1/2: 16-slot FIXED tables, plain probing only
+    dict(hash_pair=4), dict(hash_pair=1, addressing=1), dict(hash_pair=2, slots_per_bucket=32),
+    dict(hash_pair=1, probe_both=1), dict(hash_pair=3, addressing=1), dict(hash_pair=3, slots_per_bucket=64),
 ])
 def test_create_rejects_bad_config_without_touching_the_device(H, bad):
     cfg = H.hive_config_default(**bad)

@@ -74,24 +74,39 @@ def test_unaligned_and_ragged_arrays_take_the_scalar_path(H):
 
 
 def pair_candidates(pair, keys, nb):
-    """Both candidate buckets of every key under a table's hash pair, from
-    the oracle's transcriptions (CRC-64 contributes its low 32 bits)."""
+    """The candidate buckets of every key under a table's hash choice, from
+    the oracle's transcriptions (CRC-64 contributes its low 32 bits; the
+    three-candidate choice is BitHash1, BitHash2 and CityHash32)."""
     le = [int(k).to_bytes(4, "little") for k in keys]
     if pair == 1:
-        h1 = [oracle.crc32_bytes(b) for b in le]
-        h2 = [oracle.crc64_bytes(b) & 0xFFFFFFFF for b in le]
+        hs = [[oracle.crc32_bytes(b) for b in le], [oracle.crc64_bytes(b) & 0xFFFFFFFF for b in le]]
+    elif pair == 2:
+        hs = [[oracle.murmur3_bytes(b, 0) for b in le], [oracle.city32_bytes(b) for b in le]]
     else:
-        h1 = [oracle.murmur3_bytes(b, 0) for b in le]
-        h2 = [oracle.city32_bytes(b) for b in le]
-    return np.array(h1, np.int64) % nb, np.array(h2, np.int64) % nb
+        hs = [[oracle.bithash1(int(k)) for k in keys], [oracle.bithash2(int(k)) for k in keys],
+              [oracle.city32_bytes(b) for b in le]]
+    return [np.array(h, np.int64) % nb for h in hs]
 
 
-@pytest.mark.parametrize("pair", [1, 2])
+def check_in_candidates(t, pair, nb, o):
+    words, where = t.dump(with_where=True)
+    assert np.array_equal(words, o.dump())
+    k = (words & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+    cands = pair_candidates(pair, k, nb)
+    inb = where >= 0
+    ok = np.zeros(int(inb.sum()), bool)
+    for c in cands:
+        ok |= where[inb] == c[inb]
+    assert ok.all(), f"{(~ok).sum()} entries outside their candidate buckets"
+
+
+@pytest.mark.parametrize("pair", [1, 2, 3])
 @pytest.mark.parametrize("lf,E,stash", [(0.5, 8, 1024), (0.97, 8, 1024), (0.99, 2, 64)])
 def test_table_with_other_hash_pair_matches_oracle(H, pair, lf, E, stash):
-    """A FIXED table addressed by CRC-32/CRC-64 or MurmurHash3/CityHash32:
-    every lookup, delete and the final contents equal the dictionary's, and
-    every bucket entry sits in one of its two candidates under that pair."""
+    """A FIXED table addressed by CRC-32/CRC-64, MurmurHash3/CityHash32 or
+    three candidates (BitHash1, BitHash2, CityHash32): every lookup, delete
+    and the final contents equal the dictionary's, and every bucket entry
+    sits in one of its candidates under that choice."""
     S, nb = 16, 97
     n = int(S * nb * lf)
     ks = wl.KeyStream(95 + pair)
@@ -108,12 +123,7 @@ def test_table_with_other_hash_pair_matches_oracle(H, pair, lf, E, stash):
     v, f = t.lookup(dev(q))
     ov, of = o.lookup(q)
     assert np.array_equal(f.cpu().numpy(), of) and np.array_equal(v.cpu().numpy(), ov)
-    words, where = t.dump(with_where=True)
-    assert np.array_equal(words, o.dump())
-    k = (words & np.uint64(0xFFFFFFFF)).astype(np.uint32)
-    c1, c2 = pair_candidates(pair, k, nb)
-    inb = where >= 0
-    assert np.all((where[inb] == c1[inb]) | (where[inb] == c2[inb]))
+    check_in_candidates(t, pair, nb, o)
     dk = keys[::3]
     assert np.array_equal(t.delete(dev(dk), flags=H.HIVE_UNIQUE).cpu().numpy(), o.delete(dk))
     v, f = t.lookup(dev(q))
@@ -122,6 +132,29 @@ def test_table_with_other_hash_pair_matches_oracle(H, pair, lf, E, stash):
     assert np.array_equal(t.dump(), o.dump())
     with pytest.raises(H.HiveError):
         t.placement()
+    t.close()
+
+
+@pytest.mark.parametrize("pair", [1, 2, 3])
+def test_mixed_batches_under_other_hash_choices(H, pair):
+    """Mixed batches (Zipf keys with repeated inserts, deletes, lookups, dedupe
+    on) on a FIXED table at about 90% load under each hash choice: outputs,
+    key counts and contents equal the dictionary's, entries in candidates."""
+    S, nb, universe = 16, 2048, 1 << 16
+    ks = wl.KeyStream(120 + pair)
+    pre = ks.keys(wl.DomainPerm(120 + pair, universe).sample(int(0.88 * nb * S)))
+    t = H.Table(nb, hash_pair=pair, stash_capacity=2048, pending_capacity=2048)
+    o = oracle.O1()
+    t.insert(dev(pre), dev(wl.values_for(pre)), flags=H.HIVE_UNIQUE)
+    o.insert(pre, wl.values_for(pre))
+    for b in range(4):
+        print(f"[case] pair {pair} mixed batch {b}", flush=True)
+        mb = wl.mixed_batch(120 + pair, b, 1 << 13, universe, stream=ks, value_salt=b + 1)
+        v, f = t.mixed(dev(mb["ops"]), dev(mb["keys"]), dev(mb["vals"]))
+        ov, of = o.apply(mb["ops"], mb["keys"], mb["vals"])
+        assert np.array_equal(f.cpu().numpy(), of) and np.array_equal(v.cpu().numpy(), ov), f"batch {b}"
+        assert t.stats()["live"] == len(o)
+    check_in_candidates(t, pair, nb, o)
     t.close()
 
 

@@ -219,17 +219,21 @@ def test_dedupe_delete_batch_sized_from_the_batch(H, path):
     t.close()
 
 
+@pytest.mark.parametrize("timed", [False, True])
 @pytest.mark.parametrize("E,stash,lf", [(8, 1024, 0.97), (2, 64, 0.99), (1, 8, 0.995), (0, 4, 0.99)])
-def test_eviction_stash_pending_heavy(H, E, stash, lf):
+def test_eviction_stash_pending_heavy(H, E, stash, lf, timed):
     """Small tables near capacity: eviction chains, the stash and the pending
-    list all carry entries, and every operation still matches the oracle."""
+    list all carry entries, and every operation still matches the oracle.
+    With phase timing on, step 4 runs as a launch of its own (the eviction
+    launch leaves the entries still in hand in the worklist)."""
     S, nb = 16, 97
     n = int(S * nb * lf)
-    case(f"evict-heavy E={E} stash={stash} lf={lf}")
+    case(f"evict-heavy E={E} stash={stash} lf={lf} timed={timed}")
     ks = wl.KeyStream(40 + E)
     keys = ks.range(0, n)
     vals = wl.values_for(keys)
     t = H.Table(nb, max_evictions=E, stash_capacity=stash, pending_capacity=4096)
+    H.hive_phase_timing(t.h, timed)
     o = oracle.O1()
     t.insert(dev(keys), dev(vals), flags=H.HIVE_UNIQUE)
     o.insert(keys, vals)
@@ -319,7 +323,10 @@ def test_phase_timing_groups_reset_and_results(H):
     o.insert(keys, vals)
     ms = H.hive_phase_times(t.h)
     assert ms["dedupe"] > 0 and ms["probe"] > 0 and ms["evict"] > 0 and ms["finish"] > 0, ms
+    assert ms["stash"] > 0, ms  # 97% load: some chains run out, step 4 is timed apart
     assert ms["resize"] == 0 and ms["drain"] == 0, ms
+    st = t.stats()
+    assert st["full_chains"] > 0 and st["full_chains"] == st["stash_inserts"] + st["pending_inserts"], st
     assert all(x == 0 for x in H.hive_phase_times(t.h).values())
     q = ks.range(0, n + 100)
     v, f = t.lookup(dev(q))
