@@ -57,6 +57,9 @@ def parse():
     ap.add_argument("--validate", action="store_true",
                     help="mixed/served: also compare every output with the CPU dictionary (untimed, slow)")
     ap.add_argument("--keys-log2", type=int, default=26)
+    ap.add_argument("--entry-bits", type=int, choices=(64, 32), default=64,
+                    help="bulk: 64 = key/value pairs in 16-slot buckets; 32 = a key-only set of 32-bit entries in "
+                         "32-slot buckets (one 128-byte line each)")
     ap.add_argument("--batches", type=int, default=64, help="mixed/resize: insert batches")
     ap.add_argument("--batch-log2", type=int, default=22, help="mixed/resize: operations per batch")
     ap.add_argument("--resize-k", type=int, default=0, help="0: the autotuned value if cached, else 1024")
@@ -797,7 +800,9 @@ def run_bulk(args):
     from paper_2510_15095_amd import workload as wl
 
     n = 1 << args.keys_log2
-    nb = int(np.ceil(n / (LOAD * S)))
+    set32 = args.entry_bits == 32
+    slots = 32 if set32 else S
+    nb = int(np.ceil(n / (LOAD * slots)))
     w = wl.bulk_workload(2, n)
     dev = torch.device("cuda:0")
     keys = torch.from_numpy(w["ins_keys"]).to(dev)
@@ -810,7 +815,10 @@ def run_bulk(args):
     if args.probe_both < 0:
         from paper_2510_15095_amd import autotune
         args.probe_both = (autotune.load("probe") or {}).get("probe_both", 0)
-    t = H.Table(nb, slots_per_bucket=S, max_evictions=8, max_batch=n, probe_both=args.probe_both)
+    t = (H.Table(nb, slots_per_bucket=32, entry_bits=32, max_evictions=8, max_batch=n) if set32 else
+         H.Table(nb, slots_per_bucket=S, max_evictions=8, max_batch=n, probe_both=args.probe_both))
+    if set32:
+        vals = None
     n_present = int((w["query_idx"] < n).sum())
     deleted = np.zeros(n, bool)
     deleted[w["del_idx"]] = True
@@ -870,13 +878,14 @@ def run_bulk(args):
     # per operation (key in, value and found flag out)
     def lookup_bytes(hits):
         misses = n - hits
-        return hits * BUCKET_BYTES * (1 + frac_second) + misses * 2 * BUCKET_BYTES + 9 * n
+        io = 5 if set32 else 9  # key in, (value and) found flag out
+        return hits * BUCKET_BYTES * (1 + frac_second) + misses * 2 * BUCKET_BYTES + io * n
     lk_ms = (ms[:, 2].mean() + ms[:, 4].mean()) / 2
     lk_bytes = (lookup_bytes(n_present) + lookup_bytes(n_present2)) / 2
     achieved = lk_bytes / (lk_ms * 1e-3) / 1e9
     traffic = None
     tfile = os.path.join(ROOT, "profiles", "lookup_bulk95_traffic.json")
-    if os.path.exists(tfile):
+    if os.path.exists(tfile) and not set32:
         rec = json.load(open(tfile))
         if rec.get("source_digest") == source_digest():
             traffic = rec.get("bytes_per_launch")
@@ -903,10 +912,11 @@ def run_bulk(args):
         "config": {
             "probe_both": args.probe_both,
             "workload": f"bulk build to 95% load, plain launch: 2^{args.keys_log2} unique uniform keys into "
-                        f"{nb} x {S}-slot buckets (FIXED), 2^{args.keys_log2} lookups at 50% hits, delete "
-                        f"2^{args.keys_log2 - 1}, re-lookup",
+                        f"{nb} x {slots}-slot buckets (FIXED"
+                        f"{', key-only set of 32-bit entries' if set32 else ''}), 2^{args.keys_log2} lookups at "
+                        f"50% hits, delete 2^{args.keys_log2 - 1}, re-lookup",
             "ops_per_step": ops_step,
-            "load_factor": round(n / (nb * S), 6),
+            "load_factor": round(n / (nb * slots), 6),
         },
         "phase_mops": {k: round(v, 1) for k, v in phase_mops.items()},
         "phase_ms": {p: round(float(ms[:, j].mean()), 4) for j, p in enumerate(phases)},
@@ -915,7 +925,7 @@ def run_bulk(args):
                                                  "full_chains")},
         "placement": {"first": first, "second": second, "overflow": overflow},
         "roofline": {
-            "kernel": "ops_kernel<16, lookup>",
+            "kernel": "set_ops_kernel<lookup>" if set32 else "ops_kernel<16, lookup>",
             "bound": "hbm",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,

@@ -106,6 +106,18 @@ typedef struct {
                                  need S = 16, FIXED addressing, probe_both = 0,
                                  plain launches (the executor and
                                  hive_placement refuse such tables) */
+  uint32_t entry_bits;        /* 64 (or 0, the default): 32-bit keys with
+                                 32-bit values packed in 64-bit words.  32: a
+                                 key-only set of 32-bit entries (Section
+                                 III-A), a 32-slot bucket being one 128-byte
+                                 line; needs slots_per_bucket = 32, FIXED
+                                 addressing, HIVE_PAIR_BITHASH, probe_both 0
+                                 and plain launches.  Insert adds the key (a
+                                 key already present is left as it is; d_vals
+                                 is not read), lookup writes found flags (no
+                                 values), delete as for 64-bit entries;
+                                 hive_dump writes each key as a word with
+                                 value 0 */
 } hive_config;
 
 enum { HIVE_PAIR_BITHASH = 0, HIVE_PAIR_CRC = 1, HIVE_PAIR_MURMUR = 2, HIVE_PAIR_TRIPLE = 3 };

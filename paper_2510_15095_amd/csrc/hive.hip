@@ -1573,7 +1573,9 @@ __global__ __launch_bounds__(BLOCK) void dump_kernel(const uint64_t *buckets, ui
 
 // Placement census: live bucket entries in their first candidate bucket and
 // in their second one (the two differ).
-__global__ __launch_bounds__(BLOCK) void placement_kernel(const uint64_t *buckets, uint32_t S, Ctl *ctl) {
+// SET32: buckets of 32-bit entries (the key itself; EMPTY is all ones).
+template <bool SET32>
+__global__ __launch_bounds__(BLOCK) void placement_kernel(const void *bucket_words, uint32_t S, Ctl *ctl) {
   __shared__ unsigned long long s_first, s_second;
   if (threadIdx.x == 0) s_first = s_second = 0;
   __syncthreads();
@@ -1583,7 +1585,15 @@ __global__ __launch_bounds__(BLOCK) void placement_kernel(const uint64_t *bucket
   const uint64_t stride = (uint64_t)gridDim.x * BLOCK;
   const uint64_t span = (n_slots + stride - 1) / stride * stride;
   for (uint64_t t = (uint64_t)blockIdx.x * BLOCK + threadIdx.x; t < span; t += stride) {
-    const uint64_t w = t < n_slots ? buckets[t] : EMPTY;
+    uint64_t w = EMPTY;
+    if (t < n_slots) {
+      if constexpr (SET32) {
+        const uint32_t x = ((const uint32_t *)bucket_words)[t];
+        w = x == 0xFFFFFFFFu ? EMPTY : x;
+      } else {
+        w = ((const uint64_t *)bucket_words)[t];
+      }
+    }
     const bool live = w != EMPTY;
     const bool first = live && address(geo, bithash1(key_of(w))) == (uint32_t)(t / S);
     const uint64_t mf = ballot(first), ms = ballot(live && !first);
@@ -2295,6 +2305,392 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
   }
 }
 
+// ---------------------------------------------------------------------------
+// 32-bit entries: a key-only set (Section III-A: with 32-bit entries a
+// 32-slot bucket is one 128-byte line).  The entry is the key itself; EMPTY
+// is 0xFFFFFFFF and a deleted stash or pending entry is 0 (both reserved
+// keys).  The steps are those of the 64-bit table: P1 hashes, probes the
+// first candidate (a 32-lane group per bucket, one 4-byte load per lane, two
+// buckets per wave-wide load), the second after a miss, then looks up,
+// deletes (one agent-scope atomic store of EMPTY) or inserts: a key already
+// present is left as it is (there is no value to replace), a new one claims
+// the lowest EMPTY slot of the emptier candidate by a 32-bit CAS; P3 runs
+// the bounded cuckoo chains one lane per item on fresh copies of whole
+// buckets, then the stash or the pending list.  FIXED addressing, BitHash1/2,
+// plain launches.
+// ---------------------------------------------------------------------------
+constexpr uint32_t EMPTY32 = 0xFFFFFFFFu;
+constexpr uint32_t TOMB32 = 0u;
+constexpr int SET_S = 32;        // slots per bucket
+constexpr int SET_CH = 16;       // wave-wide bucket loads in flight
+
+struct SetArgs {
+  uint32_t *buckets;
+  uint32_t *hint;
+  uint32_t *stash;
+  uint32_t *pending;
+  Ctl *ctl;
+  uint64_t *wl;  // eviction worklist (keys widened to 64 bits), NSHARD segments
+  uint64_t wl_seg_cap;
+  const uint64_t *dd;  // dedupe set, or null
+  uint64_t dd_mask;
+  const uint8_t *ops;
+  const uint32_t *keys;
+  uint8_t *flags_out;
+  uint64_t n;
+  uint64_t stash_cap, pending_cap;
+  uint32_t max_evictions;
+};
+
+__device__ __forceinline__ uint32_t cas32(uint32_t *p, uint32_t expected, uint32_t desired) {
+  __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+  return expected;
+}
+
+// Search of the stash (open-addressed, linear probing from mix32(key), ends
+// at EMPTY) and the pending list.
+__device__ __forceinline__ uint32_t *set_overflow_find(const SetArgs &a, uint64_t n_stash, uint64_t n_pend,
+                                                       uint32_t k) {
+  if (n_stash) {
+    const uint64_t mask = stash_slots_for(a.stash_cap) - 1;
+    for (uint64_t i = 0, p = mix32(k) & mask; i <= mask; ++i, p = (p + 1) & mask) {
+      const uint32_t x = a.stash[p];
+      if (x == EMPTY32) break;
+      if (x == k) return a.stash + p;
+    }
+  }
+  for (uint64_t p = 0; p < n_pend; ++p)
+    if (a.pending[p] == k) return a.pending + p;
+  return nullptr;
+}
+
+// One probe round: operations t < count have key keys[t] and bucket
+// bkts[t] (owner list[t], or t itself); each 32-lane group loads one bucket
+// per wave-wide load and publishes the match and EMPTY masks to the owner.
+// bkts[] holds 64 entries, padded from `count` on with a bucket loaded
+// anyway.
+__device__ __forceinline__ void set_probe_round(const uint32_t *__restrict__ buckets, const uint32_t *keys,
+                                                const uint32_t *bkts, const uint8_t *list, int count,
+                                                uint32_t *m_out, uint32_t *e_out, int g, int sl) {
+  for (int base = 0; base < count; base += 2 * SET_CH) {
+    uint32_t w[SET_CH];
+#pragma unroll
+    for (int j = 0; j < SET_CH; ++j) w[j] = buckets[(uint64_t)bkts[base + 2 * j + g] * SET_S + sl];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int j = 0; j < SET_CH; ++j) {
+      const int t = base + 2 * j + g;
+      const bool mine = t < count;
+      const uint32_t ko = keys[t];
+      const uint64_t mm = ballot(mine && ko != 0u && w[j] == ko);
+      const uint64_t ee = ballot(w[j] == EMPTY32);
+      if (mine && sl == 0) {
+        const int o = list ? list[t] : t;
+        m_out[o] = (uint32_t)(mm >> (g * 32));
+        e_out[o] = (uint32_t)(ee >> (g * 32));
+      }
+    }
+  }
+}
+
+template <uint32_t MODE>
+__global__ __launch_bounds__(BLOCK) void set_ops_kernel(SetArgs a) {
+  __shared__ uint32_t s_key[WAVES][64], s_b1[WAVES][64], s_k2[WAVES][64], s_b2[WAVES][64];
+  __shared__ uint8_t s_list[WAVES][64];
+  __shared__ uint32_t s_m[2][WAVES][64], s_e[2][WAVES][64];
+  const Geo geo = read_geo(a.ctl);
+  const uint64_t n_stash = min(ld_ctl(&a.ctl->stash_count), a.stash_cap);
+  const uint64_t n_pend = min(ld_ctl(&a.ctl->pending_count), a.pending_cap);
+  const bool overflow_used = (n_stash | n_pend) != 0;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int g = lane >> 5, sl = lane & 31;
+  const uint64_t ntiles = (a.n + BLOCK - 1) / BLOCK;
+  for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const uint64_t i = tile * BLOCK + threadIdx.x;
+    const bool active = i < a.n;
+    uint32_t op = OP_NONE, k = 0;
+    if (active) {
+      op = (MODE == OP_MIXED) ? (uint32_t)__builtin_nontemporal_load(&a.ops[i]) : MODE;
+      k = __builtin_nontemporal_load(&a.keys[i]);
+    }
+    const bool valid = active && op <= OP_LOOKUP && valid_key(k);
+    bool work = valid;
+    if (work && a.dd && op != OP_LOOKUP) work = dedupe_winner(a.dd, a.dd_mask, k, (uint32_t)i);
+    uint32_t c1 = 0, c2 = 0;
+    if (work) {
+      c1 = fastmod(bithash1(k), geo.magic, (uint32_t)geo.n_buckets);
+      c2 = fastmod(bithash2(k), geo.magic, (uint32_t)geo.n_buckets);
+    }
+    s_key[wv][lane] = work ? k : 0u;
+    s_b1[wv][lane] = c1;
+    wave_lds_sync();
+    set_probe_round(a.buckets, s_key[wv], s_b1[wv], nullptr, 64, s_m[0][wv], s_e[0][wv], g, sl);
+    wave_lds_sync();
+    const uint32_t m1 = s_m[0][wv][lane], e1 = s_e[0][wv][lane];
+    const bool need2 = work && m1 == 0 && c2 != c1;
+    const uint64_t need2_mask = ballot(need2);
+    const int n2 = __popcll(need2_mask);
+    compact_second(need2, need2_mask, n2, k, c2, c1, lane, s_k2[wv], s_b2[wv], s_list[wv]);
+    wave_lds_sync();
+    if (n2 > 0) set_probe_round(a.buckets, s_k2[wv], s_b2[wv], s_list[wv], n2, s_m[1][wv], s_e[1][wv], g, sl);
+    wave_lds_sync();
+    const uint32_t m2 = need2 ? s_m[1][wv][lane] : 0u, e2 = need2 ? s_e[1][wv][lane] : 0u;
+
+    uint8_t out_f = 0;
+    int dl = 0;
+    bool to_wl = false;
+    if (work) {
+      uint32_t *slot = nullptr;
+      bool in_bucket = false;
+      if (m1) {
+        slot = a.buckets + (uint64_t)c1 * SET_S + __builtin_ctz(m1);
+        in_bucket = true;
+      } else if (m2) {
+        slot = a.buckets + (uint64_t)c2 * SET_S + __builtin_ctz(m2);
+        in_bucket = true;
+      } else if (overflow_used && hinted(a.hint, c1, c2)) {
+        slot = set_overflow_find(a, n_stash, n_pend, k);
+      }
+      if (op == OP_LOOKUP) {
+        out_f = slot != nullptr;
+      } else if (op == OP_DELETE) {
+        if (slot && in_bucket) {
+          // an atomic store: claims of other XCDs change this line in the
+          // same launch (see the 64-bit table's delete)
+          __hip_atomic_store(slot, EMPTY32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          out_f = 1;
+          dl = -1;
+        } else if (slot && cas32(slot, k, TOMB32) == k) {
+          out_f = 1;
+          dl = -1;
+        }
+      } else if (!slot) {
+        // a new key: claim-then-commit in the emptier candidate first
+        dl = 1;
+        uint32_t f_first = e1, f_second = (c2 != c1) ? e2 : 0u, b_first = c1, b_second = c2;
+        if (__builtin_popcount(f_second) > __builtin_popcount(f_first)) {
+          const uint32_t tf = f_first;
+          f_first = f_second;
+          f_second = tf;
+          b_first = c2;
+          b_second = c1;
+        }
+        bool placed = false;
+        while (!placed && (f_first | f_second)) {
+          if (f_first == 0) {
+            f_first = f_second;
+            f_second = 0;
+            b_first = b_second;
+          }
+          const int s = __builtin_ctz(f_first);
+          if (cas32(a.buckets + (uint64_t)b_first * SET_S + s, EMPTY32, k) == EMPTY32)
+            placed = true;
+          else
+            f_first &= f_first - 1;
+        }
+        to_wl = !placed;
+      }
+    }
+    const uint64_t wl_mask = ballot(to_wl);
+    if (wl_mask) {
+      const int leader = __builtin_ctzll(wl_mask);
+      uint64_t base = 0;
+      if (lane == leader) base = wl_append(a.ctl, tile, (uint64_t)__popcll(wl_mask));
+      base = read_lane64(base, leader);
+      if (to_wl) a.wl[(tile % NSHARD) * a.wl_seg_cap + base + rank_below(wl_mask)] = k;
+    }
+    const uint64_t up = ballot(dl > 0), down = ballot(dl < 0), bad = ballot(active && !valid);
+    if (lane == 0) {
+      Shard *sh = shard_of(a.ctl, (tile * WAVES + wv) % NSHARD);
+      const int64_t d = (int64_t)__popcll(up) - (int64_t)__popcll(down);
+      if (d != 0) add64(&sh->live, (uint64_t)d);
+      if (bad) add64(&sh->invalid_keys, (uint64_t)__popcll(bad));
+    }
+    if (active && MODE != OP_INSERT && a.flags_out) __builtin_nontemporal_store(out_f, &a.flags_out[i]);
+  }
+}
+
+// A lane's fresh copy of a whole 32-slot bucket (128 bytes).
+__device__ __forceinline__ uint32_t load_set_bucket(const uint32_t *bkt, uint32_t *w) {
+  uint64_t x[16];
+  load_bucket16_fresh((const uint64_t *)bkt, x);
+  uint32_t free_mask = 0;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    w[2 * j] = (uint32_t)x[j];
+    w[2 * j + 1] = (uint32_t)(x[j] >> 32);
+  }
+#pragma unroll
+  for (int j = 0; j < SET_S; ++j) free_mask |= (uint32_t)(w[j] == EMPTY32) << j;
+  return free_mask;
+}
+
+__device__ __forceinline__ bool set_claim(uint32_t *bkt, uint32_t free_mask, uint32_t k) {
+  for (; free_mask; free_mask &= free_mask - 1)
+    if (cas32(bkt + __builtin_ctz(free_mask), EMPTY32, k) == EMPTY32) return true;
+  return false;
+}
+
+// Step 4: the first EMPTY or TOMB word of the key's stash run (given a
+// reserved position c < capacity), else the pending list.  Returns 0 stash
+// (EMPTY word), 3 stash (TOMB word), 1 pending, 2 lost.
+__device__ __forceinline__ int set_overflow_place(const SetArgs &a, const Geo &geo, uint32_t k, uint64_t c) {
+  int where = -1;
+  if (c < a.stash_cap) {
+    const uint64_t mask = stash_slots_for(a.stash_cap) - 1;
+    for (uint64_t i = 0, p = mix32(k) & mask; i <= mask; ++i, p = (p + 1) & mask) {
+      const uint32_t cur = cas32(a.stash + p, EMPTY32, k);
+      if (cur == EMPTY32) {
+        where = 0;
+        break;
+      }
+      if (cur == TOMB32 && cas32(a.stash + p, TOMB32, k) == TOMB32) {
+        where = 3;
+        break;
+      }
+    }
+  }
+  if (where < 0) {
+    const uint64_t p = add64(&a.ctl->pending_count, 1);
+    if (p < a.pending_cap) {
+      __hip_atomic_store(a.pending + p, k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      where = 1;
+    } else {
+      atomicOr(&a.ctl->error, ERR_PENDING_LOST);
+      where = 2;
+    }
+  }
+  set_hint(a.hint, fastmod(bithash1(k), geo.magic, (uint32_t)geo.n_buckets));
+  set_hint(a.hint, fastmod(bithash2(k), geo.magic, (uint32_t)geo.n_buckets));
+  return where;
+}
+
+// P3 of the set: one lane per worklist item, as the 64-bit table's 16-slot
+// eviction shape (Algorithm 3 with a pseudo-random victim slot).
+__global__ __launch_bounds__(BLOCK) void set_evict_kernel(SetArgs a) {
+  __shared__ uint64_t pre[NSHARD + 1];
+  wl_prefix(a.ctl, pre);
+  const uint64_t cnt = pre[NSHARD];
+  if (cnt == 0) return;
+  const Geo geo = read_geo(a.ctl);
+  const bool unreserved = ld_ctl(&a.ctl->stash_count) + cnt <= a.stash_cap;
+  const int lane = threadIdx.x & 63;
+  const uint64_t stride = (uint64_t)gridDim.x * BLOCK;
+  const uint32_t nb = (uint32_t)geo.n_buckets;
+  uint64_t n_evict = 0, n_full = 0, n_side = 0, n_fresh = 0;
+  for (uint64_t base = (uint64_t)blockIdx.x * BLOCK + (threadIdx.x & ~63u); base < cnt; base += stride) {
+    const uint64_t t = base + lane;
+    bool placed = true;
+    uint32_t k = 0;
+    if (t < cnt) {
+      k = (uint32_t)a.wl[wl_slot(pre, t, a.wl_seg_cap)];
+      const uint32_t c1 = fastmod(bithash1(k), geo.magic, nb), c2 = fastmod(bithash2(k), geo.magic, nb);
+      uint32_t w[SET_S];
+      const uint32_t f1 = load_set_bucket(a.buckets + (uint64_t)c1 * SET_S, w);
+      const uint32_t f2 = c2 != c1 ? load_set_bucket(a.buckets + (uint64_t)c2 * SET_S, w) : 0u;
+      if (__builtin_popcount(f2) > __builtin_popcount(f1))
+        placed = set_claim(a.buckets + (uint64_t)c2 * SET_S, f2, k) ||
+                 set_claim(a.buckets + (uint64_t)c1 * SET_S, f1, k);
+      else
+        placed = set_claim(a.buckets + (uint64_t)c1 * SET_S, f1, k) ||
+                 set_claim(a.buckets + (uint64_t)c2 * SET_S, f2, k);
+      uint32_t b = c1;
+      for (uint32_t kick = 1; kick <= a.max_evictions && !placed; ++kick) {
+        uint32_t *bkt = a.buckets + (uint64_t)b * SET_S;
+        const uint32_t fm = load_set_bucket(bkt, w);
+        if (set_claim(bkt, fm, k)) {
+          placed = true;
+          break;
+        }
+        const int s0 = (int)(mix32(k ^ (kick * 0x9E3779B9u)) & (SET_S - 1));
+        uint32_t ws = 0;
+#pragma unroll
+        for (int j = 0; j < SET_S; ++j)
+          if (j == s0) ws = w[j];
+        if (cas32(bkt + s0, ws, k) != ws) continue;  // the slot changed: count the round, keep the key
+        if (ws == EMPTY32) {
+          placed = true;
+          break;
+        }
+        ++n_evict;
+        k = ws;
+        const uint32_t v1 = fastmod(bithash1(k), geo.magic, nb), v2 = fastmod(bithash2(k), geo.magic, nb);
+        b = (b == v1) ? v2 : v1;
+      }
+    }
+    const bool push = !placed;
+    const uint64_t pm = ballot(push);
+    if (pm) {
+      const int leader = __builtin_ctzll(pm);
+      uint64_t room = 0;
+      if (!unreserved) {
+        if (lane == leader) {
+          const uint64_t nn = (uint64_t)__popcll(pm);
+          room = load_fresh(&a.ctl->stash_count) < a.stash_cap ? add64(&a.ctl->stash_count, nn) : a.stash_cap;
+        }
+        room = read_lane64(room, leader);
+      }
+      if (push) {
+        ++n_full;
+        const int where = set_overflow_place(a, geo, k, room + rank_below(pm));
+        n_side += (where == 0 || where == 3) ? 1 : where == 1 ? (1ull << 32) : 0;
+        n_fresh += where == 0;
+      }
+    }
+  }
+  const uint64_t e = wave_sum64(n_evict), f = wave_sum64(n_full), sd = wave_sum64(n_side), fr = wave_sum64(n_fresh);
+  if (lane == 0 && (e | f | sd)) {
+    Shard *sh = shard_of(a.ctl, ((uint64_t)blockIdx.x * WAVES + (threadIdx.x >> 6)) % NSHARD);
+    if (e) add64(&sh->evictions, e);
+    if (f) add64(&sh->full_chains, f);
+    if ((uint32_t)sd) add64(&sh->stash_inserts, (uint32_t)sd);
+    if (fr && unreserved) add64(&sh->stash_unreserved, fr);
+    if (sd >> 32) add64(&sh->pending_inserts, sd >> 32);
+  }
+}
+
+// Every live key of the set as a 64-bit word (value half 0) with its place.
+__global__ __launch_bounds__(BLOCK) void set_dump_kernel(const uint32_t *buckets, const uint32_t *stash,
+                                                         const uint32_t *pending, Ctl *ctl, uint64_t stash_cap,
+                                                         uint64_t pending_cap, uint64_t *out, int64_t *where,
+                                                         uint64_t cap) {
+  const uint64_t nb = ctl->n_buckets;
+  const uint64_t n_stash = min(ctl->stash_count, stash_cap) ? stash_slots_for(stash_cap) : 0;
+  const uint64_t n_pend = min(ctl->pending_count, pending_cap);
+  const uint64_t n_slots = nb * SET_S, total = n_slots + n_stash + n_pend;
+  const uint64_t stride = (uint64_t)gridDim.x * BLOCK;
+  const uint64_t span = (total + stride - 1) / stride * stride;
+  const int lane = threadIdx.x & 63;
+  for (uint64_t t = (uint64_t)blockIdx.x * BLOCK + threadIdx.x; t < span; t += stride) {
+    uint32_t w = EMPTY32;
+    int64_t pl = 0;
+    if (t < n_slots) {
+      w = buckets[t];
+      pl = (int64_t)(t / SET_S);
+    } else if (t < n_slots + n_stash) {
+      w = stash[t - n_slots];
+      pl = -1;
+    } else if (t < total) {
+      w = pending[t - n_slots - n_stash];
+      pl = -2;
+    }
+    const bool live = t < total && w != EMPTY32 && w != TOMB32;
+    const uint64_t m = ballot(live);
+    if (m) {
+      const int leader = __builtin_ctzll(m);
+      uint64_t base = 0;
+      if (lane == leader) base = add64(&ctl->dump_count, (uint64_t)__popcll(m));
+      base = read_lane64(base, leader);
+      const uint64_t pos = base + rank_below(m);
+      if (live && pos < cap) {
+        out[pos] = w;
+        if (where) where[pos] = pl;
+      }
+    }
+  }
+}
+
 }  // namespace hive
 
 // ===========================================================================
@@ -2305,6 +2701,7 @@ using namespace hive;
 struct hive_table {
   hive_config cfg;
   uint32_t S;
+  uint32_t entry_bytes = 8;  // 4: a key-only set of 32-bit entries
   uint64_t initial_buckets;
   uint64_t max_buckets;
   uint64_t stash_cap, pending_cap;
@@ -2420,9 +2817,9 @@ static uint64_t hint_words(uint64_t buckets) { return (buckets + 31) / 32; }
 
 static hive_status reset_table(hive_table *h, hipStream_t st) {
   hive_status s;
-  if ((s = fill_u64(h->d_buckets, h->max_buckets * h->S, EMPTY, st)) != HIVE_OK) return s;
+  if ((s = fill_u64(h->d_buckets, h->max_buckets * h->S * h->entry_bytes / 8, EMPTY, st)) != HIVE_OK) return s;
   if ((s = fill_u32(h->d_hint, hint_words(h->max_buckets), 0u, st)) != HIVE_OK) return s;
-  if ((s = fill_u64(h->d_stash, stash_slots_for(h->stash_cap), EMPTY, st)) != HIVE_OK) return s;
+  if ((s = fill_u64(h->d_stash, stash_slots_for(h->stash_cap) * h->entry_bytes / 8, EMPTY, st)) != HIVE_OK) return s;
   if ((s = fill_u64((uint64_t *)shard_of(h->d_ctl, 0), NSHARD * SHARD_STRIDE / 8, 0, st)) != HIVE_OK) return s;
   hipLaunchKernelGGL(ctl_reset_kernel, dim3(1), dim3(1), 0, st, h->d_ctl, initial_ctl(h));
   return launch_check();
@@ -2739,7 +3136,7 @@ static hive_status run_batch(hive_t h, uint32_t mode, const uint8_t *d_ops, cons
                              uint8_t *d_flags_out, void *stream, bool no_alloc = false) {
   if (!h || (n > 0 && !d_keys)) return HIVE_ERR_ARG;
   if (n >= 0xFFFFFFFFull) return HIVE_ERR_ARG;  // batch indices are 32-bit in the dedupe set
-  if (mode == OP_INSERT && n > 0 && !d_vals) return HIVE_ERR_ARG;
+  if (mode == OP_INSERT && n > 0 && !d_vals && h->entry_bytes == 8) return HIVE_ERR_ARG;  // sets read no values
   if (mode == OP_MIXED && n > 0 && !d_ops) return HIVE_ERR_ARG;
   if (flags & ~(uint32_t)HIVE_UNIQUE) return HIVE_ERR_ARG;
   hipStream_t st = (hipStream_t)stream;
@@ -2806,6 +3203,29 @@ static hive_status run_batch(hive_t h, uint32_t mode, const uint8_t *d_ops, cons
     a.dd = dd;
     a.dd_mask = cap - 1;
   }
+  if (h->entry_bytes == 4) {
+    SetArgs sa{(uint32_t *)h->d_buckets, h->d_hint, (uint32_t *)h->d_stash, (uint32_t *)h->d_pending, h->d_ctl,
+               h->d_wl, h->wl_seg_cap, a.dd, a.dd_mask, d_ops, d_keys, d_flags_out, n, h->stash_cap, h->pending_cap,
+               h->cfg.max_evictions};
+    phase_mark(h, HIVE_PHASE_PROBE, st);
+    const dim3 grid((unsigned)std::min<uint64_t>((n + BLOCK - 1) / BLOCK, OPS_GRID));
+    switch (mode) {
+      case OP_INSERT: hipLaunchKernelGGL(set_ops_kernel<OP_INSERT>, grid, dim3(BLOCK), 0, st, sa); break;
+      case OP_DELETE: hipLaunchKernelGGL(set_ops_kernel<OP_DELETE>, grid, dim3(BLOCK), 0, st, sa); break;
+      case OP_LOOKUP: hipLaunchKernelGGL(set_ops_kernel<OP_LOOKUP>, grid, dim3(BLOCK), 0, st, sa); break;
+      default: hipLaunchKernelGGL(set_ops_kernel<OP_MIXED>, grid, dim3(BLOCK), 0, st, sa); break;
+    }
+    if (mode == OP_INSERT || mode == OP_MIXED) {
+      phase_mark(h, HIVE_PHASE_EVICT, st);
+      hipLaunchKernelGGL(set_evict_kernel, dim3(grid_for(n, BLOCK, EVICT_GRID)), dim3(BLOCK), 0, st, sa);
+    }
+    if (mode != OP_LOOKUP) {
+      phase_mark(h, HIVE_PHASE_FINISH, st);
+      launch_finish(h, st);
+    }
+    phase_mark(h, -1, st);
+    return launch_check();
+  }
   const bool linear = h->cfg.addressing == HIVE_LINEAR;
   if (linear && h->cfg.pre_expand && (mode == OP_INSERT || mode == OP_MIXED)) {
     // grow before the batch so that live + (inserts of the batch) fits
@@ -2867,6 +3287,11 @@ hive_status hive_create(const hive_config *cfg_in, uint64_t initial_buckets, voi
   if (S != 16 && S != 32 && S != 64) return HIVE_ERR_ARG;
   if (cfg.addressing != HIVE_FIXED && cfg.addressing != HIVE_LINEAR) return HIVE_ERR_ARG;
   if (cfg.hash_pair > HIVE_PAIR_TRIPLE) return HIVE_ERR_ARG;
+  if (cfg.entry_bits != 0 && cfg.entry_bits != 64 && cfg.entry_bits != 32) return HIVE_ERR_ARG;
+  const bool set32 = cfg.entry_bits == 32;
+  // key-only sets: 32 slots of 4 bytes (one 128-byte line), FIXED, BitHash1/2
+  if (set32 && (S != 32 || cfg.addressing != HIVE_FIXED || cfg.hash_pair != HIVE_PAIR_BITHASH || cfg.probe_both))
+    return HIVE_ERR_ARG;
   // only 16-slot FIXED tables on plain launches have the other hash pairs
   if (cfg.hash_pair != HIVE_PAIR_BITHASH && (S != 16 || cfg.addressing != HIVE_FIXED || cfg.probe_both))
     return HIVE_ERR_ARG;
@@ -2887,6 +3312,7 @@ hive_status hive_create(const hive_config *cfg_in, uint64_t initial_buckets, voi
   hive_table *h = new (std::nothrow) hive_table();
   if (!h) return HIVE_ERR_OOM;
   h->S = S;
+  h->entry_bytes = set32 ? 4 : 8;
   h->initial_buckets = initial_buckets;
   h->max_buckets = max_b;
   // default: 1% of the slots of the largest table (the arena)
@@ -2897,10 +3323,10 @@ hive_status hive_create(const hive_config *cfg_in, uint64_t initial_buckets, voi
   cfg.max_buckets = max_b;
   h->cfg = cfg;
   hive_status s = HIVE_OK;
-  if ((s = alloc((void **)&h->d_buckets, max_b * S * 8, &h->bytes)) != HIVE_OK ||
+  if ((s = alloc((void **)&h->d_buckets, max_b * S * h->entry_bytes, &h->bytes)) != HIVE_OK ||
       (s = alloc((void **)&h->d_hint, hint_words(max_b) * 4, &h->bytes)) != HIVE_OK ||
-      (s = alloc((void **)&h->d_stash, stash_slots_for(h->stash_cap) * 8, &h->bytes)) != HIVE_OK ||
-      (s = alloc((void **)&h->d_pending, h->pending_cap * 8, &h->bytes)) != HIVE_OK ||
+      (s = alloc((void **)&h->d_stash, stash_slots_for(h->stash_cap) * h->entry_bytes, &h->bytes)) != HIVE_OK ||
+      (s = alloc((void **)&h->d_pending, h->pending_cap * h->entry_bytes, &h->bytes)) != HIVE_OK ||
       (s = alloc((void **)&h->d_ctl, CTL_BYTES, &h->bytes)) != HIVE_OK) {
     free_table(h);
     return s;
@@ -2975,14 +3401,14 @@ hive_status hive_delete_batch(hive_t h, const uint32_t *d_keys, uint64_t n, uint
 
 hive_status hive_mixed_batch(hive_t h, const uint8_t *d_ops, const uint32_t *d_keys, const uint32_t *d_vals,
                              uint64_t n, uint32_t flags, uint32_t *d_vals_out, uint8_t *d_flags_out, void *stream) {
-  if (h && n > 0 && !d_vals) return HIVE_ERR_ARG;  // inserts read their values
+  if (h && n > 0 && !d_vals && h->entry_bytes == 8) return HIVE_ERR_ARG;  // inserts read their values
   return run_batch(h, OP_MIXED, d_ops, d_keys, d_vals, n, flags, d_vals_out, d_flags_out, stream);
 }
 
 hive_status hive_mixed_batch_noalloc(hive_t h, const uint8_t *d_ops, const uint32_t *d_keys, const uint32_t *d_vals,
                                      uint64_t n, uint32_t flags, uint32_t *d_vals_out, uint8_t *d_flags_out,
                                      void *stream) {
-  if (h && n > 0 && !d_vals) return HIVE_ERR_ARG;
+  if (h && n > 0 && !d_vals && h->entry_bytes == 8) return HIVE_ERR_ARG;
   return run_batch(h, OP_MIXED, d_ops, d_keys, d_vals, n, flags, d_vals_out, d_flags_out, stream, true);
 }
 
@@ -3034,8 +3460,13 @@ hive_status hive_dump(hive_t h, uint64_t *d_words, int64_t *d_where, uint64_t ca
   hipLaunchKernelGGL(ctl_zero_dump_kernel, dim3(1), dim3(1), 0, st, h->d_ctl);
   hive_status s = launch_check();
   if (s != HIVE_OK) return s;
-  hipLaunchKernelGGL(dump_kernel, dim3(2048), dim3(BLOCK), 0, st, h->d_buckets, h->S, h->d_stash, h->d_pending,
-                     h->d_ctl, h->stash_cap, h->pending_cap, d_words, d_where, capacity);
+  if (h->entry_bytes == 4)
+    hipLaunchKernelGGL(set_dump_kernel, dim3(2048), dim3(BLOCK), 0, st, (const uint32_t *)h->d_buckets,
+                       (const uint32_t *)h->d_stash, (const uint32_t *)h->d_pending, h->d_ctl, h->stash_cap,
+                       h->pending_cap, d_words, d_where, capacity);
+  else
+    hipLaunchKernelGGL(dump_kernel, dim3(2048), dim3(BLOCK), 0, st, h->d_buckets, h->S, h->d_stash, h->d_pending,
+                       h->d_ctl, h->stash_cap, h->pending_cap, d_words, d_where, capacity);
   if ((s = launch_check()) != HIVE_OK) return s;
   Ctl c;
   HIP_OK(hipMemcpyAsync(&c, h->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
@@ -3052,7 +3483,12 @@ hive_status hive_placement(hive_t h, uint64_t *out, void *stream) {
   hipLaunchKernelGGL(ctl_zero_placement_kernel, dim3(1), dim3(1), 0, st, h->d_ctl);
   hive_status s = launch_check();
   if (s != HIVE_OK) return s;
-  hipLaunchKernelGGL(placement_kernel, dim3(2048), dim3(BLOCK), 0, st, h->d_buckets, h->S, h->d_ctl);
+  if (h->entry_bytes == 4)
+    hipLaunchKernelGGL(placement_kernel<true>, dim3(2048), dim3(BLOCK), 0, st, (const void *)h->d_buckets, h->S,
+                       h->d_ctl);
+  else
+    hipLaunchKernelGGL(placement_kernel<false>, dim3(2048), dim3(BLOCK), 0, st, (const void *)h->d_buckets, h->S,
+                       h->d_ctl);
   if ((s = launch_check()) != HIVE_OK) return s;
   Ctl c;
   HIP_OK(hipMemcpyAsync(&c, h->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
@@ -3194,7 +3630,8 @@ fail:
 hive_status hive_drain_submit(hive_drain_t d, hive_t h, const hive_batch_desc *b, uint64_t *ticket) {
   if (!d || !h || !b || !ticket) return HIVE_ERR_ARG;
   if (h->S != d->S) return HIVE_ERR_ARG;
-  if (h->cfg.hash_pair != HIVE_PAIR_BITHASH) return HIVE_ERR_ARG;  // the executor runs BitHash1/2 tables only
+  // the executor runs BitHash1/2 tables of 64-bit entries only
+  if (h->cfg.hash_pair != HIVE_PAIR_BITHASH || h->entry_bytes != 8) return HIVE_ERR_ARG;
   if (b->op_mode > HIVE_OP_MIXED) return HIVE_ERR_ARG;
   if (b->n > 0 && !b->d_keys) return HIVE_ERR_ARG;
   if ((b->op_mode == HIVE_OP_INSERT || b->op_mode == HIVE_OP_MIXED) && b->n > 0 && !b->d_vals) return HIVE_ERR_ARG;

@@ -47,6 +47,7 @@ class hive_config(ctypes.Structure):
         ("max_batch", ctypes.c_uint64),
         ("probe_both", ctypes.c_uint32),
         ("hash_pair", ctypes.c_uint32),
+        ("entry_bits", ctypes.c_uint32),
     ]
 
 
@@ -192,8 +193,9 @@ def hive_destroy(h) -> None:
 def hive_insert_batch(h, keys, vals, flags: int = 0, stream=None) -> None:
     import torch
     n = keys.numel()
-    _check(_lib.hive_insert_batch(h, _dev(keys, torch.uint32, "keys"), _dev(vals, torch.uint32, "vals", n), n,
-                                  flags, _stream_ptr(stream)), "hive_insert_batch")
+    _check(_lib.hive_insert_batch(h, _dev(keys, torch.uint32, "keys"),
+                                  _dev(vals, torch.uint32, "vals", n, optional=True), n, flags,
+                                  _stream_ptr(stream)), "hive_insert_batch")
 
 
 def hive_lookup_batch(h, keys, vals_out=None, found_out=None, stream=None) -> None:
@@ -217,7 +219,7 @@ def hive_mixed_batch(h, ops, keys, vals, vals_out=None, flags_out=None, flags: i
     import torch
     n = keys.numel()
     _check(_lib.hive_mixed_batch(h, _dev(ops, torch.uint8, "ops", n), _dev(keys, torch.uint32, "keys"),
-                                 _dev(vals, torch.uint32, "vals", n), n, flags,
+                                 _dev(vals, torch.uint32, "vals", n, optional=True), n, flags,
                                  _dev(vals_out, torch.uint32, "vals_out", n, optional=True),
                                  _dev(flags_out, torch.uint8, "flags_out", n, optional=True),
                                  _stream_ptr(stream)), "hive_mixed_batch")

@@ -91,6 +91,9 @@ def test_config_defaults(H):
     # hash choices other than BitHash1/2: 16-slot FIXED tables, plain probing only
     dict(hash_pair=4), dict(hash_pair=1, addressing=1), dict(hash_pair=2, slots_per_bucket=32),
     dict(hash_pair=1, probe_both=1), dict(hash_pair=3, addressing=1), dict(hash_pair=3, slots_per_bucket=64),
+    # 32-bit entries: 32-slot FIXED BitHash tables only
+    dict(entry_bits=32), dict(entry_bits=48), dict(entry_bits=32, slots_per_bucket=32, addressing=1),
+    dict(entry_bits=32, slots_per_bucket=32, hash_pair=2),
 ])
 def test_create_rejects_bad_config_without_touching_the_device(H, bad):
     cfg = H.hive_config_default(**bad)
