@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true", help="suite: skip the mixed sub-record")
     ap.add_argument("--no-served", action="store_true", help="suite: skip the served sub-record")
     ap.add_argument("--mixed-steps", type=int, default=2, help="suite: timed passes over the mixed batches")
+    ap.add_argument("--blocks-per-cu", type=int, default=-1,
+                    help="persistent executor blocks per CU (0: as many as fit; -1: the autotuned value, else 1)")
     ap.add_argument("--tables", type=int, default=256, help="served: tables")
     ap.add_argument("--table-log2-max", type=float, default=24, help="served: largest table (log2 keys)")
     ap.add_argument("--requests", type=int, default=20000, help="served: requests")
@@ -119,7 +121,8 @@ def main():
         tuned = {"resize": autotune.load("resize"), "executor": autotune.load("executor")}
     if not args.resize_k:
         args.resize_k = (tuned.get("resize") or {}).get("resize_k", 1024)
-    args.blocks_per_cu = (tuned.get("executor") or {}).get("blocks_per_cu", 1)
+    if args.blocks_per_cu < 0:
+        args.blocks_per_cu = (tuned.get("executor") or {}).get("blocks_per_cu", 1)
     run = {"suite": run_suite, "bulk": run_bulk, "mixed": run_mixed, "resize": run_resize, "served": run_served,
            "breakdown": run_breakdown, "hashes": run_hashes, "gather": run_gather}[args.workload]
     out = run(args)
@@ -390,7 +393,7 @@ def run_served(args):
     print(f"[bench] {len(reqs)} requests on {len(specs)} tables generated", file=sys.stderr, flush=True)
     budget = sv.footprint_bytes(specs)
     srv = sv.Server(specs, budget, max_request=1 << int(np.ceil(args.request_log2)), ring=1024, streams=8,
-                    blocks_per_cu=args.blocks_per_cu or 1)
+                    blocks_per_cu=args.blocks_per_cu)
     res = {}
     validate = {}
     expect = served_expectation(specs, reqs) if args.validate else None
