@@ -68,6 +68,10 @@ def parse():
     ap.add_argument("--autotune", action="store_true", help="run the autotuner first and use its picks")
     ap.add_argument("--probe-both", type=int, default=-1,
                     help="bulk: 1 = lookups/deletes probe both candidates in one round (-1: autotuned, else 0)")
+    ap.add_argument("--probe-tuning", type=int, default=-1,
+                    help="bulk/mixed: probe-kernel variant word (hive_config.probe_tuning; -1: autotuned, else 0)")
+    ap.add_argument("--probe-grid", type=int, default=-1,
+                    help="bulk/mixed: blocks per probe launch cap (0: 32768; -1: autotuned, else 0)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="bulk: first run one plain device copy of this many MiB (a known-size dispatch that "
                          "scales HBM byte counters read by a profiler)")
@@ -114,15 +118,22 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     tuned = {}
-    if args.workload in ("suite", "mixed", "resize", "served"):
+    if args.workload in ("suite", "bulk", "mixed", "resize", "served"):
         from paper_2510_15095_amd import autotune
         if args.autotune:
-            autotune.tune(args.workload if args.workload != "suite" else "mixed")
-        tuned = {"resize": autotune.load("resize"), "executor": autotune.load("executor")}
+            autotune.tune({"suite": "all", "bulk": "probe"}.get(args.workload, args.workload))
+        tuned = {sec: autotune.load(sec) for sec in ("resize", "executor", "probe", "probe_kernel")}
     if not args.resize_k:
         args.resize_k = (tuned.get("resize") or {}).get("resize_k", 1024)
     if args.blocks_per_cu < 0:
         args.blocks_per_cu = (tuned.get("executor") or {}).get("blocks_per_cu", 1)
+    if args.probe_both < 0:
+        args.probe_both = (tuned.get("probe") or {}).get("probe_both", 0)
+    pk = tuned.get("probe_kernel") or {}
+    if args.probe_tuning < 0:
+        args.probe_tuning = 0 if args.probe_both else pk.get("probe_tuning", 0)
+    if args.probe_grid < 0:
+        args.probe_grid = pk.get("probe_grid", 0)
     run = {"suite": run_suite, "bulk": run_bulk, "mixed": run_mixed, "resize": run_resize, "served": run_served,
            "breakdown": run_breakdown, "hashes": run_hashes, "gather": run_gather}[args.workload]
     out = run(args)
@@ -190,7 +201,8 @@ def mixed_setup(args):
         "vout": torch.empty(n_ops, dtype=torch.uint32, device=dev),
         "fout": torch.empty(n_ops, dtype=torch.uint8, device=dev),
         "table": H.Table(MIXED_NB0, addressing=H.HIVE_LINEAR, max_buckets=4 * MIXED_NB0, lf_expand_pct=95,
-                         post_policy=1, resize_k=args.resize_k, max_batch=n_ops),
+                         post_policy=1, resize_k=args.resize_k, max_batch=n_ops, probe_tuning=args.probe_tuning,
+                         probe_grid=args.probe_grid),
     }
     print(f"[bench] mixed inputs ready: {nbat} batches of {n_ops} ops", file=sys.stderr, flush=True)
     return st
@@ -325,7 +337,8 @@ def run_mixed(args):
     ms_step = float(ms.sum(axis=1).mean())
     rec = base_record(args, nbat * n_ops / (ms_step * 1e-3) / 1e6, ms_step,
                       mixed_label(args) + f"; {args.executor} executor",
-                      {"ops_per_step": nbat * n_ops, "batches": nbat, "resize_k": args.resize_k})
+                      {"ops_per_step": nbat * n_ops, "batches": nbat, "resize_k": args.resize_k,
+                       "probe_tuning": args.probe_tuning, "probe_grid": args.probe_grid})
     rec["batch_ms"] = {"mean": round(float(ms.mean()), 4), "p50": round(float(np.percentile(ms, 50)), 4),
                        "p99": round(float(np.percentile(ms, 99)), 4)}
     if args.validate:
@@ -342,7 +355,8 @@ def mixed_subrecord(args):
     steps, warmup = max(1, args.mixed_steps), 1
     out = {"config": {"workload": mixed_label(args), "batches": args.batches,
                       "ops_per_batch": 1 << args.batch_log2, "resize_k": args.resize_k,
-                      "persistent_blocks_per_cu": args.blocks_per_cu, "steps": steps, "warmup": warmup}}
+                      "persistent_blocks_per_cu": args.blocks_per_cu, "probe_tuning": args.probe_tuning,
+                      "probe_grid": args.probe_grid, "steps": steps, "warmup": warmup}}
     times = {}
     for ex in ("plain", "persistent"):
         ms = mixed_time(args, st, ex, steps, warmup)
@@ -815,11 +829,10 @@ def run_bulk(args):
     vout = torch.empty(n, dtype=torch.uint32, device=dev)
     fout = torch.empty(n, dtype=torch.uint8, device=dev)
     dout = torch.empty(dk.numel(), dtype=torch.uint8, device=dev)
-    if args.probe_both < 0:
-        from paper_2510_15095_amd import autotune
-        args.probe_both = (autotune.load("probe") or {}).get("probe_both", 0)
-    t = (H.Table(nb, slots_per_bucket=32, entry_bits=32, max_evictions=8, max_batch=n) if set32 else
-         H.Table(nb, slots_per_bucket=S, max_evictions=8, max_batch=n, probe_both=args.probe_both))
+    t = (H.Table(nb, slots_per_bucket=32, entry_bits=32, max_evictions=8, max_batch=n, probe_grid=args.probe_grid)
+         if set32 else
+         H.Table(nb, slots_per_bucket=S, max_evictions=8, max_batch=n, probe_both=args.probe_both,
+                 probe_tuning=args.probe_tuning, probe_grid=args.probe_grid))
     if set32:
         vals = None
     n_present = int((w["query_idx"] < n).sum())
@@ -914,6 +927,8 @@ def run_bulk(args):
         "data": "synthetic",
         "config": {
             "probe_both": args.probe_both,
+            "probe_tuning": 0 if set32 else args.probe_tuning,
+            "probe_grid": args.probe_grid,
             "workload": f"bulk build to 95% load, plain launch: 2^{args.keys_log2} unique uniform keys into "
                         f"{nb} x {slots}-slot buckets (FIXED"
                         f"{', key-only set of 32-bit entries' if set32 else ''}), 2^{args.keys_log2} lookups at "

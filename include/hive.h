@@ -118,6 +118,23 @@ typedef struct {
                                  values), delete as for 64-bit entries;
                                  hive_dump writes each key as a word with
                                  value 0 */
+  uint32_t probe_tuning;      /* probe-kernel variant per operation kind,
+                                 four bits each: bits 0-3 insert batches,
+                                 4-7 delete, 8-11 lookup, 12-15 mixed.  A
+                                 variant sets the occupancy target (waves
+                                 per SIMD) and the bucket loads in flight
+                                 per wave and probe chunk: 0 (default) 4 and
+                                 16; 1: 6 and 16; 2: 8 and 8; 3: 6 and 8;
+                                 4: 8 and 4.  Inserts take 0, 3 or 4 (their
+                                 fused round holds twice the loads).
+                                 Non-zero needs S = 16, HIVE_PAIR_BITHASH,
+                                 probe_both 0 and 64-bit entries; results
+                                 are the same for every variant.  Picked by
+                                 measurement (the package's autotuner);
+                                 HIVE_ERR_ARG for anything else */
+  uint32_t probe_grid;        /* most blocks of 256 operations one probe
+                                 launch starts; each block strides over the
+                                 batch's tiles (0 = 32768, at most 2^20) */
 } hive_config;
 
 enum { HIVE_PAIR_BITHASH = 0, HIVE_PAIR_CRC = 1, HIVE_PAIR_MURMUR = 2, HIVE_PAIR_TRIPLE = 3 };

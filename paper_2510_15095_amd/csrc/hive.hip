@@ -346,22 +346,23 @@ __device__ __forceinline__ bool dedupe_winner(const uint64_t *dd, uint64_t mask,
 // bucket (the caller pads them), so idle group slots re-load a line that is
 // loaded anyway, their result is ignored, and the loads need neither
 // control flow nor clamped indices.
-template <int S>
+// PIPE: wave-wide loads in flight per chunk (the probe's pipelining depth).
+template <int S, int PIPE = Traits<S>::CH>
 __device__ __forceinline__ void probe_round(const uint64_t *__restrict__ buckets, const uint32_t *keys,
                                             const uint32_t *bkts, const uint8_t *list, int count,
                                             typename Traits<S>::Mask *m_out, typename Traits<S>::Mask *e_out,
                                             uint64_t *w_out, int g, int sl) {
   using T = Traits<S>;
   using Mask = typename T::Mask;
-  for (int base = 0; base < count; base += T::OPS_PER_CHUNK) {
-    uint64_t w[T::CH];
+  for (int base = 0; base < count; base += PIPE * T::G) {
+    uint64_t w[PIPE];
 #pragma unroll
-    for (int j = 0; j < T::CH; ++j) w[j] = buckets[(uint64_t)bkts[base + j * T::G + g] * S + sl];
+    for (int j = 0; j < PIPE; ++j) w[j] = buckets[(uint64_t)bkts[base + j * T::G + g] * S + sl];
     // keep the operands of the consume loop from being read (and held in
     // registers) while the loads are in flight
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int j = 0; j < T::CH; ++j) {
+    for (int j = 0; j < PIPE; ++j) {
       const int t = base + j * T::G + g;
       const bool mine = t < count;
       const uint32_t ko = keys[t];
@@ -381,10 +382,10 @@ __device__ __forceinline__ void probe_round(const uint64_t *__restrict__ buckets
   }
 }
 
-// Both probe rounds of an insert batch at once (S = 16): 16 loads for the
-// first candidates of the wave's 64 operations and up to 16 for the second
-// candidates are in flight together.
-template <int S>
+// Both probe rounds of an insert batch at once (S = 16): PIPE loads for the
+// first candidates and PIPE for the second are in flight together (with
+// PIPE = 16 one chunk covers the wave's 64 operations).
+template <int S, int PIPE = Traits<S>::CH>
 __device__ __forceinline__ void probe_round_pair(const uint64_t *__restrict__ buckets, const uint32_t *keys1,
                                                  const uint32_t *bkts1, typename Traits<S>::Mask *m1_out,
                                                  typename Traits<S>::Mask *e1_out, uint64_t *w1_out,
@@ -393,16 +394,17 @@ __device__ __forceinline__ void probe_round_pair(const uint64_t *__restrict__ bu
                                                  typename Traits<S>::Mask *e2_out, uint64_t *w2_out, int g, int sl) {
   using T = Traits<S>;
   using Mask = typename T::Mask;
-  static_assert(S == 16, "the fused round covers one chunk per candidate");
-  uint64_t wa[T::CH], wb[T::CH];
+  static_assert(S == 16, "the fused round is built for 16-slot buckets");
+  for (int base = 0; base < 64; base += PIPE * T::G) {
+  uint64_t wa[PIPE], wb[PIPE];
 #pragma unroll
-  for (int j = 0; j < T::CH; ++j) wa[j] = buckets[(uint64_t)bkts1[j * T::G + g] * S + sl];
+  for (int j = 0; j < PIPE; ++j) wa[j] = buckets[(uint64_t)bkts1[base + j * T::G + g] * S + sl];
 #pragma unroll
-  for (int j = 0; j < T::CH; ++j) wb[j] = buckets[(uint64_t)bkts2[j * T::G + g] * S + sl];
+  for (int j = 0; j < PIPE; ++j) wb[j] = buckets[(uint64_t)bkts2[base + j * T::G + g] * S + sl];
   __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-  for (int j = 0; j < T::CH; ++j) {
-    const int t = j * T::G + g;
+  for (int j = 0; j < PIPE; ++j) {
+    const int t = base + j * T::G + g;
     const uint32_t ko = keys1[t];
     const uint64_t mm = ballot(ko != 0u && key_of(wa[j]) == ko);
     const uint64_t ee = ballot(wa[j] == EMPTY);
@@ -414,8 +416,8 @@ __device__ __forceinline__ void probe_round_pair(const uint64_t *__restrict__ bu
     if (gm != 0 && sl == ctz_mask(gm)) w1_out[t] = wa[j];
   }
 #pragma unroll
-  for (int j = 0; j < T::CH; ++j) {
-    const int t = j * T::G + g;
+  for (int j = 0; j < PIPE; ++j) {
+    const int t = base + j * T::G + g;
     const bool mine = t < count2;
     const uint32_t ko = mine ? keys2[t] : 0u;
     const uint64_t mm = ballot(mine && ko != 0u && key_of(wb[j]) == ko);
@@ -429,6 +431,7 @@ __device__ __forceinline__ void probe_round_pair(const uint64_t *__restrict__ bu
       }
       if (gm != 0 && sl == ctz_mask(gm)) w2_out[o] = wb[j];
     }
+  }
   }
 }
 
@@ -520,7 +523,7 @@ __device__ __forceinline__ OpsView read_view(const Ctl *c, uint64_t stash_cap, u
 // PAIR: the table's candidate hashes (HashPair); BitHash1/2 by default.
 // With three candidates (PAIR_TRIPLE) the third is probed in a third round
 // by the operations that found their key in neither of the first two.
-template <int S, uint32_t MODE, bool BOTH, int PAIR = PAIR_BITHASH>
+template <int S, uint32_t MODE, bool BOTH, int PAIR = PAIR_BITHASH, int PIPE = Traits<S>::CH>
 __device__ __forceinline__ void ops_tile(const OpsArgs &a, const OpsView &view, uint64_t tile,
                                          OpsShared<S, PairArity<PAIR>::D> &sh) {
   using T = Traits<S>;
@@ -576,13 +579,13 @@ __device__ __forceinline__ void ops_tile(const OpsArgs &a, const OpsView &view, 
     const int n2 = __popcll(need2_mask);
     compact_second(need2, need2_mask, n2, k, c2, c1, lane, s_k2[wv], s_b2[wv], s_list[wv]);
     wave_lds_sync();
-    probe_round_pair<S>(a.buckets, s_key[wv], s_b1[wv], s_m[0][wv], s_e[0][wv], s_w[0][wv], s_k2[wv], s_b2[wv],
-                        s_list[wv], n2, s_m[1][wv], s_e[1][wv], s_w[1][wv], g, sl);
+    probe_round_pair<S, PIPE>(a.buckets, s_key[wv], s_b1[wv], s_m[0][wv], s_e[0][wv], s_w[0][wv], s_k2[wv],
+                              s_b2[wv], s_list[wv], n2, s_m[1][wv], s_e[1][wv], s_w[1][wv], g, sl);
     wave_lds_sync();
     m1 = s_m[0][wv][lane];
   } else {
     // round 1: first candidate of every operation
-    probe_round<S>(a.buckets, s_key[wv], s_b1[wv], nullptr, 64, s_m[0][wv], s_e[0][wv], s_w[0][wv], g, sl);
+    probe_round<S, PIPE>(a.buckets, s_key[wv], s_b1[wv], nullptr, 64, s_m[0][wv], s_e[0][wv], s_w[0][wv], g, sl);
     wave_lds_sync();
     m1 = s_m[0][wv][lane];
     need2 = work && m1 == 0 && c2 != c1;
@@ -592,7 +595,8 @@ __device__ __forceinline__ void ops_tile(const OpsArgs &a, const OpsView &view, 
     wave_lds_sync();
     // round 2: second candidate of the operations that missed in the first
     if (n2 > 0)
-      probe_round<S>(a.buckets, s_k2[wv], s_b2[wv], s_list[wv], n2, s_m[1][wv], s_e[1][wv], s_w[1][wv], g, sl);
+      probe_round<S, PIPE>(a.buckets, s_k2[wv], s_b2[wv], s_list[wv], n2, s_m[1][wv], s_e[1][wv], s_w[1][wv], g,
+                           sl);
     wave_lds_sync();
   }
   const Mask e1 = s_e[0][wv][lane];
@@ -610,7 +614,8 @@ __device__ __forceinline__ void ops_tile(const OpsArgs &a, const OpsView &view, 
     compact_second(need3, need3_mask, n3, k, c3, c1, lane, s_k2[wv], s_b2[wv], s_list[wv]);
     wave_lds_sync();
     if (n3 > 0)
-      probe_round<S>(a.buckets, s_k2[wv], s_b2[wv], s_list[wv], n3, s_m[2][wv], s_e[2][wv], s_w[2][wv], g, sl);
+      probe_round<S, PIPE>(a.buckets, s_k2[wv], s_b2[wv], s_list[wv], n3, s_m[2][wv], s_e[2][wv], s_w[2][wv], g,
+                           sl);
     wave_lds_sync();
     if (need3) {
       m3 = s_m[2][wv][lane];
@@ -760,13 +765,17 @@ __device__ __forceinline__ void ops_tile(const OpsArgs &a, const OpsView &view, 
   }
 }
 
-template <int S, uint32_t MODE, bool BOTH, int PAIR = PAIR_BITHASH>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(OPS_WAVES_PER_EU))) void ops_kernel(
-    OpsArgs a) {
+// WPE: the occupancy target (waves per SIMD) the registers are allocated
+// for; PIPE: loads in flight per probe chunk.  Tuned variants of the
+// 16-slot BitHash kernels are picked per table (hive_config.probe_tuning).
+template <int S, uint32_t MODE, bool BOTH, int PAIR = PAIR_BITHASH, int WPE = OPS_WAVES_PER_EU,
+          int PIPE = Traits<S>::CH>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) void ops_kernel(OpsArgs a) {
   __shared__ OpsShared<S, PairArity<PAIR>::D> sh;
   const OpsView view = read_view(a.ctl, a.stash_cap, a.pending_cap);
   const uint64_t ntiles = (a.n + BLOCK - 1) / BLOCK;
-  for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) ops_tile<S, MODE, BOTH, PAIR>(a, view, tile, sh);
+  for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
+    ops_tile<S, MODE, BOTH, PAIR, PIPE>(a, view, tile, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -2899,20 +2908,50 @@ static hive_status ensure_scratch(hive_table *h, uint64_t n, uint64_t n_dd, hipS
   return HIVE_OK;
 }
 
-template <int S, uint32_t MODE, bool BOTH, int PAIR = PAIR_BITHASH>
-static void launch_ops(const OpsArgs &a, hipStream_t st) {
-  const uint64_t blocks = std::min<uint64_t>((a.n + BLOCK - 1) / BLOCK, OPS_GRID);
-  hipLaunchKernelGGL((ops_kernel<S, MODE, BOTH, PAIR>), dim3((unsigned)blocks), dim3(BLOCK), 0, st, a);
+// Probe-kernel variants a table may select per operation kind
+// (hive_config.probe_tuning): occupancy target in waves per SIMD and loads
+// in flight per probe chunk.  Variant 0 is the default; the others exist
+// for 16-slot BitHash tables probing the second candidate after a miss
+// (probe_both = 0).  The insert kernel's fused round holds twice the loads,
+// so variants 1 and 2 would spill registers there and are refused for
+// inserts (kInsertTunings).
+struct ProbeTuning {
+  int waves_per_simd, loads_in_flight;
+};
+static constexpr ProbeTuning kProbeTunings[] = {{OPS_WAVES_PER_EU, 16}, {6, 16}, {8, 8}, {6, 8}, {8, 4}};
+static constexpr int kNumProbeTunings = sizeof(kProbeTunings) / sizeof(kProbeTunings[0]);
+static constexpr uint32_t kInsertTunings = (1u << 0) | (1u << 3) | (1u << 4);
+
+template <int S, uint32_t MODE, bool BOTH, int PAIR = PAIR_BITHASH, int V = 0>
+static void launch_ops(const OpsArgs &a, uint32_t grid_cap, hipStream_t st) {
+  constexpr ProbeTuning t = kProbeTunings[V];
+  const uint64_t blocks = std::min<uint64_t>((a.n + BLOCK - 1) / BLOCK, grid_cap ? grid_cap : OPS_GRID);
+  hipLaunchKernelGGL((ops_kernel<S, MODE, BOTH, PAIR, t.waves_per_simd, t.loads_in_flight>),
+                     dim3((unsigned)blocks), dim3(BLOCK), 0, st, a);
+}
+
+template <int S, bool BOTH, int PAIR = PAIR_BITHASH, int V = 0>
+static void launch_ops_mode_v(uint32_t mode, const OpsArgs &a, uint32_t grid_cap, hipStream_t st) {
+  switch (mode) {
+    case OP_INSERT: launch_ops<S, OP_INSERT, BOTH, PAIR, V>(a, grid_cap, st); break;
+    case OP_DELETE: launch_ops<S, OP_DELETE, BOTH, PAIR, V>(a, grid_cap, st); break;
+    case OP_LOOKUP: launch_ops<S, OP_LOOKUP, BOTH, PAIR, V>(a, grid_cap, st); break;
+    default: launch_ops<S, OP_MIXED, BOTH, PAIR, V>(a, grid_cap, st); break;
+  }
 }
 
 template <int S, bool BOTH, int PAIR = PAIR_BITHASH>
-static void launch_ops_mode(uint32_t mode, const OpsArgs &a, hipStream_t st) {
-  switch (mode) {
-    case OP_INSERT: launch_ops<S, OP_INSERT, BOTH, PAIR>(a, st); break;
-    case OP_DELETE: launch_ops<S, OP_DELETE, BOTH, PAIR>(a, st); break;
-    case OP_LOOKUP: launch_ops<S, OP_LOOKUP, BOTH, PAIR>(a, st); break;
-    default: launch_ops<S, OP_MIXED, BOTH, PAIR>(a, st); break;
+static void launch_ops_mode(uint32_t mode, const OpsArgs &a, const hive_config &cfg, hipStream_t st) {
+  if constexpr (S == 16 && !BOTH && PAIR == PAIR_BITHASH) {
+    switch ((cfg.probe_tuning >> (4 * std::min<uint32_t>(mode, OP_MIXED))) & 15u) {
+      case 1: launch_ops_mode_v<S, BOTH, PAIR, 1>(mode, a, cfg.probe_grid, st); return;
+      case 2: launch_ops_mode_v<S, BOTH, PAIR, 2>(mode, a, cfg.probe_grid, st); return;
+      case 3: launch_ops_mode_v<S, BOTH, PAIR, 3>(mode, a, cfg.probe_grid, st); return;
+      case 4: launch_ops_mode_v<S, BOTH, PAIR, 4>(mode, a, cfg.probe_grid, st); return;
+      default: break;
+    }
   }
+  launch_ops_mode_v<S, BOTH, PAIR, 0>(mode, a, cfg.probe_grid, st);
 }
 
 // The eviction grid: one group per item up to EVICT_GRID blocks (chains are
@@ -3208,7 +3247,8 @@ static hive_status run_batch(hive_t h, uint32_t mode, const uint8_t *d_ops, cons
                h->d_wl, h->wl_seg_cap, a.dd, a.dd_mask, d_ops, d_keys, d_flags_out, n, h->stash_cap, h->pending_cap,
                h->cfg.max_evictions};
     phase_mark(h, HIVE_PHASE_PROBE, st);
-    const dim3 grid((unsigned)std::min<uint64_t>((n + BLOCK - 1) / BLOCK, OPS_GRID));
+    const uint64_t cap = h->cfg.probe_grid ? h->cfg.probe_grid : OPS_GRID;
+    const dim3 grid((unsigned)std::min<uint64_t>((n + BLOCK - 1) / BLOCK, cap));
     switch (mode) {
       case OP_INSERT: hipLaunchKernelGGL(set_ops_kernel<OP_INSERT>, grid, dim3(BLOCK), 0, st, sa); break;
       case OP_DELETE: hipLaunchKernelGGL(set_ops_kernel<OP_DELETE>, grid, dim3(BLOCK), 0, st, sa); break;
@@ -3235,18 +3275,18 @@ static hive_status run_batch(hive_t h, uint32_t mode, const uint8_t *d_ops, cons
   switch (h->S) {
     case 16:
       if (h->cfg.hash_pair == PAIR_CRC)
-        launch_ops_mode<16, false, PAIR_CRC>(mode, a, st);
+        launch_ops_mode<16, false, PAIR_CRC>(mode, a, h->cfg, st);
       else if (h->cfg.hash_pair == PAIR_MURMUR)
-        launch_ops_mode<16, false, PAIR_MURMUR>(mode, a, st);
+        launch_ops_mode<16, false, PAIR_MURMUR>(mode, a, h->cfg, st);
       else if (h->cfg.hash_pair == PAIR_TRIPLE)
-        launch_ops_mode<16, false, PAIR_TRIPLE>(mode, a, st);
+        launch_ops_mode<16, false, PAIR_TRIPLE>(mode, a, h->cfg, st);
       else if (h->cfg.probe_both)
-        launch_ops_mode<16, true>(mode, a, st);
+        launch_ops_mode<16, true>(mode, a, h->cfg, st);
       else
-        launch_ops_mode<16, false>(mode, a, st);
+        launch_ops_mode<16, false>(mode, a, h->cfg, st);
       break;
-    case 32: launch_ops_mode<32, false>(mode, a, st); break;
-    default: launch_ops_mode<64, false>(mode, a, st); break;
+    case 32: launch_ops_mode<32, false>(mode, a, h->cfg, st); break;
+    default: launch_ops_mode<64, false>(mode, a, h->cfg, st); break;
   }
   if ((s = launch_check()) != HIVE_OK) return s;
   if (mode == OP_INSERT || mode == OP_MIXED) {
@@ -3295,6 +3335,14 @@ hive_status hive_create(const hive_config *cfg_in, uint64_t initial_buckets, voi
   // only 16-slot FIXED tables on plain launches have the other hash pairs
   if (cfg.hash_pair != HIVE_PAIR_BITHASH && (S != 16 || cfg.addressing != HIVE_FIXED || cfg.probe_both))
     return HIVE_ERR_ARG;
+  // probe_tuning: one variant per operation kind (insert, delete, lookup,
+  // mixed), four bits each
+  if ((cfg.probe_tuning >> 16) != 0 || !((kInsertTunings >> (cfg.probe_tuning & 15u)) & 1u) ||
+      (cfg.probe_tuning && (S != 16 || cfg.hash_pair != HIVE_PAIR_BITHASH || cfg.probe_both || set32)))
+    return HIVE_ERR_ARG;
+  for (int kind = 0; kind < 4; ++kind)
+    if (((cfg.probe_tuning >> (4 * kind)) & 15u) >= (uint32_t)kNumProbeTunings) return HIVE_ERR_ARG;
+  if (cfg.probe_grid > (1u << 20)) return HIVE_ERR_ARG;
   if (initial_buckets < 1) return HIVE_ERR_ARG;
   if (cfg.max_evictions > 1024) return HIVE_ERR_ARG;
   if (cfg.lf_expand_pct == 0 || cfg.lf_expand_pct > 100 || cfg.lf_contract_pct >= cfg.lf_expand_pct)

@@ -48,6 +48,8 @@ class hive_config(ctypes.Structure):
         ("probe_both", ctypes.c_uint32),
         ("hash_pair", ctypes.c_uint32),
         ("entry_bits", ctypes.c_uint32),
+        ("probe_tuning", ctypes.c_uint32),
+        ("probe_grid", ctypes.c_uint32),
     ]
 
 
@@ -166,6 +168,19 @@ def _check(status: int, where: str, warn_ok: bool = False) -> int:
     if status < 0 or (status > 0 and not warn_ok):
         raise HiveError(status, where)
     return status
+
+
+# probe-kernel variants (hive_config.probe_tuning): (waves per SIMD, loads in
+# flight) per variant index; inserts take the ones in PROBE_INSERT_VARIANTS
+PROBE_VARIANTS = ((4, 16), (6, 16), (8, 8), (6, 8), (8, 4))
+PROBE_INSERT_VARIANTS = (0, 3, 4)
+PROBE_KINDS = ("insert", "delete", "lookup", "mixed")
+
+
+def probe_tuning(insert: int = 0, delete: int = 0, lookup: int = 0, mixed: int = 0) -> int:
+    """Pack one probe-kernel variant per operation kind into the
+    hive_config.probe_tuning word."""
+    return insert | delete << 4 | lookup << 8 | mixed << 12
 
 
 # ----------------------------------------------------------- C ABI mirrors

@@ -94,6 +94,12 @@ def test_config_defaults(H):
     # 32-bit entries: 32-slot FIXED BitHash tables only
     dict(entry_bits=32), dict(entry_bits=48), dict(entry_bits=32, slots_per_bucket=32, addressing=1),
     dict(entry_bits=32, slots_per_bucket=32, hash_pair=2),
+    # probe-kernel variants: 16-slot BitHash tables without probe_both only;
+    # inserts refuse the variants that would spill; unknown variants and bits
+    dict(probe_tuning=1), dict(probe_tuning=2), dict(probe_tuning=5 << 8), dict(probe_tuning=1 << 16),
+    dict(probe_tuning=3 << 4, slots_per_bucket=32), dict(probe_tuning=3, hash_pair=3),
+    dict(probe_tuning=3 << 12, probe_both=1), dict(probe_tuning=3, entry_bits=32, slots_per_bucket=32),
+    dict(probe_grid=(1 << 20) + 1),
 ])
 def test_create_rejects_bad_config_without_touching_the_device(H, bad):
     cfg = H.hive_config_default(**bad)

@@ -77,11 +77,11 @@ def host(t):
     return t.cpu().numpy()
 
 
-def policy_buckets(nb, live, extra, max_b):
-    """Bucket count after the expansion rule of Section IV-C: split K pairs
+def policy_buckets(nb, live, extra, max_b, k=K):
+    """Bucket count after the expansion rule of Section IV-C: split k pairs
     at a time while (live + extra) exceeds LF_E% of the slots."""
     while (live + extra) * 100 > LF_E * nb * S and nb < max_b:
-        nb = min(nb + K, max_b)
+        nb = min(nb + k, max_b)
     return nb
 
 
@@ -98,16 +98,22 @@ def test_mixed_config_full_size(H, rule, path):
     pre_keys, batches = data()
     max_b = 4 * NB0
     pre_rule = rule == "pre"
+    # the resize step, probe-kernel variants and grid cap the benchmark
+    # launches with
+    from paper_2510_15095_amd import autotune
+    pk = autotune.load("probe_kernel") or {}
+    k = (autotune.load("resize") or {}).get("resize_k", K)
     t = H.Table(NB0, addressing=H.HIVE_LINEAR, max_buckets=max_b, lf_expand_pct=LF_E, pre_expand=int(pre_rule),
-                post_policy=1, resize_k=K, max_batch=max(SIZES))
+                post_policy=1, resize_k=k, max_batch=max(SIZES), probe_tuning=pk.get("probe_tuning", 0),
+                probe_grid=pk.get("probe_grid", 0))
     o1 = oracle.O1(1 << 25)
     case(f"mixed config {rule}/{path}: prefill 2^24 keys")
     t.insert(dev(pre_keys), dev(wl.values_for(pre_keys)), flags=H.HIVE_UNIQUE)
     o1.insert(pre_keys, wl.values_for(pre_keys))
     st = t.stats()
     assert st["status"] == H.HIVE_OK and st["live"] == N_PRE, st
-    nb = policy_buckets(NB0, 0, N_PRE, max_b) if pre_rule else NB0
-    nb = policy_buckets(nb, N_PRE, 0, max_b)
+    nb = policy_buckets(NB0, 0, N_PRE, max_b, k) if pre_rule else NB0
+    nb = policy_buckets(nb, N_PRE, 0, max_b, k)
     check_geometry(st, nb)
     expected, drained_big = [], False
     stash_before = st["stash_count"]
@@ -116,13 +122,13 @@ def test_mixed_config_full_size(H, rule, path):
             case(f"mixed config {rule}/plain: batch {b} of {mb['ops'].size} ops")
             n_ins = int((mb["ops"] == wl.OP_INSERT).sum())
             if pre_rule:
-                nb = policy_buckets(nb, len(o1), n_ins, max_b)
+                nb = policy_buckets(nb, len(o1), n_ins, max_b, k)
             v, f = t.mixed(dev(mb["ops"]), dev(mb["keys"]), dev(mb["vals"]))
             ov, of = o1.apply(mb["ops"], mb["keys"], mb["vals"])
             assert np.array_equal(host(f), of), f"flags differ in batch {b}"
             assert np.array_equal(host(v), ov), f"values differ in batch {b}"
             nb_before = nb
-            nb = policy_buckets(nb, len(o1), 0, max_b)
+            nb = policy_buckets(nb, len(o1), 0, max_b, k)
             st = t.stats()
             print(f"batch {b}: live {st['live']} buckets {st['n_buckets']} stash {st['stash_count']} "
                   f"pending {st['pending_count']} evict items {st['evict_items']}", flush=True)
@@ -158,12 +164,12 @@ def test_mixed_config_full_size(H, rule, path):
         for b, mb in enumerate(batches):
             n_ins = int((mb["ops"] == wl.OP_INSERT).sum())
             if pre_rule:
-                nb = policy_buckets(nb, len(o1), n_ins, max_b)
+                nb = policy_buckets(nb, len(o1), n_ins, max_b, k)
             ov, of = o1.apply(mb["ops"], mb["keys"], mb["vals"])
             assert np.array_equal(host(outs[b][1]), of), f"flags differ in batch {b}"
             assert np.array_equal(host(outs[b][0]), ov), f"values differ in batch {b}"
             assert int(live_after[b]) == len(o1)
-            nb = policy_buckets(nb, len(o1), 0, max_b)
+            nb = policy_buckets(nb, len(o1), 0, max_b, k)
             expected.append(nb)
         H.hive_drain_destroy(d)
         assert nb_after1 == expected[1]

@@ -423,12 +423,12 @@ def test_bulk_95pct_reduced(H, probe_both):
     run_bulk(H, 1 << 20, seed=2, probe_both=probe_both)
 
 
-def run_bulk(H, n_keys, seed, probe_both=0):
+def run_bulk(H, n_keys, seed, probe_both=0, **cfg):
     S = 16
     nb = int(np.ceil(n_keys / (0.95 * S)))
-    case(f"bulk n={n_keys} buckets={nb} probe_both={probe_both}")
+    case(f"bulk n={n_keys} buckets={nb} probe_both={probe_both} {cfg}")
     w = wl.bulk_workload(seed, n_keys)
-    t = H.Table(nb, probe_both=probe_both)
+    t = H.Table(nb, probe_both=probe_both, **cfg)
     t.insert(dev(w["ins_keys"]), dev(w["ins_vals"]), flags=H.HIVE_UNIQUE)
     st = t.stats()
     assert st["live"] == n_keys and st["status"] == H.HIVE_OK, st
@@ -463,6 +463,24 @@ def test_bulk_95pct_full_size(H):
     checked against the generator's closed-form expectation."""
     st = run_bulk(H, 1 << 26, seed=2)
     print("bulk 2^26 stats:", st)
+
+
+def tuned_probe_cfg():
+    """The probe-kernel variant word and grid cap the benchmark launches
+    with (the autotuner's picks for this GPU), or a non-default variant of
+    every kind when none are recorded."""
+    from paper_2510_15095_amd import autotune
+    from paper_2510_15095_amd import hive
+    pk = autotune.load("probe_kernel") or {}
+    tuning = pk.get("probe_tuning", 0) or hive.probe_tuning(4, 2, 2, 2)
+    return dict(probe_tuning=tuning, probe_grid=pk.get("probe_grid", 0))
+
+
+def test_bulk_95pct_full_size_tuned_probe(H):
+    """The same full-size sequence with the probe-kernel variants and grid
+    cap the benchmark runs."""
+    st = run_bulk(H, 1 << 26, seed=2, **tuned_probe_cfg())
+    print("bulk 2^26 tuned stats:", st)
 
 
 def test_bulk_launches_striding_over_tiles_with_ragged_tails(H):

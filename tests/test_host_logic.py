@@ -72,6 +72,7 @@ def test_autotune_cache_roundtrip(tmp_path, monkeypatch):
     path = tmp_path / "tuned.json"
     monkeypatch.setenv("HIVE_TUNE_CACHE", str(path))
     monkeypatch.setattr(autotune, "gpu_arch", lambda: "gfx950")
+    monkeypatch.setattr(autotune, "SHIPPED_DIR", str(tmp_path / "none"))
     assert autotune.load("resize") is None
     path.write_text(json.dumps({"gfx950": {"resize": {"resize_k": 256}},
                                 "gfx942": {"resize": {"resize_k": 64}}}))
@@ -79,3 +80,32 @@ def test_autotune_cache_roundtrip(tmp_path, monkeypatch):
     assert autotune.load("executor") is None
     path.write_text("not json")
     assert autotune.load("resize") is None
+
+
+def test_autotune_falls_back_to_shipped_values(tmp_path, monkeypatch):
+    """Without a cache on this machine, load() returns the values shipped for
+    the architecture; a cached section takes precedence.  The shipped probe
+    word is one the library accepts (one known variant per kind, inserts
+    only the variants without register spills)."""
+    from paper_2510_15095_amd import autotune
+    from paper_2510_15095_amd import hive as H
+    monkeypatch.setenv("HIVE_TUNE_CACHE", str(tmp_path / "absent.json"))
+    monkeypatch.setattr(autotune, "gpu_arch", lambda: "gfx950")
+    pk = autotune.load("probe_kernel")
+    assert pk is not None and 0 <= pk["probe_grid"] <= 1 << 20
+    word = pk["probe_tuning"]
+    nib = [(word >> (4 * i)) & 15 for i in range(4)]
+    assert word >> 16 == 0 and nib[0] in H.PROBE_INSERT_VARIANTS and all(x < len(H.PROBE_VARIANTS) for x in nib)
+    assert [tuple(pk["variants"][k]) for k in H.PROBE_KINDS] == [H.PROBE_VARIANTS[x] for x in nib]
+    assert autotune.load("resize")["resize_k"] >= 1
+    (tmp_path / "absent.json").write_text(json.dumps({"gfx950": {"resize": {"resize_k": 64}}}))
+    assert autotune.load("resize") == {"resize_k": 64}
+    monkeypatch.setattr(autotune, "gpu_arch", lambda: "gfx90a")
+    assert autotune.load("probe_kernel") is None
+
+
+def test_autotune_keeps_default_within_margin():
+    from paper_2510_15095_amd import autotune
+    assert autotune._pick({0: 100.0, 1: 101.9, 2: 99.0}, 0) == 0
+    assert autotune._pick({0: 100.0, 1: 102.1, 2: 103.0}, 0) == 2
+    assert autotune._pick({16: 50.0, 32: 40.0}, 16) == 16
