@@ -62,7 +62,8 @@ constexpr int RESIZE_GRID = 2048; // blocks of a resize pass (grid-stride over p
 // per block, measured over 2,048 .. 65,536 blocks: the launch pays less
 // block setup, such as the coherent read of the control line)
 constexpr uint64_t OPS_GRID = 32768;
-constexpr int DRAIN_GRID = 256;
+constexpr int DRAIN_GRID = 2048;
+constexpr int DRAIN_WORDS = 8;  // stash words per thread and trip of the drain
 #ifndef OPS_WAVES_PER_EU
 #define OPS_WAVES_PER_EU 4  // occupancy target of the probe kernel (waves per SIMD)
 #endif
@@ -212,14 +213,12 @@ __global__ __launch_bounds__(BLOCK) void fill_u32_kernel(uint32_t *p, uint64_t n
 // set.  Plain loads come first: a key already present costs no CAS, and an
 // index that cannot win costs no max/min atomic (a stale load is only ever
 // an older value, which would already beat the index, so the skip is safe).
-__device__ __forceinline__ void dedupe_record(uint64_t *dd, uint64_t mask, uint32_t op, uint32_t k, uint64_t e) {
-  uint64_t s = mix32(k) & mask;
+// Settle record e of key k whose claim of slot s found `cur` (not EMPTY):
+// the same key keeps the larger insert index or the smaller delete index;
+// another key sends the record on along the probe sequence.
+__device__ __forceinline__ void dedupe_settle(uint64_t *dd, uint64_t mask, uint32_t op, uint32_t k, uint64_t e,
+                                              uint64_t s, uint64_t cur) {
   for (uint64_t probe = 0; probe <= mask; ++probe) {
-    uint64_t cur = dd[s];
-    if (cur == EMPTY) {
-      cur = cas64(&dd[s], EMPTY, e);
-      if (cur == EMPTY) return;
-    }
     if ((uint32_t)(cur >> 32) == k) {
       if (op == OP_INSERT) {
         if (cur < e) __hip_atomic_fetch_max(&dd[s], e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -229,7 +228,22 @@ __device__ __forceinline__ void dedupe_record(uint64_t *dd, uint64_t mask, uint3
       return;
     }
     s = (s + 1) & mask;
+    cur = dd[s];
+    if (cur == EMPTY) {
+      cur = cas64(&dd[s], EMPTY, e);
+      if (cur == EMPTY) return;
+    }
   }
+}
+
+__device__ __forceinline__ void dedupe_record(uint64_t *dd, uint64_t mask, uint32_t op, uint32_t k, uint64_t e) {
+  const uint64_t s = mix32(k) & mask;
+  uint64_t cur = dd[s];
+  if (cur == EMPTY) {
+    cur = cas64(&dd[s], EMPTY, e);
+    if (cur == EMPTY) return;
+  }
+  dedupe_settle(dd, mask, op, k, e, s, cur);
 }
 
 __device__ __forceinline__ void dedupe_insert(uint64_t *dd, uint64_t mask, uint32_t op, const uint32_t *keys,
@@ -283,16 +297,23 @@ __global__ __launch_bounds__(BLOCK) void dedupe_build_kernel(uint64_t *dd, uint6
     op = OP_DELETE;
     chunk = blockIdx.x - nch;
   }
-  for (int j = threadIdx.x; j < DD_LDS; j += BLOCK) tab[j] = EMPTY;
-  __syncthreads();
   const uint64_t base = chunk * DD_CHUNK;
+  // the chunk's operands first, all loads in flight together
+  uint32_t kk[DD_PER_THREAD];
+  bool take[DD_PER_THREAD];
 #pragma unroll
   for (int j = 0; j < DD_PER_THREAD; ++j) {
     const uint64_t i = base + (uint64_t)j * BLOCK + threadIdx.x;
-    if (i >= n || (mode == OP_MIXED && ops[i] != op)) continue;
-    const uint32_t k = keys[i];
-    if (!valid_key(k)) continue;
-    const uint64_t e = ((uint64_t)k << 32) | (uint32_t)i;
+    take[j] = i < n && (mode != OP_MIXED || ops[i] == op);
+    kk[j] = i < n ? keys[i] : 0u;
+  }
+  for (int j = threadIdx.x; j < DD_LDS; j += BLOCK) tab[j] = EMPTY;
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < DD_PER_THREAD; ++j) {
+    const uint32_t k = kk[j];
+    if (!take[j] || !valid_key(k)) continue;
+    const uint64_t e = ((uint64_t)k << 32) | (uint32_t)(base + (uint64_t)j * BLOCK + threadIdx.x);
     for (uint32_t s = mix32(k) & (DD_LDS - 1);; s = (s + 1) & (DD_LDS - 1)) {
       uint64_t cur = tab[s];
       if (cur == EMPTY) {
@@ -309,10 +330,54 @@ __global__ __launch_bounds__(BLOCK) void dedupe_build_kernel(uint64_t *dd, uint6
     }
   }
   __syncthreads();
-  for (int j = threadIdx.x; j < DD_LDS; j += BLOCK) {
-    const uint64_t e = tab[j];
-    if (e != EMPTY) dedupe_record(dd, mask, op, (uint32_t)(e >> 32), e);
+  // compact the chunk's distinct keys to the front of the table (wave by
+  // wave, rows in order), so that each thread then records at most
+  // DD_PER_THREAD of them instead of visiting DD_LDS / BLOCK mostly empty
+  // slots with a dependent load and claim each
+  constexpr int ROWS = DD_LDS / BLOCK;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  uint64_t row[ROWS];
+  uint32_t rank[ROWS];
+  uint32_t mine = 0;
+#pragma unroll
+  for (int r = 0; r < ROWS; ++r) {
+    row[r] = tab[r * BLOCK + threadIdx.x];
+    const uint64_t m = ballot(row[r] != EMPTY);
+    rank[r] = mine + rank_below(m);
+    mine += (uint32_t)__popcll(m);
   }
+  __syncthreads();  // every wave holds its rows in registers: tab may be overwritten
+  // the waves' counts go to the table's last words (a chunk has at most
+  // DD_CHUNK = DD_LDS / 2 distinct keys, so the compacted list stays clear
+  // of them), keeping the block's LDS at 32 KiB (five blocks per CU)
+  static_assert(DD_CHUNK + WAVES <= DD_LDS, "wave counts overlap the compacted list");
+  if (lane == 0) tab[DD_LDS - 1 - wv] = mine;
+  __syncthreads();
+  uint32_t off = 0, cnt = 0;
+#pragma unroll
+  for (int w = 0; w < WAVES; ++w) {
+    const uint32_t c = (uint32_t)tab[DD_LDS - 1 - w];
+    off += w < wv ? c : 0u;
+    cnt += c;
+  }
+#pragma unroll
+  for (int r = 0; r < ROWS; ++r)
+    if (row[r] != EMPTY) tab[off + rank[r]] = row[r];
+  __syncthreads();
+  // record: every claim of a thread's entries in flight together, then the
+  // entries whose first slot was taken settle one by one
+  uint64_t ent[DD_PER_THREAD], got[DD_PER_THREAD], slot[DD_PER_THREAD];
+#pragma unroll
+  for (int r = 0; r < DD_PER_THREAD; ++r) {
+    const uint32_t q = (uint32_t)r * BLOCK + threadIdx.x;
+    ent[r] = q < cnt ? tab[q] : EMPTY;
+    slot[r] = mix32((uint32_t)(ent[r] >> 32)) & mask;
+  }
+#pragma unroll
+  for (int r = 0; r < DD_PER_THREAD; ++r) got[r] = ent[r] != EMPTY ? cas64(&dd[slot[r]], EMPTY, ent[r]) : EMPTY;
+#pragma unroll
+  for (int r = 0; r < DD_PER_THREAD; ++r)
+    if (got[r] != EMPTY) dedupe_settle(dd, mask, op, (uint32_t)(ent[r] >> 32), ent[r], slot[r], got[r]);
 }
 
 // Blocks of the plain path's dedupe build for a batch of n operations.
@@ -396,42 +461,42 @@ __device__ __forceinline__ void probe_round_pair(const uint64_t *__restrict__ bu
   using Mask = typename T::Mask;
   static_assert(S == 16, "the fused round is built for 16-slot buckets");
   for (int base = 0; base < 64; base += PIPE * T::G) {
-  uint64_t wa[PIPE], wb[PIPE];
+    uint64_t wa[PIPE], wb[PIPE];
 #pragma unroll
-  for (int j = 0; j < PIPE; ++j) wa[j] = buckets[(uint64_t)bkts1[base + j * T::G + g] * S + sl];
+    for (int j = 0; j < PIPE; ++j) wa[j] = buckets[(uint64_t)bkts1[base + j * T::G + g] * S + sl];
 #pragma unroll
-  for (int j = 0; j < PIPE; ++j) wb[j] = buckets[(uint64_t)bkts2[base + j * T::G + g] * S + sl];
-  __builtin_amdgcn_sched_barrier(0);
+    for (int j = 0; j < PIPE; ++j) wb[j] = buckets[(uint64_t)bkts2[base + j * T::G + g] * S + sl];
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-  for (int j = 0; j < PIPE; ++j) {
-    const int t = base + j * T::G + g;
-    const uint32_t ko = keys1[t];
-    const uint64_t mm = ballot(ko != 0u && key_of(wa[j]) == ko);
-    const uint64_t ee = ballot(wa[j] == EMPTY);
-    const Mask gm = (Mask)((mm >> (g * S)) & T::FULL);
-    if (sl == 0) {
-      m1_out[t] = gm;
-      e1_out[t] = (Mask)((ee >> (g * S)) & T::FULL);
-    }
-    if (gm != 0 && sl == ctz_mask(gm)) w1_out[t] = wa[j];
-  }
-#pragma unroll
-  for (int j = 0; j < PIPE; ++j) {
-    const int t = base + j * T::G + g;
-    const bool mine = t < count2;
-    const uint32_t ko = mine ? keys2[t] : 0u;
-    const uint64_t mm = ballot(mine && ko != 0u && key_of(wb[j]) == ko);
-    const uint64_t ee = ballot(wb[j] == EMPTY);
-    const Mask gm = (Mask)((mm >> (g * S)) & T::FULL);
-    if (mine) {
-      const int o = list2[t];
+    for (int j = 0; j < PIPE; ++j) {
+      const int t = base + j * T::G + g;
+      const uint32_t ko = keys1[t];
+      const uint64_t mm = ballot(ko != 0u && key_of(wa[j]) == ko);
+      const uint64_t ee = ballot(wa[j] == EMPTY);
+      const Mask gm = (Mask)((mm >> (g * S)) & T::FULL);
       if (sl == 0) {
-        m2_out[o] = gm;
-        e2_out[o] = (Mask)((ee >> (g * S)) & T::FULL);
+        m1_out[t] = gm;
+        e1_out[t] = (Mask)((ee >> (g * S)) & T::FULL);
       }
-      if (gm != 0 && sl == ctz_mask(gm)) w2_out[o] = wb[j];
+      if (gm != 0 && sl == ctz_mask(gm)) w1_out[t] = wa[j];
     }
-  }
+#pragma unroll
+    for (int j = 0; j < PIPE; ++j) {
+      const int t = base + j * T::G + g;
+      const bool mine = t < count2;
+      const uint32_t ko = mine ? keys2[t] : 0u;
+      const uint64_t mm = ballot(mine && ko != 0u && key_of(wb[j]) == ko);
+      const uint64_t ee = ballot(wb[j] == EMPTY);
+      const Mask gm = (Mask)((mm >> (g * S)) & T::FULL);
+      if (mine) {
+        const int o = list2[t];
+        if (sl == 0) {
+          m2_out[o] = gm;
+          e2_out[o] = (Mask)((ee >> (g * S)) & T::FULL);
+        }
+        if (gm != 0 && sl == ctz_mask(gm)) w2_out[o] = wb[j];
+      }
+    }
   }
 }
 
@@ -1341,10 +1406,19 @@ __global__ void resize_plan_kernel(ResizeArgs a, uint32_t mode, uint64_t amount)
 }
 
 // Ticket for "the last block of this launch": every block has finished its
-// reads of the control block and its writes to the table.  Two levels, so
-// that no counter takes more than NSHARD atomics: block b counts on shard
-// b % NSHARD, and the block completing a shard counts on Ctl::ticket.  The
-// last block resets both levels for the next launch.
+// reads of the control block.  Two levels, so that no counter takes more
+// than NSHARD atomics: block b counts on shard b % NSHARD, and the block
+// completing a shard counts on Ctl::ticket.  The last block resets both
+// levels for the next launch.
+//
+// No release fence before the count: the last block only rewrites control
+// scalars (geometry, counts) that the other blocks read before they count
+// (their loads have returned: the values bound the work they did), and the
+// table words the other blocks wrote are read by later launches, which the
+// kernel boundary orders.  An agent-scope release writes back the block's
+// L2, one after another per XCD: with a 2,048-block grid the fences alone
+// cost 26 us (43 us with dirty lines) against 7 us for the same launch
+// without them.
 __device__ __forceinline__ bool last_block(Ctl *c) {
   __shared__ bool last;
   __syncthreads();
@@ -1352,11 +1426,8 @@ __device__ __forceinline__ bool last_block(Ctl *c) {
     const uint64_t grid = gridDim.x, s = blockIdx.x % NSHARD;
     const uint64_t in_shard = (grid - s + NSHARD - 1) / NSHARD;
     bool l = false;
-    __threadfence();
-    if (add64(&shard_of(c, s)->ticket, 1) + 1 == in_shard) {
-      __threadfence();
+    if (add64(&shard_of(c, s)->ticket, 1) + 1 == in_shard)
       l = add64(&c->ticket, 1) + 1 == min(grid, (uint64_t)NSHARD);
-    }
     last = l;
   }
   __syncthreads();
@@ -1492,15 +1563,15 @@ __global__ __launch_bounds__(BLOCK) void resize_pass2_kernel(ResizeArgs a) {
 // per wave and item range; `t` indexes stash words (the whole table, which
 // is reset to EMPTY on the way) then pending entries, and the 256-entry tile
 // t / 256 picks the worklist segment.
-__device__ __forceinline__ void drain_collect(uint64_t t, uint64_t n_stash_words, uint64_t total, uint64_t *stash,
-                                              const uint64_t *pending, uint64_t *wl, uint64_t seg_cap, Ctl *c) {
-  uint64_t w = TOMB;
-  if (t < n_stash_words) {
-    w = stash[t];
-    if (w != EMPTY) stash[t] = EMPTY;
-  } else if (t < total) {
-    w = pending[t - n_stash_words];
-  }
+__device__ __forceinline__ uint64_t drain_word(uint64_t t, uint64_t n_stash_words, uint64_t total,
+                                               const uint64_t *stash, const uint64_t *pending) {
+  return t < n_stash_words ? stash[t] : t < total ? pending[t - n_stash_words] : TOMB;
+}
+
+// Word w (drain_word of t) to the worklist; a used stash word is reset.
+__device__ __forceinline__ void drain_append(uint64_t t, uint64_t w, uint64_t n_stash_words, uint64_t *stash,
+                                             uint64_t *wl, uint64_t seg_cap, Ctl *c) {
+  if (t < n_stash_words && w != EMPTY) stash[t] = EMPTY;
   const bool live = w != TOMB && w != EMPTY;
   const uint64_t m = ballot(live);
   if (m) {
@@ -1512,6 +1583,11 @@ __device__ __forceinline__ void drain_collect(uint64_t t, uint64_t n_stash_words
     base = read_lane64(base, leader);
     if (live) wl[(tile % NSHARD) * seg_cap + base + rank_below(m)] = w;
   }
+}
+
+__device__ __forceinline__ void drain_collect(uint64_t t, uint64_t n_stash_words, uint64_t total, uint64_t *stash,
+                                              const uint64_t *pending, uint64_t *wl, uint64_t seg_cap, Ctl *c) {
+  drain_append(t, drain_word(t, n_stash_words, total, stash, pending), n_stash_words, stash, wl, seg_cap, c);
 }
 
 __device__ __forceinline__ void drain_done(volatile Ctl *c) {
@@ -1532,8 +1608,18 @@ __global__ __launch_bounds__(BLOCK) void drain_kernel(uint64_t *stash, uint64_t 
   if (total) {
     for (uint64_t t = tid; t < hint_n; t += stride) hint[t] = 0u;
   }
-  const uint64_t span = (total + stride - 1) / stride * stride;
-  for (uint64_t t = tid; t < span; t += stride) drain_collect(t, n_stash, total, stash, pending, wl, seg_cap, c);
+  // DRAIN_WORDS words per thread and trip, all loads in flight together (the
+  // scan of a mostly empty stash table is bound by load latency)
+  const uint64_t step = stride * DRAIN_WORDS;
+  const uint64_t span = (total + step - 1) / step * step;  // uniform trip count
+  const uint64_t first = (uint64_t)blockIdx.x * BLOCK * DRAIN_WORDS + threadIdx.x;
+  for (uint64_t base = first; base < span; base += step) {
+    uint64_t w[DRAIN_WORDS];
+#pragma unroll
+    for (int j = 0; j < DRAIN_WORDS; ++j) w[j] = drain_word(base + (uint64_t)j * BLOCK, n_stash, total, stash, pending);
+#pragma unroll
+    for (int j = 0; j < DRAIN_WORDS; ++j) drain_append(base + (uint64_t)j * BLOCK, w[j], n_stash, stash, wl, seg_cap, c);
+  }
   if (last_block(c) && threadIdx.x == 0) drain_done(c);
 }
 
