@@ -1608,17 +1608,55 @@ __global__ __launch_bounds__(BLOCK) void drain_kernel(uint64_t *stash, uint64_t 
   if (total) {
     for (uint64_t t = tid; t < hint_n; t += stride) hint[t] = 0u;
   }
-  // DRAIN_WORDS words per thread and trip, all loads in flight together (the
-  // scan of a mostly empty stash table is bound by load latency)
-  const uint64_t step = stride * DRAIN_WORDS;
-  const uint64_t span = (total + step - 1) / step * step;  // uniform trip count
-  const uint64_t first = (uint64_t)blockIdx.x * BLOCK * DRAIN_WORDS + threadIdx.x;
-  for (uint64_t base = first; base < span; base += step) {
+  // A trip of a block takes DRAIN_WORDS tiles of 256 words that share one
+  // worklist segment (tiles T, T + NSHARD, ...: word t is in tile t / 256,
+  // which appends to segment tile % NSHARD, so segment fills stay within the
+  // capacity sized from the words walked), loads all of its words at once
+  // (the walk of a mostly empty stash table is bound by load latency), and
+  // appends its live words with one atomic: per-wave appends queued
+  // thousands of atomics on each segment counter.
+  __shared__ uint32_t s_wave[WAVES];
+  __shared__ uint64_t s_base;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const uint64_t tiles = (total + BLOCK - 1) / BLOCK;
+  const uint64_t group = (uint64_t)NSHARD * DRAIN_WORDS;  // tiles of NSHARD trips
+  const uint64_t trips = (tiles + group - 1) / group * NSHARD;
+  for (uint64_t q = blockIdx.x; q < trips; q += gridDim.x) {
+    const uint64_t seg = q % NSHARD, tile0 = (q / NSHARD) * group + seg;
     uint64_t w[DRAIN_WORDS];
 #pragma unroll
-    for (int j = 0; j < DRAIN_WORDS; ++j) w[j] = drain_word(base + (uint64_t)j * BLOCK, n_stash, total, stash, pending);
+    for (int j = 0; j < DRAIN_WORDS; ++j)
+      w[j] = drain_word((tile0 + (uint64_t)j * NSHARD) * BLOCK + threadIdx.x, n_stash, total, stash, pending);
+    uint32_t mine = 0;
 #pragma unroll
-    for (int j = 0; j < DRAIN_WORDS; ++j) drain_append(base + (uint64_t)j * BLOCK, w[j], n_stash, stash, wl, seg_cap, c);
+    for (int j = 0; j < DRAIN_WORDS; ++j) {
+      const uint64_t t = (tile0 + (uint64_t)j * NSHARD) * BLOCK + threadIdx.x;
+      if (t < n_stash && w[j] != EMPTY) stash[t] = EMPTY;
+      mine += (w[j] != TOMB && w[j] != EMPTY) ? 1u : 0u;
+    }
+    // block-wide exclusive prefix of the live counts
+    uint32_t incl = mine;
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += y;
+    }
+    if (lane == 63) s_wave[wv] = incl;
+    __syncthreads();
+    uint32_t before = 0, sum = 0;
+#pragma unroll
+    for (int x = 0; x < WAVES; ++x) {
+      before += x < wv ? s_wave[x] : 0u;
+      sum += s_wave[x];
+    }
+    if (threadIdx.x == 0 && sum) s_base = wl_append(c, seg, sum);
+    __syncthreads();
+    if (sum) {
+      uint64_t pos = seg * seg_cap + s_base + before + incl - mine;
+#pragma unroll
+      for (int j = 0; j < DRAIN_WORDS; ++j)
+        if (w[j] != TOMB && w[j] != EMPTY) wl[pos++] = w[j];
+    }
+    __syncthreads();  // s_wave and s_base of the next trip
   }
   if (last_block(c) && threadIdx.x == 0) drain_done(c);
 }
