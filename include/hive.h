@@ -203,7 +203,7 @@ hive_status hive_mixed_batch(hive_t h, const uint8_t *d_ops, const uint32_t *d_k
  * under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc): the same operation, outputs and contract, with no hipMalloc,
  * hipFree or other allocating call.  The batch's dedupe set (needed unless
- * `flags` has HIVE_UNIQUE) lives in a 64 MiB array of device memory that the
+ * `flags` has HIVE_UNIQUE) lives in a 128 MiB array of device memory that the
  * library holds on each GPU it runs on until the process ends, so with
  * dedupe a call takes at most 2^22 operations; the eviction worklist is the
  * table's own, preallocated at create, so n may not exceed

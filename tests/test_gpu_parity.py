@@ -184,6 +184,74 @@ def test_dedupe_last_insert_wins_first_delete_reports(H):
     t.close()
 
 
+def _lowbias32(x):
+    """The library's mix for its dedupe partitions ("lowbias32", C. Wellons),
+    restated here only to build keys that all land in one partition."""
+    x = x.astype(np.uint64)
+    m = np.uint64(0xFFFFFFFF)
+    x ^= x >> np.uint64(16)
+    x = (x * np.uint64(0x7FEB352D)) & m
+    x ^= x >> np.uint64(15)
+    x = (x * np.uint64(0x846CA68B)) & m
+    return (x ^ (x >> np.uint64(16))).astype(np.uint32)
+
+
+def _one_partition_keys(n, top, seed):
+    """n distinct valid keys whose mix has the same top nine bits (one dedupe
+    partition of the plain path)."""
+    rng = np.random.default_rng(seed)
+    out = np.empty(0, np.uint32)
+    while out.size < n:
+        x = rng.integers(1, 0xFFFFFFFF, 1 << 24, dtype=np.uint64).astype(np.uint32)
+        out = np.unique(np.concatenate([out, x[(_lowbias32(x) >> np.uint32(23)) == top]]))
+    return rng.permutation(out)[:n]
+
+
+@pytest.mark.parametrize("kind", ["insert", "mixed", "set32"])
+def test_dedupe_partition_beyond_its_lds_table(H, kind):
+    """The plain path deduplicates per hash partition in an LDS table that
+    takes 6,144 distinct keys; a batch that puts about 9,000 distinct keys
+    of one type (with repeats) in one partition takes the partition's HBM
+    fallback table.  Outputs, key count and contents equal the
+    dictionary's."""
+    keys = _one_partition_keys(12000, 77, 41)
+    rng = np.random.default_rng(42)
+    reps = keys[rng.integers(0, keys.size, 30000)]
+    case(f"dedupe partition overflow, {kind}")
+    set32 = kind == "set32"
+    t = H.Table(4096, slots_per_bucket=32, entry_bits=32) if set32 else H.Table(4096)
+    o = oracle.O1()
+    if kind in ("insert", "set32"):
+        ins = np.concatenate([keys, reps])
+        vals = np.zeros(ins.size, np.uint32) if set32 else rng.integers(1, 1 << 32, ins.size, dtype=np.uint64).astype(np.uint32)
+        t.insert(dev(ins), None if set32 else dev(vals))
+        o.insert(ins, vals)
+        dk = np.concatenate([keys[rng.integers(0, keys.size, 20000)], wl.KeyStream(43).range(0, 500)])
+        assert np.array_equal(host(t.delete(dev(dk))), o.delete(dk))
+    else:
+        pre = keys[:3000]
+        t.insert(dev(pre), dev(wl.values_for(pre)), flags=H.HIVE_UNIQUE)
+        o.insert(pre, wl.values_for(pre))
+        # inserts of keys[3000:] with repeats, deletes of keys[:2000] with
+        # repeats, lookups of others: disjoint key sets per type
+        ins = keys[3000:][rng.integers(0, 9000, 30000)]
+        dels = keys[:2000][rng.integers(0, 2000, 8000)]
+        looks = keys[2000:3000][rng.integers(0, 1000, 4000)]
+        ks = np.concatenate([ins, dels, looks])
+        ops = np.concatenate([np.full(ins.size, wl.OP_INSERT), np.full(dels.size, wl.OP_DELETE),
+                              np.full(looks.size, wl.OP_LOOKUP)]).astype(np.uint8)
+        perm = rng.permutation(ks.size)
+        ks, ops = ks[perm], ops[perm]
+        vals = rng.integers(1, 1 << 32, ks.size, dtype=np.uint64).astype(np.uint32)
+        v, f = t.mixed(dev(ops), dev(ks), dev(vals))
+        ov, of = o.apply(ops, ks, vals)
+        assert np.array_equal(host(f), of) and np.array_equal(host(v), ov)
+    st = t.stats()
+    assert st["status"] >= 0 and st["live"] == len(o), st
+    assert np.array_equal(t.dump(), o.dump())
+    t.close()
+
+
 @pytest.mark.parametrize("path", ["plain", "persistent"])
 def test_dedupe_delete_batch_sized_from_the_batch(H, path):
     """A delete batch with repeats (no HIVE_UNIQUE) on a table whose scratch
