@@ -297,6 +297,8 @@ constexpr int DD_LDS = 2 * (int)DD_CHUNK;
 constexpr int DDP_BITS = 9;
 constexpr int DDP_BINS = 1 << DDP_BITS;  // partitions per operation type
 constexpr uint64_t DDP_SEG = 8;          // chunks per segment
+constexpr int DDP_SCATTER_LOADS = 4;     // staged records per thread in flight (scatter)
+constexpr int DDP_RESOLVE_LOADS = 8;     // records per thread in flight (resolve)
 constexpr int DDP_TAB = 8192;            // entries of a resolve table (64 KiB)
 constexpr uint32_t DDP_CAP = DDP_TAB * 3 / 4;
 static_assert(DDP_BINS % 64 == 0 && DDP_BINS <= BLOCK * 2, "partition counts per block");
@@ -427,28 +429,42 @@ __global__ __launch_bounds__(BLOCK) void ddp_segsum_kernel(DdpArgs d) {
 }
 
 // Step 3.  Block (ti, g): partitions g * 64 .. g * 64 + 63 of type ti, one per
-// lane; the waves take consecutive ranges of segments.
-__global__ __launch_bounds__(BLOCK) void ddp_scan_kernel(DdpArgs d) {
-  __shared__ uint32_t part[WAVES][64];
+// lane; its DDP_SCAN_WAVES waves take consecutive ranges of segments, eight
+// loads in flight at a time.
+constexpr int DDP_SCAN_WAVES = 16;
+__global__ __launch_bounds__(DDP_SCAN_WAVES * 64) void ddp_scan_kernel(DdpArgs d) {
+  __shared__ uint32_t part[DDP_SCAN_WAVES][64];
   constexpr int GROUPS = DDP_BINS / 64;
   const uint32_t ti = blockIdx.x / GROUPS;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int b = (blockIdx.x % GROUPS) * 64 + lane;
-  const uint64_t q = (d.nseg + WAVES - 1) / WAVES;
+  const uint64_t q = (d.nseg + DDP_SCAN_WAVES - 1) / DDP_SCAN_WAVES;
   const uint64_t s0 = min((uint64_t)wv * q, d.nseg), s1 = min(s0 + q, d.nseg);
   uint32_t *col = d.seg + (uint64_t)ti * d.nseg * DDP_BINS + b;
   uint32_t sum = 0;
-  for (uint64_t s = s0; s < s1; ++s) sum += col[s * DDP_BINS];
+  for (uint64_t s = s0; s < s1; s += 8) {
+    uint32_t v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = s + j < s1 ? col[(s + j) * DDP_BINS] : 0u;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) sum += v[j];
+  }
   part[wv][lane] = sum;
   __syncthreads();
   uint32_t run = 0;
   for (int w = 0; w < wv; ++w) run += part[w][lane];
-  for (uint64_t s = s0; s < s1; ++s) {
-    const uint32_t v = col[s * DDP_BINS];
-    col[s * DDP_BINS] = run;
-    run += v;
+  for (uint64_t s = s0; s < s1; s += 8) {
+    uint32_t v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = s + j < s1 ? col[(s + j) * DDP_BINS] : 0u;
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (s + j < s1) {
+        col[(s + j) * DDP_BINS] = run;
+        run += v[j];
+      }
   }
-  if (wv == WAVES - 1) d.tot[ti * DDP_BINS + b] = run;
+  if (wv == DDP_SCAN_WAVES - 1) d.tot[ti * DDP_BINS + b] = run;
 }
 
 // Start of every partition in `rec` (exclusive prefix of the totals over
@@ -492,14 +508,32 @@ __global__ __launch_bounds__(BLOCK) void ddp_scatter_kernel(DdpArgs d) {
   uint32_t *cur = starts + ti * DDP_BINS;  // this type's cursors
   for (int b = threadIdx.x; b < DDP_BINS; b += BLOCK) cur[b] += d.seg[((uint64_t)ti * d.nseg + s) * DDP_BINS + b];
   __syncthreads();
+  // the segment's staged records as one list (chunk j holds [pre[j],
+  // pre[j + 1])), DDP_SCATTER_LOADS loads in flight per thread at a time
   const uint64_t c0 = s * DDP_SEG, c1 = min(c0 + DDP_SEG, d.nch);
-  for (uint64_t c = c0; c < c1; ++c) {
-    const uint32_t n_c = d.cnt[(uint64_t)ti * d.nch + c];
-    const uint64_t *st = d.stage + ((uint64_t)ti * d.nch + c) * DD_CHUNK;
-    for (uint32_t q = threadIdx.x; q < n_c; q += BLOCK) {
-      const uint64_t e = st[q];
-      d.rec[atomicAdd(&cur[ddp_bin((uint32_t)(e >> 32))], 1u)] = e;
+  uint32_t pre[DDP_SEG + 1];
+  pre[0] = 0;
+#pragma unroll
+  for (int j = 0; j < (int)DDP_SEG; ++j) pre[j + 1] = pre[j] + (c0 + j < c1 ? d.cnt[(uint64_t)ti * d.nch + c0 + j] : 0u);
+  const uint32_t total = pre[DDP_SEG];
+  const uint64_t *st = d.stage + ((uint64_t)ti * d.nch + c0) * DD_CHUNK;
+  constexpr int U = DDP_SCATTER_LOADS;
+  for (uint32_t t0 = threadIdx.x; t0 < total; t0 += U * BLOCK) {
+    uint64_t e[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t t = t0 + u * BLOCK;
+      e[u] = EMPTY;
+      if (t < total) {
+        int j = 0;
+#pragma unroll
+        for (int x = 1; x < (int)DDP_SEG; ++x) j += t >= pre[x] ? 1 : 0;
+        e[u] = st[(uint64_t)j * DD_CHUNK + (t - pre[j])];
+      }
     }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (e[u] != EMPTY) d.rec[atomicAdd(&cur[ddp_bin((uint32_t)(e[u] >> 32))], 1u)] = e[u];
   }
 }
 
@@ -523,27 +557,46 @@ __global__ __launch_bounds__(BLOCK) void ddp_resolve_kernel(DdpArgs d) {
   // at most BLOCK claims land after the one that crosses DDP_CAP (one per
   // thread in flight), so the table never fills and every probe ends
   static_assert(DDP_CAP + BLOCK < DDP_TAB, "resolve table headroom");
-  for (uint64_t r = threadIdx.x; r < count; r += BLOCK) {
-    if (*(volatile uint32_t *)&s_over) break;
-    const uint64_t e = rec[r];
-    const uint32_t k = (uint32_t)(e >> 32);
-    for (uint32_t sl = mix32(k) & (DDP_TAB - 1);; sl = (sl + 1) & (DDP_TAB - 1)) {
-      uint64_t cur = tab[sl];
-      if (cur == EMPTY) {
-        cur = atomicCAS((unsigned long long *)&tab[sl], (unsigned long long)EMPTY, (unsigned long long)e);
+  // records DDP_RESOLVE_LOADS at a time per thread, all loads in flight; the
+  // overflow flag is checked before every insert, so each thread claims at
+  // most one slot after the count crosses DDP_CAP
+  constexpr int U = DDP_RESOLVE_LOADS;
+  for (uint64_t r0 = threadIdx.x; r0 < count; r0 += (uint64_t)U * BLOCK) {
+    uint64_t es[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint64_t r = r0 + (uint64_t)u * BLOCK;
+      es[u] = r < count ? rec[r] : EMPTY;
+    }
+    bool over = false;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint64_t e = es[u];
+      if (e == EMPTY) continue;
+      if (*(volatile uint32_t *)&s_over) {
+        over = true;
+        break;
+      }
+      const uint32_t k = (uint32_t)(e >> 32);
+      for (uint32_t sl = mix32(k) & (DDP_TAB - 1);; sl = (sl + 1) & (DDP_TAB - 1)) {
+        uint64_t cur = tab[sl];
         if (cur == EMPTY) {
-          if (atomicAdd(&s_claims, 1u) + 1 > DDP_CAP) s_over = 1;
+          cur = atomicCAS((unsigned long long *)&tab[sl], (unsigned long long)EMPTY, (unsigned long long)e);
+          if (cur == EMPTY) {
+            if (atomicAdd(&s_claims, 1u) + 1 > DDP_CAP) s_over = 1;
+            break;
+          }
+        }
+        if ((uint32_t)(cur >> 32) == k) {
+          if (op == OP_INSERT)
+            atomicMax((unsigned long long *)&tab[sl], (unsigned long long)e);
+          else
+            atomicMin((unsigned long long *)&tab[sl], (unsigned long long)e);
           break;
         }
       }
-      if ((uint32_t)(cur >> 32) == k) {
-        if (op == OP_INSERT)
-          atomicMax((unsigned long long *)&tab[sl], (unsigned long long)e);
-        else
-          atomicMin((unsigned long long *)&tab[sl], (unsigned long long)e);
-        break;
-      }
     }
+    if (over) break;
   }
   __syncthreads();
   if (!s_over) {
@@ -3534,7 +3587,7 @@ static hive_status launch_dedupe(uint64_t *dd, uint32_t mode, const uint8_t *d_o
   d.mode = mode;
   hipLaunchKernelGGL(ddp_collect_kernel, dim3((unsigned)(nt * d.nch)), dim3(BLOCK), 0, st, d);
   hipLaunchKernelGGL(ddp_segsum_kernel, dim3((unsigned)(nt * d.nseg)), dim3(BLOCK), 0, st, d);
-  hipLaunchKernelGGL(ddp_scan_kernel, dim3(nt * (DDP_BINS / 64)), dim3(BLOCK), 0, st, d);
+  hipLaunchKernelGGL(ddp_scan_kernel, dim3(nt * (DDP_BINS / 64)), dim3(DDP_SCAN_WAVES * 64), 0, st, d);
   hipLaunchKernelGGL(ddp_scatter_kernel, dim3((unsigned)(nt * d.nseg)), dim3(BLOCK), 0, st, d);
   hipLaunchKernelGGL(ddp_resolve_kernel, dim3(nt * DDP_BINS), dim3(BLOCK), 0, st, d);
   *win = d.win;
