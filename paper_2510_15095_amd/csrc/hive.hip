@@ -1267,6 +1267,52 @@ __device__ __forceinline__ void load_bucket16_fresh(const uint64_t *b, uint64_t 
   }
 }
 
+// Two whole buckets per lane, all sixteen loads in flight before the one
+// wait (the same loads as load_bucket16_fresh).
+__device__ __forceinline__ void load_bucket16x2_fresh(const uint64_t *b1, const uint64_t *b2, uint64_t *w1,
+                                                      uint64_t *w2) {
+  u32x4 x0, x1, x2, x3, x4, x5, x6, x7, y0, y1, y2, y3, y4, y5, y6, y7;
+  asm volatile(
+      "global_load_dwordx4 %0, %16, off sc1\n"
+      "global_load_dwordx4 %1, %16, off offset:16 sc1\n"
+      "global_load_dwordx4 %2, %16, off offset:32 sc1\n"
+      "global_load_dwordx4 %3, %16, off offset:48 sc1\n"
+      "global_load_dwordx4 %4, %16, off offset:64 sc1\n"
+      "global_load_dwordx4 %5, %16, off offset:80 sc1\n"
+      "global_load_dwordx4 %6, %16, off offset:96 sc1\n"
+      "global_load_dwordx4 %7, %16, off offset:112 sc1\n"
+      "global_load_dwordx4 %8, %17, off sc1\n"
+      "global_load_dwordx4 %9, %17, off offset:16 sc1\n"
+      "global_load_dwordx4 %10, %17, off offset:32 sc1\n"
+      "global_load_dwordx4 %11, %17, off offset:48 sc1\n"
+      "global_load_dwordx4 %12, %17, off offset:64 sc1\n"
+      "global_load_dwordx4 %13, %17, off offset:80 sc1\n"
+      "global_load_dwordx4 %14, %17, off offset:96 sc1\n"
+      "global_load_dwordx4 %15, %17, off offset:112 sc1\n"
+      "s_waitcnt vmcnt(0)\n"
+      : "=&v"(x0), "=&v"(x1), "=&v"(x2), "=&v"(x3), "=&v"(x4), "=&v"(x5), "=&v"(x6), "=&v"(x7), "=&v"(y0),
+        "=&v"(y1), "=&v"(y2), "=&v"(y3), "=&v"(y4), "=&v"(y5), "=&v"(y6), "=&v"(y7)
+      : "v"(b1), "v"(b2)
+      : "memory");
+  const u32x4 xs[8] = {x0, x1, x2, x3, x4, x5, x6, x7};
+  const u32x4 ys[8] = {y0, y1, y2, y3, y4, y5, y6, y7};
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    w1[2 * j] = ((uint64_t)xs[j][1] << 32) | xs[j][0];
+    w1[2 * j + 1] = ((uint64_t)xs[j][3] << 32) | xs[j][2];
+    w2[2 * j] = ((uint64_t)ys[j][1] << 32) | ys[j][0];
+    w2[2 * j + 1] = ((uint64_t)ys[j][3] << 32) | ys[j][2];
+  }
+}
+
+// EMPTY-slot mask of a whole bucket held by one lane.
+__device__ __forceinline__ uint32_t empty_mask16(const uint64_t *w) {
+  uint32_t m = 0;
+#pragma unroll
+  for (int p = 0; p < 16; ++p) m |= (w[p] == EMPTY ? 1u : 0u) << p;
+  return m;
+}
+
 // The group's fresh view of bucket `bkt`: words w[p] of slots sl * P + p,
 // and its EMPTY-slot mask.
 template <int S>
@@ -1325,8 +1371,17 @@ __device__ __forceinline__ bool evict_chain(const EvictArgs &a, const Geo &geo, 
   const uint32_t c1 = address(geo, HashPair<PAIR>::h1(key_of(kv))), c2 = address(geo, HashPair<PAIR>::h2(key_of(kv)));
   // step 2 with fresh loads (fresh: other items of this phase change buckets)
   uint64_t w[E::P], w2v[E::P];
-  const Mask f1 = load_view<S>(a.buckets + (uint64_t)c1 * S, g, sl, w);
-  const Mask f2 = load_view<S>(a.buckets + (uint64_t)c2 * S, g, sl, w2v) & (Mask)((c2 != c1) ? ~0ull : 0ull);
+  // one lane holding whole buckets: both candidates in one round trip
+  constexpr bool kLaneBucket = E::L == 1 && E::P == 16;
+  Mask f1, f2;
+  if constexpr (kLaneBucket) {
+    load_bucket16x2_fresh(a.buckets + (uint64_t)c1 * S, a.buckets + (uint64_t)c2 * S, w, w2v);
+    f1 = (Mask)empty_mask16(w);
+    f2 = (Mask)empty_mask16(w2v) & (Mask)((c2 != c1) ? ~0ull : 0ull);
+  } else {
+    f1 = load_view<S>(a.buckets + (uint64_t)c1 * S, g, sl, w);
+    f2 = load_view<S>(a.buckets + (uint64_t)c2 * S, g, sl, w2v) & (Mask)((c2 != c1) ? ~0ull : 0ull);
+  }
   bool placed;
   if constexpr (PairArity<PAIR>::D == 3) {
     // three-choice: the emptiest candidate first, ties to the lower hash
@@ -1359,12 +1414,71 @@ __device__ __forceinline__ bool evict_chain(const EvictArgs &a, const Geo &geo, 
                group_claim<S>(a.buckets + (uint64_t)c2 * S, f2, kv, g, sl);
   }
   uint32_t b = c1;  // chains start at the first candidate
+  // look-ahead chains keep the view of the bucket they move to: w holds
+  // bucket b's words when `have_view` (first the view step 2 loaded; its
+  // free slots were just tried)
+  bool have_view = kLaneBucket && PairArity<PAIR>::D == 2;
   for (uint32_t kick = 1; kick <= max_kicks && !placed; ++kick) {
     uint64_t *bkt = a.buckets + (uint64_t)b * S;
-    const Mask fm = load_view<S>(bkt, g, sl, w);
-    if (group_claim<S>(bkt, fm, kv, g, sl)) {
-      placed = true;
-      break;
+    if (!have_view) {
+      const Mask fm = load_view<S>(bkt, g, sl, w);
+      if (group_claim<S>(bkt, fm, kv, g, sl)) {
+        placed = true;
+        break;
+      }
+    }
+    have_view = false;
+    if constexpr (kLaneBucket && PairArity<PAIR>::D == 2) {
+      // Look ahead: two candidate victims at pseudo-random distinct slots;
+      // both alternate buckets are loaded in one round trip, and a victim
+      // whose alternate has an EMPTY slot is displaced and claims that slot
+      // from the view just loaded.  At 95% load most chains then end after
+      // one displacement instead of several, and far fewer run out of
+      // rounds into the stash (mixed Zipf batches at 95%: 130 K stash
+      // entries per 2^22 operations before, about 12 K with look-ahead);
+      // with no room in either, the first is displaced and the chain goes
+      // on from its alternate.  (Four candidates, loaded one after another,
+      // stretched every chain that fails to four more round trips per
+      // displacement.)
+      constexpr int LA = 2;
+      const uint32_t r = mix32(key_of(kv) ^ (kick * 0x9E3779B9u));
+      int vs[LA];
+      uint64_t vw[LA];
+      uint32_t va[LA];
+#pragma unroll
+      for (int j = 0; j < LA; ++j) {
+        vs[j] = (int)((r + 5u * (uint32_t)j) & 15u);
+        vw[j] = w[vs[j]];
+        const uint32_t a1 = address(geo, HashPair<PAIR>::h1(key_of(vw[j])));
+        const uint32_t a2 = address(geo, HashPair<PAIR>::h2(key_of(vw[j])));
+        va[j] = (b == a1) ? a2 : a1;
+      }
+      load_bucket16x2_fresh(a.buckets + (uint64_t)va[0] * S, a.buckets + (uint64_t)va[1] * S, w, w2v);
+      const Mask fa = (Mask)empty_mask16(w) & (Mask)((va[0] != b) ? ~0ull : 0ull);
+      const Mask fb = (Mask)empty_mask16(w2v) & (Mask)((va[1] != b) ? ~0ull : 0ull);
+      const int pick = (fa == 0 && fb != 0) ? 1 : 0;
+      const Mask fpick = pick ? fb : fa;
+      const uint64_t victim = vw[pick];
+      if (cas64(bkt + vs[pick], victim, kv) != victim) continue;  // the slot changed: count the round
+      if (victim == EMPTY) {
+        placed = true;  // the slot was empty after all: the CAS claimed it
+        break;
+      }
+      ++n_evict;
+      kv = victim;
+      b = va[pick];
+      if (fpick && group_claim<S>(a.buckets + (uint64_t)b * S, fpick, kv, g, sl)) {
+        placed = true;
+        break;
+      }
+      // no room there (or it was taken meanwhile): the next displacement
+      // works from the view just loaded, one round trip fewer
+      if (pick == 1) {
+#pragma unroll
+        for (int p = 0; p < 16; ++p) w[p] = w2v[p];
+      }
+      have_view = true;
+      continue;
     }
     // victim: a pseudo-random slot (the paper's "first occupied" slot is
     // slot 0 of every full bucket, which lets two chains trade the same
