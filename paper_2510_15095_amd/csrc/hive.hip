@@ -278,14 +278,17 @@ __device__ __forceinline__ void dedupe_thread(uint64_t *dd, uint64_t mask, uint3
 //   1. collect, per chunk of DD_CHUNK operations and type: the chunk's
 //      repeats collapse in an LDS table (a Zipf(0.99) hot key is about 5% of
 //      the operations), its distinct records go to its staging area with a
-//      histogram over the partitions, and its winner flags are cleared;
+//      histogram over the partitions, and the flags of the type's operations
+//      are written: 1 for the chunk's winners, 0 for the rest;
 //   2. segment sums: the histograms summed over segments of DDP_SEG chunks;
 //   3. scan: per partition, exclusive prefixes over the segments and the
 //      partition's total;
 //   4. scatter: per segment, each record to its partition's run of `rec`;
 //   5. resolve: per partition, an LDS table keeps per key the largest insert
 //      index (the last occurrence wins) or the smallest delete index (the
-//      first reports the deletion), and sets the winners' flags.  A partition
+//      first reports the deletion), and clears the flags of the records that
+//      lose to another chunk's (random one-byte stores run at about 77 G/s:
+//      one per distinct key took 30 us of a 2^22-operation batch).  A partition
 //      with more distinct keys than the table takes falls back to a table of
 //      its own in HBM (twice its records, in the staging area), by atomics.
 // P1 then reads one flag byte per operation, coalesced, instead of looking
@@ -331,10 +334,6 @@ __global__ __launch_bounds__(BLOCK) void ddp_collect_kernel(DdpArgs d) {
   const uint64_t c = blockIdx.x % d.nch;
   const uint32_t op = ddp_op(d, ti);
   const uint64_t base = c * DD_CHUNK;
-  if (ti == 0) {  // the chunk's flags start cleared (its first type's block)
-    uint32_t *w32 = (uint32_t *)(d.win + base);
-    for (int j = threadIdx.x; j < (int)DD_CHUNK / 4; j += BLOCK) w32[j] = 0u;
-  }
   // the chunk's operands first, all loads in flight together
   uint32_t kk[DD_PER_THREAD];
   bool take[DD_PER_THREAD];
@@ -344,6 +343,12 @@ __global__ __launch_bounds__(BLOCK) void ddp_collect_kernel(DdpArgs d) {
     take[j] = i < d.n && (d.mode != OP_MIXED || d.ops[i] == op);
     kk[j] = i < d.n ? d.keys[i] : 0u;
   }
+  // the flags of this type's operations start cleared; the chunk's winners
+  // set theirs below (after barriers of this block), and the resolve step
+  // clears those that lose to another chunk
+#pragma unroll
+  for (int j = 0; j < DD_PER_THREAD; ++j)
+    if (take[j]) d.win[base + (uint64_t)j * BLOCK + threadIdx.x] = 0;
   for (int j = threadIdx.x; j < DD_LDS; j += BLOCK) tab[j] = EMPTY;
   __syncthreads();
 #pragma unroll
@@ -408,6 +413,7 @@ __global__ __launch_bounds__(BLOCK) void ddp_collect_kernel(DdpArgs d) {
   for (uint32_t q = threadIdx.x; q < cnt; q += BLOCK) {
     const uint64_t e = tab[q];
     st[q] = e;
+    d.win[(uint32_t)e] = 1;  // within this chunk's flags
     atomicAdd(&bins[ddp_bin((uint32_t)(e >> 32))], 1u);
   }
   __syncthreads();
@@ -600,9 +606,25 @@ __global__ __launch_bounds__(BLOCK) void ddp_resolve_kernel(DdpArgs d) {
   }
   __syncthreads();
   if (!s_over) {
-    for (int j = threadIdx.x; j < DDP_TAB; j += BLOCK) {
-      const uint64_t e = tab[j];
-      if (e != EMPTY) d.win[(uint32_t)e] = 1;
+    // every record's flag was set by its chunk: clear the losers' (a key
+    // recorded by several chunks), a few scattered stores instead of one
+    // per distinct key
+    for (uint64_t r0 = threadIdx.x; r0 < count; r0 += (uint64_t)U * BLOCK) {
+      uint64_t es[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint64_t r = r0 + (uint64_t)u * BLOCK;
+        es[u] = r < count ? rec[r] : EMPTY;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint64_t e = es[u];
+        if (e == EMPTY) continue;
+        const uint32_t k = (uint32_t)(e >> 32);
+        uint32_t sl = mix32(k) & (DDP_TAB - 1);
+        while ((uint32_t)(tab[sl] >> 32) != k) sl = (sl + 1) & (DDP_TAB - 1);
+        if (tab[sl] != e) d.win[(uint32_t)e] = 0;
+      }
     }
     return;
   }
@@ -632,14 +654,14 @@ __global__ __launch_bounds__(BLOCK) void ddp_resolve_kernel(DdpArgs d) {
     }
   }
   __syncthreads();
-  // the record left in its key's word is the winner
+  // the record left in its key's word is the winner; clear the others' flags
   for (uint64_t r = threadIdx.x; r < count; r += BLOCK) {
     const uint64_t e = rec[r];
     const uint32_t k = (uint32_t)(e >> 32);
     for (uint64_t sl = mix32(k) % m;; sl = (sl + 1 == m) ? 0 : sl + 1) {
       const uint64_t cur = __hip_atomic_load(&ft[sl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if ((uint32_t)(cur >> 32) == k) {
-        if (cur == e) d.win[(uint32_t)e] = 1;
+        if (cur != e) d.win[(uint32_t)e] = 0;
         break;
       }
     }
