@@ -363,10 +363,13 @@ __global__ __launch_bounds__(BLOCK) void ddp_collect_kernel(DdpArgs d) {
         if (cur == EMPTY) break;
       }
       if ((uint32_t)(cur >> 32) == k) {
-        if (op == OP_INSERT)
-          atomicMax((unsigned long long *)&tab[s], (unsigned long long)e);
-        else
+        // only an update that can change the word (a hot key's later
+        // occurrences mostly lose, and atomics on one word serialize)
+        if (op == OP_INSERT) {
+          if (cur < e) atomicMax((unsigned long long *)&tab[s], (unsigned long long)e);
+        } else if (cur > e) {
           atomicMin((unsigned long long *)&tab[s], (unsigned long long)e);
+        }
         break;
       }
     }
@@ -563,10 +566,13 @@ __global__ __launch_bounds__(BLOCK) void ddp_resolve_kernel(DdpArgs d) {
   // at most BLOCK claims land after the one that crosses DDP_CAP (one per
   // thread in flight), so the table never fills and every probe ends
   static_assert(DDP_CAP + BLOCK < DDP_TAB, "resolve table headroom");
-  // records DDP_RESOLVE_LOADS at a time per thread, all loads in flight; the
-  // overflow flag is checked before every insert, so each thread claims at
-  // most one slot after the count crosses DDP_CAP
+  // records DDP_RESOLVE_LOADS at a time per thread, all loads in flight.
+  // New keys are counted per wave and record step (one LDS atomic for the
+  // wave's claims: one per claim serialized the block on a single word),
+  // and the overflow flag is checked before every insert, so each thread
+  // claims at most one slot after the count crosses DDP_CAP
   constexpr int U = DDP_RESOLVE_LOADS;
+  const int lane = threadIdx.x & 63;
   for (uint64_t r0 = threadIdx.x; r0 < count; r0 += (uint64_t)U * BLOCK) {
     uint64_t es[U];
 #pragma unroll
@@ -578,28 +584,33 @@ __global__ __launch_bounds__(BLOCK) void ddp_resolve_kernel(DdpArgs d) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const uint64_t e = es[u];
-      if (e == EMPTY) continue;
-      if (*(volatile uint32_t *)&s_over) {
-        over = true;
-        break;
-      }
-      const uint32_t k = (uint32_t)(e >> 32);
-      for (uint32_t sl = mix32(k) & (DDP_TAB - 1);; sl = (sl + 1) & (DDP_TAB - 1)) {
-        uint64_t cur = tab[sl];
-        if (cur == EMPTY) {
-          cur = atomicCAS((unsigned long long *)&tab[sl], (unsigned long long)EMPTY, (unsigned long long)e);
+      over = over || *(volatile uint32_t *)&s_over != 0;
+      bool claimed = false;
+      if (e != EMPTY && !over) {
+        const uint32_t k = (uint32_t)(e >> 32);
+        for (uint32_t sl = mix32(k) & (DDP_TAB - 1);; sl = (sl + 1) & (DDP_TAB - 1)) {
+          uint64_t cur = tab[sl];
           if (cur == EMPTY) {
-            if (atomicAdd(&s_claims, 1u) + 1 > DDP_CAP) s_over = 1;
+            cur = atomicCAS((unsigned long long *)&tab[sl], (unsigned long long)EMPTY, (unsigned long long)e);
+            if (cur == EMPTY) {
+              claimed = true;
+              break;
+            }
+          }
+          if ((uint32_t)(cur >> 32) == k) {
+            if (op == OP_INSERT) {
+              if (cur < e) atomicMax((unsigned long long *)&tab[sl], (unsigned long long)e);
+            } else if (cur > e) {
+              atomicMin((unsigned long long *)&tab[sl], (unsigned long long)e);
+            }
             break;
           }
         }
-        if ((uint32_t)(cur >> 32) == k) {
-          if (op == OP_INSERT)
-            atomicMax((unsigned long long *)&tab[sl], (unsigned long long)e);
-          else
-            atomicMin((unsigned long long *)&tab[sl], (unsigned long long)e);
-          break;
-        }
+      }
+      const uint64_t cm = ballot(claimed);
+      if (cm && lane == __builtin_ctzll(cm)) {
+        const uint32_t c = (uint32_t)__popcll(cm);
+        if (atomicAdd(&s_claims, c) + c > DDP_CAP) s_over = 1;
       }
     }
     if (over) break;

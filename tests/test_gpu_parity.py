@@ -252,6 +252,30 @@ def test_dedupe_partition_beyond_its_lds_table(H, kind):
     t.close()
 
 
+def test_dedupe_every_partition_falls_back(H):
+    """An insert batch of 2^22 distinct keys plus 2^20 repeats (no
+    HIVE_UNIQUE): about 8,200 distinct keys per dedupe partition, more than
+    the LDS table takes, so every partition resolves in its own HBM table at
+    once.  The last occurrence of each key wins, as in the dictionary."""
+    n_keys, n_rep = 1 << 22, 1 << 20
+    case(f"dedupe with every partition in its fallback table: {n_keys} keys + {n_rep} repeats")
+    rng = np.random.default_rng(47)
+    keys = wl.KeyStream(47).range(0, n_keys)
+    ins = np.concatenate([keys, keys[rng.integers(0, n_keys, n_rep)]])
+    perm = rng.permutation(ins.size)
+    ins = ins[perm]
+    vals = rng.integers(1, 1 << 32, ins.size, dtype=np.uint64).astype(np.uint32)
+    nb = int(np.ceil(n_keys / (0.6 * 16)))
+    t = H.Table(nb, max_batch=ins.size)
+    o = oracle.O1(n_keys)
+    t.insert(dev(ins), dev(vals))
+    o.insert(ins, vals)
+    st = t.stats()
+    assert st["status"] == H.HIVE_OK and st["live"] == n_keys == len(o), st
+    assert np.array_equal(t.dump(), o.dump())
+    t.close()
+
+
 @pytest.mark.parametrize("path", ["plain", "persistent"])
 def test_dedupe_delete_batch_sized_from_the_batch(H, path):
     """A delete batch with repeats (no HIVE_UNIQUE) on a table whose scratch
