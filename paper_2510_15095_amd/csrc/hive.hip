@@ -3733,11 +3733,15 @@ static hive_status launch_dedupe(uint64_t *dd, uint32_t mode, const uint8_t *d_o
   d.keys = d_keys;
   d.mode = mode;
   hipLaunchKernelGGL(ddp_collect_kernel, dim3((unsigned)(nt * d.nch)), dim3(BLOCK), 0, st, d);
+  *win = d.win;
+  // a batch of one chunk: the chunk's winners are the batch's (the serving
+  // loop's requests are mostly this small, and each launch costs the host
+  // several microseconds)
+  if (d.nch == 1) return launch_check();
   hipLaunchKernelGGL(ddp_segsum_kernel, dim3((unsigned)(nt * d.nseg)), dim3(BLOCK), 0, st, d);
   hipLaunchKernelGGL(ddp_scan_kernel, dim3(nt * (DDP_BINS / 64)), dim3(DDP_SCAN_WAVES * 64), 0, st, d);
   hipLaunchKernelGGL(ddp_scatter_kernel, dim3((unsigned)(nt * d.nseg)), dim3(BLOCK), 0, st, d);
   hipLaunchKernelGGL(ddp_resolve_kernel, dim3(nt * DDP_BINS), dim3(BLOCK), 0, st, d);
-  *win = d.win;
   return launch_check();
 }
 
