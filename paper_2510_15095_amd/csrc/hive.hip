@@ -3588,11 +3588,13 @@ static int resize_rounds(const hive_table *h) {
   return r;
 }
 
+// merges: the call may contract (pass 2 moves merge pairs; a split-only call
+// skips its launches, which would find nothing to do)
 template <int S>
-static void launch_resize_passes(const ResizeArgs &ra, int rounds, hipStream_t st) {
+static void launch_resize_passes(const ResizeArgs &ra, int rounds, bool merges, hipStream_t st) {
   for (int r = 0; r < rounds; ++r) {
     hipLaunchKernelGGL(resize_pass1_kernel<S>, dim3(RESIZE_GRID), dim3(BLOCK), 0, st, ra);
-    hipLaunchKernelGGL(resize_pass2_kernel<S>, dim3(RESIZE_GRID), dim3(BLOCK), 0, st, ra);
+    if (merges) hipLaunchKernelGGL(resize_pass2_kernel<S>, dim3(RESIZE_GRID), dim3(BLOCK), 0, st, ra);
   }
 }
 
@@ -3628,10 +3630,12 @@ static hive_status resize_sequence(hive_table *h, uint32_t mode, uint64_t amount
                        d_ops, amount);
   hipLaunchKernelGGL(resize_plan_kernel, dim3(1), dim3(1), 0, st, ra, mode, amount);
   const int rounds = resize_rounds(h);
+  // pre-batch growth and explicit splits never merge
+  const bool merges = mode == PLAN_POST || mode == PLAN_MERGE;
   switch (h->S) {
-    case 16: launch_resize_passes<16>(ra, rounds, st); break;
-    case 32: launch_resize_passes<32>(ra, rounds, st); break;
-    default: launch_resize_passes<64>(ra, rounds, st); break;
+    case 16: launch_resize_passes<16>(ra, rounds, merges, st); break;
+    case 32: launch_resize_passes<32>(ra, rounds, merges, st); break;
+    default: launch_resize_passes<64>(ra, rounds, merges, st); break;
   }
   phase_mark(h, HIVE_PHASE_DRAIN, st);
   hipLaunchKernelGGL(drain_kernel, dim3(DRAIN_GRID), dim3(BLOCK), 0, st, h->d_stash, h->stash_cap, h->d_pending,
