@@ -1811,6 +1811,20 @@ __global__ __launch_bounds__(BLOCK) void count_inserts_kernel(Ctl *c, const uint
   if (threadIdx.x == 0 && block_sum) add64(&c->plan_inserts, block_sum);
 }
 
+// A mixed batch's insert count and the plan in one block (batches of at most
+// BLOCK * 16 operations: one launch fewer).
+__global__ __launch_bounds__(BLOCK) void count_and_plan_kernel(ResizeArgs a, const uint8_t *ops, uint64_t n) {
+  __shared__ unsigned long long block_sum;
+  if (threadIdx.x == 0) block_sum = 0;
+  __syncthreads();
+  unsigned long long mine = 0;
+  for (uint64_t i = threadIdx.x; i < n; i += BLOCK) mine += ops[i] == OP_INSERT;
+  mine = wave_sum64(mine);
+  if ((threadIdx.x & 63) == 0 && mine) atomicAdd(&block_sum, mine);
+  __syncthreads();
+  if (threadIdx.x == 0) plan_start(a.ctl, a, PLAN_PRE_MIXED, block_sum);
+}
+
 __global__ void resize_plan_kernel(ResizeArgs a, uint32_t mode, uint64_t amount) {
   uint64_t n = amount;
   if (mode == PLAN_PRE_MIXED) {
@@ -3625,10 +3639,14 @@ static hive_status resize_sequence(hive_table *h, uint32_t mode, uint64_t amount
   ResizeArgs ra{h->d_buckets, h->d_hint, h->d_ctl, h->S, h->cfg.resize_k, h->cfg.lf_expand_pct,
                 h->cfg.lf_contract_pct};
   phase_mark(h, HIVE_PHASE_RESIZE, st);
-  if (mode == PLAN_PRE_MIXED)
-    hipLaunchKernelGGL(count_inserts_kernel, dim3(grid_for(amount, BLOCK * 16ull, 1024)), dim3(BLOCK), 0, st, h->d_ctl,
-                       d_ops, amount);
-  hipLaunchKernelGGL(resize_plan_kernel, dim3(1), dim3(1), 0, st, ra, mode, amount);
+  if (mode == PLAN_PRE_MIXED && amount <= BLOCK * 16ull) {
+    hipLaunchKernelGGL(count_and_plan_kernel, dim3(1), dim3(BLOCK), 0, st, ra, d_ops, amount);
+  } else {
+    if (mode == PLAN_PRE_MIXED)
+      hipLaunchKernelGGL(count_inserts_kernel, dim3(grid_for(amount, BLOCK * 16ull, 1024)), dim3(BLOCK), 0, st,
+                         h->d_ctl, d_ops, amount);
+    hipLaunchKernelGGL(resize_plan_kernel, dim3(1), dim3(1), 0, st, ra, mode, amount);
+  }
   const int rounds = resize_rounds(h);
   // pre-batch growth and explicit splits never merge
   const bool merges = mode == PLAN_POST || mode == PLAN_MERGE;
