@@ -874,6 +874,16 @@ __device__ __forceinline__ OpsView read_view(const Ctl *c, uint64_t stash_cap, u
   return v;
 }
 
+// A wave's key-count change and reserved-key count, added to shard
+// unit % NSHARD by its first lane.
+__device__ __forceinline__ void ops_counts_add(Ctl *c, uint64_t unit, int64_t live_acc, uint64_t bad_acc) {
+  if ((threadIdx.x & 63) == 0) {
+    Shard *shd = shard_of(c, unit % NSHARD);
+    if (live_acc != 0) add64(&shd->live, (uint64_t)live_acc);
+    if (bad_acc) add64(&shd->invalid_keys, bad_acc);
+  }
+}
+
 // P1 for one tile of WAVES x 64 operations [tile * 256, tile * 256 + 256).
 // BOTH: probe both candidates in one round for every operation (inserts of
 // new keys always need both; for lookups and deletes it trades bytes for one
@@ -883,7 +893,8 @@ __device__ __forceinline__ OpsView read_view(const Ctl *c, uint64_t stash_cap, u
 // by the operations that found their key in neither of the first two.
 template <int S, uint32_t MODE, bool BOTH, int PAIR = PAIR_BITHASH, int PIPE = Traits<S>::CH>
 __device__ __forceinline__ void ops_tile(const OpsArgs &a, const OpsView &view, uint64_t tile,
-                                         OpsShared<S, PairArity<PAIR>::D> &sh) {
+                                         OpsShared<S, PairArity<PAIR>::D> &sh, int64_t &live_acc,
+                                         uint64_t &bad_acc) {
   using T = Traits<S>;
   using Mask = typename T::Mask;
   constexpr bool D3 = PairArity<PAIR>::D == 3;
@@ -1110,17 +1121,14 @@ __device__ __forceinline__ void ops_tile(const OpsArgs &a, const OpsView &view, 
     base = read_lane64(base, leader);
     if (to_wl) a.wl[(tile % NSHARD) * a.wl_seg_cap + base + rank_below(wl_mask)] = kv;
   }
-  // key count and reserved keys: one atomic per wave on the wave's shard
-  // (aggregating the block's waves into one atomic per tile measured 2-4%
-  // slower on bulk inserts and lookups: the two block barriers cost more
-  // than the atomics, which do not queue enough to matter here)
+  // key count and reserved keys: summed per wave in registers over the
+  // wave's tiles (the caller adds them to its shard once: device atomics
+  // run at about 26 G/s, and an insert batch already spends one per
+  // operation; aggregating the block's waves per tile instead measured 2-4%
+  // slower, its two block barriers costing more than the atomics)
   const uint64_t up = ballot(dl > 0), down = ballot(dl < 0), bad = ballot(active && !valid);
-  if (lane == 0) {
-    Shard *sh = shard_of(a.ctl, (tile * WAVES + wv) % NSHARD);
-    const int64_t d = (int64_t)__popcll(up) - (int64_t)__popcll(down);
-    if (d != 0) add64(&sh->live, (uint64_t)d);
-    if (bad) add64(&sh->invalid_keys, (uint64_t)__popcll(bad));
-  }
+  live_acc += (int64_t)__popcll(up) - (int64_t)__popcll(down);
+  bad_acc += (uint64_t)__popcll(bad);
   if (active) {
     if (MODE == OP_LOOKUP || MODE == OP_MIXED) {
       if (a.vals_out) __builtin_nontemporal_store(out_v, &a.vals_out[i]);
@@ -1140,8 +1148,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) vo
   __shared__ OpsShared<S, PairArity<PAIR>::D> sh;
   const OpsView view = read_view(a.ctl, a.stash_cap, a.pending_cap);
   const uint64_t ntiles = (a.n + BLOCK - 1) / BLOCK;
+  int64_t live_acc = 0;
+  uint64_t bad_acc = 0;
   for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
-    ops_tile<S, MODE, BOTH, PAIR, PIPE>(a, view, tile, sh);
+    ops_tile<S, MODE, BOTH, PAIR, PIPE>(a, view, tile, sh, live_acc, bad_acc);
+  ops_counts_add(a.ctl, (uint64_t)blockIdx.x * WAVES + (threadIdx.x >> 6), live_acc, bad_acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -2737,12 +2748,15 @@ __device__ __forceinline__ void run_chunk(ReqState *r, const ReqDesc &d, uint32_
       const OpsView view = read_view(d.t.ctl, d.t.stash_cap, d.t.pending_cap);
       // one probe variant only (the second candidate after a miss): a
       // second inlined copy would cost the resident grid occupancy
+      int64_t live_acc = 0;
+      uint64_t bad_acc = 0;
       switch (d.mode) {
-        case OP_INSERT: ops_tile<S, OP_INSERT, false>(a, view, c, sh); break;
-        case OP_DELETE: ops_tile<S, OP_DELETE, false>(a, view, c, sh); break;
-        case OP_LOOKUP: ops_tile<S, OP_LOOKUP, false>(a, view, c, sh); break;
-        default: ops_tile<S, OP_MIXED, false>(a, view, c, sh); break;
+        case OP_INSERT: ops_tile<S, OP_INSERT, false>(a, view, c, sh, live_acc, bad_acc); break;
+        case OP_DELETE: ops_tile<S, OP_DELETE, false>(a, view, c, sh, live_acc, bad_acc); break;
+        case OP_LOOKUP: ops_tile<S, OP_LOOKUP, false>(a, view, c, sh, live_acc, bad_acc); break;
+        default: ops_tile<S, OP_MIXED, false>(a, view, c, sh, live_acc, bad_acc); break;
       }
+      ops_counts_add(d.t.ctl, c * WAVES + (threadIdx.x >> 6), live_acc, bad_acc);
       break;
     }
     default: break;  // PH_START: no data-parallel work
