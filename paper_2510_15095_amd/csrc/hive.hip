@@ -327,35 +327,48 @@ __device__ __forceinline__ uint32_t ddp_op(const DdpArgs &d, uint32_t ti) {
   return d.mode == OP_MIXED ? (ti == 0 ? OP_INSERT : OP_DELETE) : d.mode;
 }
 
-// Step 1.  Block (ti, c): operation type ti, chunk c.
+// Step 1.  Block c: chunk c, every recorded operation type at once (a mixed
+// batch's inserts and deletes share the block's loads and table: their keys
+// are disjoint by contract, so one table collapses both).  A table entry
+// holds the key, the operation's type in bit 31 and its index within the
+// chunk: a key's entries share one type, so the per-type rule (inserts keep
+// the last occurrence, deletes the first) orders them by index as before.
 __global__ __launch_bounds__(BLOCK) void ddp_collect_kernel(DdpArgs d) {
   __shared__ uint64_t tab[DD_LDS];
-  const uint32_t ti = (uint32_t)(blockIdx.x / d.nch);
-  const uint64_t c = blockIdx.x % d.nch;
-  const uint32_t op = ddp_op(d, ti);
+  const uint64_t c = blockIdx.x;
   const uint64_t base = c * DD_CHUNK;
-  // the chunk's operands first, all loads in flight together
+  static_assert(DD_CHUNK <= (1ull << 31), "chunk indices share a word with the type bit");
+  // the chunk's operands first, all loads in flight together; ty: the
+  // operation's type (0 or 1), or -1 when it is not recorded
   uint32_t kk[DD_PER_THREAD];
-  bool take[DD_PER_THREAD];
+  int ty[DD_PER_THREAD];
 #pragma unroll
   for (int j = 0; j < DD_PER_THREAD; ++j) {
     const uint64_t i = base + (uint64_t)j * BLOCK + threadIdx.x;
-    take[j] = i < d.n && (d.mode != OP_MIXED || d.ops[i] == op);
+    ty[j] = -1;
+    if (i < d.n) {
+      if (d.mode != OP_MIXED) ty[j] = 0;
+      else {
+        const uint8_t o = d.ops[i];
+        ty[j] = o == OP_INSERT ? 0 : (o == OP_DELETE ? 1 : -1);
+      }
+    }
     kk[j] = i < d.n ? d.keys[i] : 0u;
   }
-  // the flags of this type's operations start cleared; the chunk's winners
-  // set theirs below (after barriers of this block), and the resolve step
-  // clears those that lose to another chunk
+  // the flags of recorded operations start cleared; the chunk's winners set
+  // theirs below (after barriers of this block), and the resolve step clears
+  // those that lose to another chunk
 #pragma unroll
   for (int j = 0; j < DD_PER_THREAD; ++j)
-    if (take[j]) d.win[base + (uint64_t)j * BLOCK + threadIdx.x] = 0;
+    if (ty[j] >= 0) d.win[base + (uint64_t)j * BLOCK + threadIdx.x] = 0;
   for (int j = threadIdx.x; j < DD_LDS; j += BLOCK) tab[j] = EMPTY;
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < DD_PER_THREAD; ++j) {
     const uint32_t k = kk[j];
-    if (!take[j] || !valid_key(k)) continue;
-    const uint64_t e = ((uint64_t)k << 32) | (uint32_t)(base + (uint64_t)j * BLOCK + threadIdx.x);
+    if (ty[j] < 0 || !valid_key(k)) continue;
+    const bool keep_last = ddp_op(d, (uint32_t)ty[j]) == OP_INSERT;
+    const uint64_t e = ((uint64_t)k << 32) | ((uint32_t)ty[j] << 31) | (uint32_t)(j * BLOCK + threadIdx.x);
     for (uint32_t s = mix32(k) & (DD_LDS - 1);; s = (s + 1) & (DD_LDS - 1)) {
       uint64_t cur = tab[s];
       if (cur == EMPTY) {
@@ -365,7 +378,7 @@ __global__ __launch_bounds__(BLOCK) void ddp_collect_kernel(DdpArgs d) {
       if ((uint32_t)(cur >> 32) == k) {
         // only an update that can change the word (a hot key's later
         // occurrences mostly lose, and atomics on one word serialize)
-        if (op == OP_INSERT) {
+        if (keep_last) {
           if (cur < e) atomicMax((unsigned long long *)&tab[s], (unsigned long long)e);
         } else if (cur > e) {
           atomicMin((unsigned long long *)&tab[s], (unsigned long long)e);
@@ -375,54 +388,73 @@ __global__ __launch_bounds__(BLOCK) void ddp_collect_kernel(DdpArgs d) {
     }
   }
   __syncthreads();
-  // compact the chunk's distinct keys to the front of the table (wave by
-  // wave, rows in order)
+  // compact the chunk's distinct keys to the front of the table, type 0
+  // first, then type 1 (wave by wave, rows in order)
   constexpr int ROWS = DD_LDS / BLOCK;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   uint64_t row[ROWS];
   uint32_t rank[ROWS];
-  uint32_t mine = 0;
+  uint32_t mine[2] = {0, 0};
 #pragma unroll
   for (int r = 0; r < ROWS; ++r) {
     row[r] = tab[r * BLOCK + threadIdx.x];
-    const uint64_t m = ballot(row[r] != EMPTY);
-    rank[r] = mine + rank_below(m);
-    mine += (uint32_t)__popcll(m);
+    const bool used = row[r] != EMPTY, t1 = ((uint32_t)row[r] >> 31) != 0;
+    const uint64_t m0 = ballot(used && !t1), m1 = ballot(used && t1);
+    rank[r] = t1 ? mine[1] + rank_below(m1) : mine[0] + rank_below(m0);
+    mine[0] += (uint32_t)__popcll(m0);
+    mine[1] += (uint32_t)__popcll(m1);
   }
   __syncthreads();  // every wave holds its rows in registers: tab may be overwritten
   // the waves' counts go to the table's last words (a chunk has at most
-  // DD_CHUNK = DD_LDS / 2 distinct keys, so the compacted list stays clear
+  // DD_CHUNK = DD_LDS / 2 distinct keys, so the compacted lists stay clear
   // of them), keeping the block's LDS at 32 KiB (five blocks per CU)
-  static_assert(DD_CHUNK + WAVES <= DD_LDS, "wave counts overlap the compacted list");
-  if (lane == 0) tab[DD_LDS - 1 - wv] = mine;
+  static_assert(DD_CHUNK + 2 * WAVES <= DD_LDS, "wave counts overlap the compacted lists");
+  if (lane == 0) {
+    tab[DD_LDS - 1 - wv] = mine[0];
+    tab[DD_LDS - 1 - WAVES - wv] = mine[1];
+  }
   __syncthreads();
-  uint32_t off = 0, cnt = 0;
+  uint32_t off0 = 0, off1 = 0, cnt0 = 0, cnt1 = 0;
 #pragma unroll
   for (int w = 0; w < WAVES; ++w) {
-    const uint32_t cw = (uint32_t)tab[DD_LDS - 1 - w];
-    off += w < wv ? cw : 0u;
-    cnt += cw;
+    const uint32_t c0w = (uint32_t)tab[DD_LDS - 1 - w], c1w = (uint32_t)tab[DD_LDS - 1 - WAVES - w];
+    off0 += w < wv ? c0w : 0u;
+    off1 += w < wv ? c1w : 0u;
+    cnt0 += c0w;
+    cnt1 += c1w;
   }
 #pragma unroll
   for (int r = 0; r < ROWS; ++r)
-    if (row[r] != EMPTY) tab[off + rank[r]] = row[r];
+    if (row[r] != EMPTY) {
+      const bool t1 = ((uint32_t)row[r] >> 31) != 0;
+      tab[(t1 ? cnt0 + off1 : off0) + rank[r]] = row[r];
+    }
   __syncthreads();
-  // histogram over the partitions, in the table's upper half
-  static_assert(DD_CHUNK * 2 >= DDP_BINS && DD_CHUNK + DDP_BINS / 2 <= DD_LDS - WAVES, "histogram room");
+  // histograms over the partitions, one per type, in the table's upper half
+  static_assert(DD_CHUNK * 2 >= DDP_BINS && DD_CHUNK + DDP_BINS <= DD_LDS - 2 * WAVES, "histogram room");
   uint32_t *bins = (uint32_t *)(tab + DD_CHUNK);
-  for (int b = threadIdx.x; b < DDP_BINS; b += BLOCK) bins[b] = 0u;
+  for (int b = threadIdx.x; b < 2 * DDP_BINS; b += BLOCK) bins[b] = 0u;
   __syncthreads();
-  uint64_t *st = d.stage + ((uint64_t)ti * d.nch + c) * DD_CHUNK;
-  for (uint32_t q = threadIdx.x; q < cnt; q += BLOCK) {
-    const uint64_t e = tab[q];
-    st[q] = e;
-    d.win[(uint32_t)e] = 1;  // within this chunk's flags
-    atomicAdd(&bins[ddp_bin((uint32_t)(e >> 32))], 1u);
+  uint64_t *st0 = d.stage + c * DD_CHUNK, *st1 = d.stage + ((uint64_t)d.nch + c) * DD_CHUNK;
+  for (uint32_t q = threadIdx.x; q < cnt0 + cnt1; q += BLOCK) {
+    const uint64_t t = tab[q];
+    const uint32_t k = (uint32_t)(t >> 32), i = (uint32_t)(base + ((uint32_t)t & (DD_CHUNK - 1)));
+    const uint64_t e = ((uint64_t)k << 32) | i;
+    const bool t1 = q >= cnt0;
+    if (t1) st1[q - cnt0] = e;
+    else st0[q] = e;
+    d.win[i] = 1;  // within this chunk's flags
+    atomicAdd(&bins[(t1 ? DDP_BINS : 0) + ddp_bin(k)], 1u);
   }
   __syncthreads();
-  uint16_t *h = d.hist + ((uint64_t)ti * d.nch + c) * DDP_BINS;
-  for (int b = threadIdx.x; b < DDP_BINS; b += BLOCK) h[b] = (uint16_t)bins[b];
-  if (threadIdx.x == 0) d.cnt[(uint64_t)ti * d.nch + c] = cnt;
+  for (uint32_t ti = 0; ti < d.nt; ++ti) {
+    uint16_t *h = d.hist + ((uint64_t)ti * d.nch + c) * DDP_BINS;
+    for (int b = threadIdx.x; b < DDP_BINS; b += BLOCK) h[b] = (uint16_t)bins[ti * DDP_BINS + b];
+  }
+  if (threadIdx.x == 0) {
+    d.cnt[c] = cnt0;
+    if (d.nt > 1) d.cnt[(uint64_t)d.nch + c] = cnt1;
+  }
 }
 
 // Step 2.  Block (ti, s): the histograms of segment s summed.
@@ -477,10 +509,13 @@ __global__ __launch_bounds__(DDP_SCAN_WAVES * 64) void ddp_scan_kernel(DdpArgs d
 }
 
 // Start of every partition in `rec` (exclusive prefix of the totals over
-// (type, partition)) into out[0 .. nt * DDP_BINS); the whole block calls it.
+// (type, partition)) into out[0 .. nt * DDP_BINS); the whole block (NT
+// threads) calls it.
+template <int NT>
 __device__ __forceinline__ void ddp_starts(const DdpArgs &d, uint32_t *out) {
-  __shared__ uint32_t s_wave[WAVES];
-  constexpr int PER = 2 * DDP_BINS / BLOCK;  // values per thread (up to two types)
+  __shared__ uint32_t s_wave[NT / 64];
+  constexpr int PER = 2 * DDP_BINS / NT;  // values per thread (up to two types)
+  static_assert(PER >= 1 && PER * NT == 2 * DDP_BINS, "partition counts per block");
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const uint32_t total = d.nt * DDP_BINS;
   uint32_t v[PER], mine = 0;
@@ -508,14 +543,19 @@ __device__ __forceinline__ void ddp_starts(const DdpArgs &d, uint32_t *out) {
   __syncthreads();
 }
 
+// The scatter and resolve steps wait on dependent loads and LDS atomics with
+// few blocks per CU (a grid of a few hundred, and the resolve table's 64 KiB
+// of LDS), so their blocks are 16 waves wide.
+constexpr int DDP_WIDE = 1024;
+
 // Step 4.  Block (ti, s): the records of segment s to their partitions' runs.
-__global__ __launch_bounds__(BLOCK) void ddp_scatter_kernel(DdpArgs d) {
+__global__ __launch_bounds__(DDP_WIDE) void ddp_scatter_kernel(DdpArgs d) {
   __shared__ uint32_t starts[2 * DDP_BINS];
   const uint32_t ti = (uint32_t)(blockIdx.x / d.nseg);
   const uint64_t s = blockIdx.x % d.nseg;
-  ddp_starts(d, starts);
+  ddp_starts<DDP_WIDE>(d, starts);
   uint32_t *cur = starts + ti * DDP_BINS;  // this type's cursors
-  for (int b = threadIdx.x; b < DDP_BINS; b += BLOCK) cur[b] += d.seg[((uint64_t)ti * d.nseg + s) * DDP_BINS + b];
+  for (int b = threadIdx.x; b < DDP_BINS; b += DDP_WIDE) cur[b] += d.seg[((uint64_t)ti * d.nseg + s) * DDP_BINS + b];
   __syncthreads();
   // the segment's staged records as one list (chunk j holds [pre[j],
   // pre[j + 1])), DDP_SCATTER_LOADS loads in flight per thread at a time
@@ -527,11 +567,11 @@ __global__ __launch_bounds__(BLOCK) void ddp_scatter_kernel(DdpArgs d) {
   const uint32_t total = pre[DDP_SEG];
   const uint64_t *st = d.stage + ((uint64_t)ti * d.nch + c0) * DD_CHUNK;
   constexpr int U = DDP_SCATTER_LOADS;
-  for (uint32_t t0 = threadIdx.x; t0 < total; t0 += U * BLOCK) {
+  for (uint32_t t0 = threadIdx.x; t0 < total; t0 += U * DDP_WIDE) {
     uint64_t e[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const uint32_t t = t0 + u * BLOCK;
+      const uint32_t t = t0 + u * DDP_WIDE;
       e[u] = EMPTY;
       if (t < total) {
         int j = 0;
@@ -547,25 +587,25 @@ __global__ __launch_bounds__(BLOCK) void ddp_scatter_kernel(DdpArgs d) {
 }
 
 // Step 5.  Block (ti, b): partition b of type ti.
-__global__ __launch_bounds__(BLOCK) void ddp_resolve_kernel(DdpArgs d) {
+__global__ __launch_bounds__(DDP_WIDE) void ddp_resolve_kernel(DdpArgs d) {
   __shared__ uint64_t tab[DDP_TAB];
   __shared__ uint32_t starts[2 * DDP_BINS];
   __shared__ uint32_t s_claims, s_over;
   const uint32_t ti = blockIdx.x / DDP_BINS, b = blockIdx.x % DDP_BINS;
   const uint32_t op = ddp_op(d, ti);
-  ddp_starts(d, starts);
+  ddp_starts<DDP_WIDE>(d, starts);
   const uint64_t start = starts[ti * DDP_BINS + b], count = d.tot[ti * DDP_BINS + b];
   if (count == 0) return;  // the same in the whole block
-  for (int j = threadIdx.x; j < DDP_TAB; j += BLOCK) tab[j] = EMPTY;
+  for (int j = threadIdx.x; j < DDP_TAB; j += DDP_WIDE) tab[j] = EMPTY;
   if (threadIdx.x == 0) {
     s_claims = 0;
     s_over = 0;
   }
   __syncthreads();
   const uint64_t *rec = d.rec + start;
-  // at most BLOCK claims land after the one that crosses DDP_CAP (one per
+  // at most DDP_WIDE claims land after the one that crosses DDP_CAP (one per
   // thread in flight), so the table never fills and every probe ends
-  static_assert(DDP_CAP + BLOCK < DDP_TAB, "resolve table headroom");
+  static_assert(DDP_CAP + DDP_WIDE < DDP_TAB, "resolve table headroom");
   // records DDP_RESOLVE_LOADS at a time per thread, all loads in flight.
   // New keys are counted per wave and record step (one LDS atomic for the
   // wave's claims: one per claim serialized the block on a single word),
@@ -573,11 +613,11 @@ __global__ __launch_bounds__(BLOCK) void ddp_resolve_kernel(DdpArgs d) {
   // claims at most one slot after the count crosses DDP_CAP
   constexpr int U = DDP_RESOLVE_LOADS;
   const int lane = threadIdx.x & 63;
-  for (uint64_t r0 = threadIdx.x; r0 < count; r0 += (uint64_t)U * BLOCK) {
+  for (uint64_t r0 = threadIdx.x; r0 < count; r0 += (uint64_t)U * DDP_WIDE) {
     uint64_t es[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const uint64_t r = r0 + (uint64_t)u * BLOCK;
+      const uint64_t r = r0 + (uint64_t)u * DDP_WIDE;
       es[u] = r < count ? rec[r] : EMPTY;
     }
     bool over = false;
@@ -620,11 +660,11 @@ __global__ __launch_bounds__(BLOCK) void ddp_resolve_kernel(DdpArgs d) {
     // every record's flag was set by its chunk: clear the losers' (a key
     // recorded by several chunks), a few scattered stores instead of one
     // per distinct key
-    for (uint64_t r0 = threadIdx.x; r0 < count; r0 += (uint64_t)U * BLOCK) {
+    for (uint64_t r0 = threadIdx.x; r0 < count; r0 += (uint64_t)U * DDP_WIDE) {
       uint64_t es[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const uint64_t r = r0 + (uint64_t)u * BLOCK;
+        const uint64_t r = r0 + (uint64_t)u * DDP_WIDE;
         es[u] = r < count ? rec[r] : EMPTY;
       }
 #pragma unroll
@@ -645,10 +685,10 @@ __global__ __launch_bounds__(BLOCK) void ddp_resolve_kernel(DdpArgs d) {
   // atomics (stores written through, so that the claims see them)
   uint64_t *ft = d.stage + 2 * start;
   const uint64_t m = 2 * count;
-  for (uint64_t j = threadIdx.x; j < m; j += BLOCK)
+  for (uint64_t j = threadIdx.x; j < m; j += DDP_WIDE)
     __hip_atomic_store(&ft[j], EMPTY, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
-  for (uint64_t r = threadIdx.x; r < count; r += BLOCK) {
+  for (uint64_t r = threadIdx.x; r < count; r += DDP_WIDE) {
     const uint64_t e = rec[r];
     const uint32_t k = (uint32_t)(e >> 32);
     for (uint64_t sl = mix32(k) % m;; sl = (sl + 1 == m) ? 0 : sl + 1) {
@@ -666,7 +706,7 @@ __global__ __launch_bounds__(BLOCK) void ddp_resolve_kernel(DdpArgs d) {
   }
   __syncthreads();
   // the record left in its key's word is the winner; clear the others' flags
-  for (uint64_t r = threadIdx.x; r < count; r += BLOCK) {
+  for (uint64_t r = threadIdx.x; r < count; r += DDP_WIDE) {
     const uint64_t e = rec[r];
     const uint32_t k = (uint32_t)(e >> 32);
     for (uint64_t sl = mix32(k) % m;; sl = (sl + 1 == m) ? 0 : sl + 1) {
@@ -3768,7 +3808,7 @@ static hive_status launch_dedupe(uint64_t *dd, uint32_t mode, const uint8_t *d_o
   d.ops = d_ops;
   d.keys = d_keys;
   d.mode = mode;
-  hipLaunchKernelGGL(ddp_collect_kernel, dim3((unsigned)(nt * d.nch)), dim3(BLOCK), 0, st, d);
+  hipLaunchKernelGGL(ddp_collect_kernel, dim3((unsigned)d.nch), dim3(BLOCK), 0, st, d);
   *win = d.win;
   // a batch of one chunk: the chunk's winners are the batch's (the serving
   // loop's requests are mostly this small, and each launch costs the host
@@ -3776,8 +3816,8 @@ static hive_status launch_dedupe(uint64_t *dd, uint32_t mode, const uint8_t *d_o
   if (d.nch == 1) return launch_check();
   hipLaunchKernelGGL(ddp_segsum_kernel, dim3((unsigned)(nt * d.nseg)), dim3(BLOCK), 0, st, d);
   hipLaunchKernelGGL(ddp_scan_kernel, dim3(nt * (DDP_BINS / 64)), dim3(DDP_SCAN_WAVES * 64), 0, st, d);
-  hipLaunchKernelGGL(ddp_scatter_kernel, dim3((unsigned)(nt * d.nseg)), dim3(BLOCK), 0, st, d);
-  hipLaunchKernelGGL(ddp_resolve_kernel, dim3(nt * DDP_BINS), dim3(BLOCK), 0, st, d);
+  hipLaunchKernelGGL(ddp_scatter_kernel, dim3((unsigned)(nt * d.nseg)), dim3(DDP_WIDE), 0, st, d);
+  hipLaunchKernelGGL(ddp_resolve_kernel, dim3(nt * DDP_BINS), dim3(DDP_WIDE), 0, st, d);
   return launch_check();
 }
 
