@@ -300,7 +300,7 @@ constexpr int DD_LDS = 2 * (int)DD_CHUNK;
 constexpr int DDP_BITS = 9;
 constexpr int DDP_BINS = 1 << DDP_BITS;  // partitions per operation type
 constexpr uint64_t DDP_SEG = 8;          // chunks per segment
-constexpr int DDP_SCATTER_LOADS = 4;     // staged records per thread in flight (scatter)
+constexpr int DDP_SCATTER_LOADS = 8;     // staged records per thread in flight (scatter)
 constexpr int DDP_RESOLVE_LOADS = 8;     // records per thread in flight (resolve)
 constexpr int DDP_TAB = 8192;            // entries of a resolve table (64 KiB)
 constexpr uint32_t DDP_CAP = DDP_TAB * 3 / 4;
@@ -332,7 +332,7 @@ __device__ __forceinline__ uint32_t ddp_op(const DdpArgs &d, uint32_t ti) {
 // are disjoint by contract, so one table collapses both).  A table entry
 // holds the key, the operation's type in bit 31 and its index within the
 // chunk: a key's entries share one type, so the per-type rule (inserts keep
-// the last occurrence, deletes the first) orders them by index as before.
+// the last occurrence, deletes the first) compares their indices alone.
 __global__ __launch_bounds__(BLOCK) void ddp_collect_kernel(DdpArgs d) {
   __shared__ uint64_t tab[DD_LDS];
   const uint64_t c = blockIdx.x;
@@ -549,16 +549,29 @@ __device__ __forceinline__ void ddp_starts(const DdpArgs &d, uint32_t *out) {
 constexpr int DDP_WIDE = 1024;
 
 // Step 4.  Block (ti, s): the records of segment s to their partitions' runs.
+// A record's place in its partition's run is free, so each round of up to
+// DDP_SCATTER_ROUND records is first sorted by partition in LDS (a counting
+// sort) and then written run by run: consecutive lanes store consecutive
+// words of one run, where one scattered 8-byte store per record had been
+// bound by the memory system's rate of random stores.
+constexpr int DDP_SCATTER_ROUND = DDP_WIDE * DDP_SCATTER_LOADS;
 __global__ __launch_bounds__(DDP_WIDE) void ddp_scatter_kernel(DdpArgs d) {
   __shared__ uint32_t starts[2 * DDP_BINS];
+  __shared__ uint32_t lcnt[DDP_BINS], lbase[DDP_BINS], s_sum[DDP_BINS / 64];
+  __shared__ uint64_t sorted[DDP_SCATTER_ROUND];
   const uint32_t ti = (uint32_t)(blockIdx.x / d.nseg);
   const uint64_t s = blockIdx.x % d.nseg;
   ddp_starts<DDP_WIDE>(d, starts);
   uint32_t *cur = starts + ti * DDP_BINS;  // this type's cursors
-  for (int b = threadIdx.x; b < DDP_BINS; b += DDP_WIDE) cur[b] += d.seg[((uint64_t)ti * d.nseg + s) * DDP_BINS + b];
+  static_assert(DDP_BINS <= DDP_WIDE, "one partition per thread");
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  if (tid < DDP_BINS) {
+    cur[tid] += d.seg[((uint64_t)ti * d.nseg + s) * DDP_BINS + tid];
+    lcnt[tid] = 0;
+  }
   __syncthreads();
   // the segment's staged records as one list (chunk j holds [pre[j],
-  // pre[j + 1])), DDP_SCATTER_LOADS loads in flight per thread at a time
+  // pre[j + 1]))
   const uint64_t c0 = s * DDP_SEG, c1 = min(c0 + DDP_SEG, d.nch);
   uint32_t pre[DDP_SEG + 1];
   pre[0] = 0;
@@ -567,11 +580,13 @@ __global__ __launch_bounds__(DDP_WIDE) void ddp_scatter_kernel(DdpArgs d) {
   const uint32_t total = pre[DDP_SEG];
   const uint64_t *st = d.stage + ((uint64_t)ti * d.nch + c0) * DD_CHUNK;
   constexpr int U = DDP_SCATTER_LOADS;
-  for (uint32_t t0 = threadIdx.x; t0 < total; t0 += U * DDP_WIDE) {
+  for (uint32_t r0 = 0; r0 < total; r0 += DDP_SCATTER_ROUND) {  // the same rounds in every thread
+    const uint32_t nr = min((uint32_t)DDP_SCATTER_ROUND, total - r0);
     uint64_t e[U];
+    uint32_t bin[U], rk[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const uint32_t t = t0 + u * DDP_WIDE;
+      const uint32_t t = r0 + u * DDP_WIDE + tid;
       e[u] = EMPTY;
       if (t < total) {
         int j = 0;
@@ -580,9 +595,52 @@ __global__ __launch_bounds__(DDP_WIDE) void ddp_scatter_kernel(DdpArgs d) {
         e[u] = st[(uint64_t)j * DD_CHUNK + (t - pre[j])];
       }
     }
+    // each record's rank within its partition in this round
 #pragma unroll
     for (int u = 0; u < U; ++u)
-      if (e[u] != EMPTY) d.rec[atomicAdd(&cur[ddp_bin((uint32_t)(e[u] >> 32))], 1u)] = e[u];
+      if (e[u] != EMPTY) {
+        bin[u] = ddp_bin((uint32_t)(e[u] >> 32));
+        rk[u] = atomicAdd(&lcnt[bin[u]], 1u);
+      }
+    __syncthreads();
+    // exclusive prefix of the round's partition counts
+    uint32_t v = 0, incl = 0;
+    if (tid < DDP_BINS) {
+      v = lcnt[tid];
+      incl = v;
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
+      }
+      if (lane == 63) s_sum[wv] = incl;
+    }
+    __syncthreads();
+    if (tid < DDP_BINS) {
+      uint32_t run = incl - v;
+      for (int w = 0; w < wv; ++w) run += s_sum[w];
+      lbase[tid] = run;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (e[u] != EMPTY) sorted[lbase[bin[u]] + rk[u]] = e[u];
+    __syncthreads();
+    // run by run to the partitions' places
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t p = u * DDP_WIDE + tid;
+      if (p < nr) {
+        const uint64_t x = sorted[p];
+        const uint32_t b = ddp_bin((uint32_t)(x >> 32));
+        d.rec[cur[b] + (p - lbase[b])] = x;
+      }
+    }
+    __syncthreads();
+    if (tid < DDP_BINS) {
+      cur[tid] += lcnt[tid];
+      lcnt[tid] = 0;
+    }
+    __syncthreads();
   }
 }
 
