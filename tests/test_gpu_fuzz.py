@@ -75,6 +75,12 @@ def test_fuzz_against_dictionary(H, seed):
     universe = max(4 * n_pre, 4096)
     n_batches = int(rng.integers(3, 7))
     n_ops = int(rng.choice([64, 257, 1000, 4096]))
+    if grows and nb >= 48 and rng.random() < 0.5:
+        # ten dedupe chunks over two segments; the universe leaves room for
+        # a batch's per-type disjoint keys, and its 40,000 keys fit the
+        # table's growth room (at least 49,152 slots)
+        n_ops = 20_000
+        universe = max(universe, 2 * n_ops)
     if not grows:
         # the new keys of all batches must fit the free slots, the stash and
         # the pending list of a table that cannot grow before a batch
