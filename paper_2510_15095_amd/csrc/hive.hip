@@ -463,8 +463,12 @@ __global__ __launch_bounds__(BLOCK) void ddp_segsum_kernel(DdpArgs d) {
   const uint64_t s = blockIdx.x % d.nseg;
   const uint64_t c0 = s * DDP_SEG, c1 = min(c0 + DDP_SEG, d.nch);
   for (int b = threadIdx.x; b < DDP_BINS; b += BLOCK) {
-    uint32_t sum = 0;
-    for (uint64_t c = c0; c < c1; ++c) sum += d.hist[((uint64_t)ti * d.nch + c) * DDP_BINS + b];
+    uint32_t v[DDP_SEG], sum = 0;  // the segment's loads in flight together
+#pragma unroll
+    for (int j = 0; j < (int)DDP_SEG; ++j)
+      v[j] = c0 + j < c1 ? d.hist[((uint64_t)ti * d.nch + c0 + j) * DDP_BINS + b] : 0u;
+#pragma unroll
+    for (int j = 0; j < (int)DDP_SEG; ++j) sum += v[j];
     d.seg[((uint64_t)ti * d.nseg + s) * DDP_BINS + b] = sum;
   }
 }
@@ -671,8 +675,10 @@ __global__ __launch_bounds__(DDP_WIDE) void ddp_resolve_kernel(DdpArgs d) {
   // claims at most one slot after the count crosses DDP_CAP
   constexpr int U = DDP_RESOLVE_LOADS;
   const int lane = threadIdx.x & 63;
+  uint64_t es[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) es[u] = EMPTY;
   for (uint64_t r0 = threadIdx.x; r0 < count; r0 += (uint64_t)U * DDP_WIDE) {
-    uint64_t es[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const uint64_t r = r0 + (uint64_t)u * DDP_WIDE;
@@ -717,13 +723,16 @@ __global__ __launch_bounds__(DDP_WIDE) void ddp_resolve_kernel(DdpArgs d) {
   if (!s_over) {
     // every record's flag was set by its chunk: clear the losers' (a key
     // recorded by several chunks), a few scattered stores instead of one
-    // per distinct key
+    // per distinct key.  A partition of at most U * DDP_WIDE records was
+    // read in one step, and each thread still holds its records.
+    const bool held = count <= (uint64_t)U * DDP_WIDE;
     for (uint64_t r0 = threadIdx.x; r0 < count; r0 += (uint64_t)U * DDP_WIDE) {
-      uint64_t es[U];
+      if (!held) {
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const uint64_t r = r0 + (uint64_t)u * DDP_WIDE;
-        es[u] = r < count ? rec[r] : EMPTY;
+        for (int u = 0; u < U; ++u) {
+          const uint64_t r = r0 + (uint64_t)u * DDP_WIDE;
+          es[u] = r < count ? rec[r] : EMPTY;
+        }
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
