@@ -1764,6 +1764,160 @@ __global__ __launch_bounds__(BLOCK) void evict_kernel(EvictArgs a) {
   evict_counters(a, unreserved, (uint64_t)blockIdx.x * WAVES + wv, n_evict, n_full, n_side, n_fresh, sl);
 }
 
+// P3 for 16-slot buckets with two candidates, as a launch whose lanes are
+// refilled as their chains end.  Each wave owns a contiguous range of the
+// worklist (at least 64 items); a lane takes the range's next item whenever
+// it holds none, so a wave lasts about as long as its lanes' total work
+// rather than one round per 64 items, each as long as its longest chain
+// (at 95% load a few percent of the chains run all their rounds, and nearly
+// every group of 64 items held one).  A lane steps through one memory round
+// trip at a time:
+//   FRESH   both candidates loaded (step 2 again, two-choice claim);
+//   LOOK    one displacement round of the look-ahead chain: two victims of
+//           the bucket in hand, both alternates loaded in one round trip,
+//           a victim displaced by CAS and its slot claimed from that view;
+//   RELOAD  the bucket in hand loaded again after a displacement CAS found
+//           its slot changed, and its free slots tried.
+// The rounds, the victims and the stash placement are those of evict_chain
+// and evict_round (step 4 reserves room once per wave and step, as there);
+// only the order in which a wave's items run differs.  The grid should be
+// resident at once: a wave's range is not shared.
+template <int PAIR>
+__global__ __launch_bounds__(BLOCK) void evict_lanes_kernel(EvictArgs a) {
+  static_assert(PairArity<PAIR>::D == 2, "two candidate buckets");
+  constexpr int S = 16;
+  using Mask = typename Traits<S>::Mask;
+  __shared__ uint64_t pre[NSHARD + 1];
+  wl_prefix(a.ctl, pre);
+  const uint64_t cnt = pre[NSHARD];
+  if (cnt == 0) return;  // same in every block
+  const Geo geo = read_geo(a.ctl);
+  // the same in every block: an unreserved launch leaves the count alone
+  const bool unreserved = ld_ctl(&a.ctl->stash_count) + cnt <= a.stash_cap;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const uint64_t nw = (uint64_t)gridDim.x * WAVES, wid = (uint64_t)blockIdx.x * WAVES + wv;
+  const uint64_t q = max<uint64_t>(64, (cnt + nw - 1) / nw);
+  const uint64_t end = min(cnt, (wid + 1) * q);
+  uint64_t cursor = wid * q;  // the wave's next item (the same in every lane)
+  const uint32_t max_kicks = a.max_evictions;
+  uint64_t n_evict = 0, n_full = 0, n_side = 0, n_fresh = 0;
+  constexpr int IDLE = 0, FRESH = 1, RELOAD = 2, LOOK = 3;
+  int st = IDLE;
+  uint64_t kv = 0;        // the entry in hand
+  uint32_t b = 0;         // the bucket it is carried into
+  uint32_t kick = 0;      // displacement rounds taken
+  uint64_t w[16], w2v[16];  // LOOK, RELOAD: w holds bucket b's words
+  while (cursor < end || ballot(st != IDLE)) {
+    // lanes without an item take the range's next ones, in lane order
+    const uint64_t nm = ballot(st == IDLE);
+    if (nm && cursor < end) {
+      const uint64_t t = cursor + rank_below(nm);
+      if (st == IDLE && t < end) {
+        kv = a.wl[wl_slot(pre, t, a.wl_seg_cap)];
+        st = FRESH;
+        kick = 0;
+      }
+      cursor += (uint64_t)__popcll(nm);
+    }
+    // this step's two bucket loads
+    uint32_t x1 = 0, x2 = 0;
+    int vs0 = 0, vs1 = 0;
+    uint64_t vw0 = 0, vw1 = 0;
+    if (st == FRESH) {
+      x1 = address(geo, HashPair<PAIR>::h1(key_of(kv)));
+      x2 = address(geo, HashPair<PAIR>::h2(key_of(kv)));
+    } else if (st == RELOAD) {
+      x1 = b;
+      x2 = b;
+    } else if (st == LOOK) {
+      // two candidate victims at pseudo-random distinct slots (round kick + 1)
+      const uint32_t r = mix32(key_of(kv) ^ ((kick + 1) * 0x9E3779B9u));
+      vs0 = (int)(r & 15u);
+      vs1 = (int)((r + 5u) & 15u);
+      vw0 = w[vs0];
+      vw1 = w[vs1];
+      const uint32_t a1 = address(geo, HashPair<PAIR>::h1(key_of(vw0))), a2 = address(geo, HashPair<PAIR>::h2(key_of(vw0)));
+      const uint32_t b1 = address(geo, HashPair<PAIR>::h1(key_of(vw1))), b2 = address(geo, HashPair<PAIR>::h2(key_of(vw1)));
+      x1 = (b == a1) ? a2 : a1;
+      x2 = (b == b1) ? b2 : b1;
+    }
+    if (st != IDLE) load_bucket16x2_fresh(a.buckets + (uint64_t)x1 * S, a.buckets + (uint64_t)x2 * S, w, w2v);
+    bool fail = false;  // the chain ran out of rounds: step 4
+    if (st == FRESH) {
+      const Mask f1 = (Mask)empty_mask16(w);
+      const Mask f2 = (Mask)empty_mask16(w2v) & (Mask)((x2 != x1) ? ~0ull : 0ull);
+      bool placed;
+      if (popc_mask(f2) > popc_mask(f1))
+        placed = group_claim<S>(a.buckets + (uint64_t)x2 * S, f2, kv, lane, 0) ||
+                 group_claim<S>(a.buckets + (uint64_t)x1 * S, f1, kv, lane, 0);
+      else
+        placed = group_claim<S>(a.buckets + (uint64_t)x1 * S, f1, kv, lane, 0) ||
+                 group_claim<S>(a.buckets + (uint64_t)x2 * S, f2, kv, lane, 0);
+      if (placed) {
+        st = IDLE;
+      } else if (max_kicks == 0) {
+        fail = true;
+      } else {
+        b = x1;  // chains start at the first candidate, whose view w holds
+        st = LOOK;
+      }
+    } else if (st == RELOAD) {
+      st = group_claim<S>(a.buckets + (uint64_t)b * S, (Mask)empty_mask16(w), kv, lane, 0) ? IDLE : LOOK;
+    } else if (st == LOOK) {
+      ++kick;
+      const Mask fa = (Mask)empty_mask16(w) & (Mask)((x1 != b) ? ~0ull : 0ull);
+      const Mask fb = (Mask)empty_mask16(w2v) & (Mask)((x2 != b) ? ~0ull : 0ull);
+      const int pick = (fa == 0 && fb != 0) ? 1 : 0;
+      const Mask fpick = pick ? fb : fa;
+      const uint64_t victim = pick ? vw1 : vw0;
+      const int vsl = pick ? vs1 : vs0;
+      if (cas64(a.buckets + (uint64_t)b * S + vsl, victim, kv) != victim) {
+        // the slot changed: the round is spent, the item stays in hand
+        if (kick < max_kicks) st = RELOAD;
+        else fail = true;
+      } else if (victim == EMPTY) {
+        st = IDLE;  // the slot was empty after all: the CAS claimed it
+      } else {
+        ++n_evict;
+        kv = victim;
+        b = pick ? x2 : x1;
+        if (fpick && group_claim<S>(a.buckets + (uint64_t)b * S, fpick, kv, lane, 0)) {
+          st = IDLE;
+        } else if (kick < max_kicks) {
+          // the next round works from the view just loaded
+          if (pick == 1) {
+#pragma unroll
+            for (int p = 0; p < 16; ++p) w[p] = w2v[p];
+          }
+        } else {
+          fail = true;
+        }
+      }
+    }
+    // step 4 for the chains that ran out of rounds
+    const uint64_t pm = ballot(fail);
+    if (pm) {
+      const int leader = __builtin_ctzll(pm);
+      uint64_t base = 0;
+      if (!unreserved) {
+        if (lane == leader) {
+          const uint64_t n = (uint64_t)__popcll(pm);
+          base = load_fresh(&a.ctl->stash_count) < a.stash_cap ? add64(&a.ctl->stash_count, n) : a.stash_cap;
+        }
+        base = read_lane64(base, leader);
+      }
+      if (fail) {
+        ++n_full;
+        const int where = overflow_place<PAIR>(a, geo, kv, base + rank_below(pm));
+        n_side += (where == 0 || where == 3) ? 1 : where == 1 ? (1ull << 32) : 0;
+        n_fresh += where == 0;
+        st = IDLE;
+      }
+    }
+  }
+  evict_counters(a, unreserved, wid, n_evict, n_full, n_side, n_fresh, 0);
+}
+
 // Step 4 as its own launch (after evict_kernel<.., DEFER>): every worklist
 // word that still holds an entry goes to the stash or the pending list, one
 // entry per lane, with the same room reservation as the fused path.
@@ -3680,9 +3834,31 @@ static void launch_ops_mode(uint32_t mode, const OpsArgs &a, const hive_config &
 // stash and pending capacity for a drain).
 static void phase_mark(hive_table *h, int kind, hipStream_t st);
 
+// Grid of evict_lanes_kernel<PAIR>: a block per 256 possible items, at most
+// as many blocks as are resident at once (a wave's range is not shared).
+template <int PAIR>
+static unsigned evict_lanes_grid(uint64_t max_items) {
+  static const unsigned resident = [] {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, evict_lanes_kernel<PAIR>, BLOCK, 0) != hipSuccess ||
+        cus < 1 || per_cu < 1) {
+      (void)hipGetLastError();
+      return (unsigned)EVICT_GRID;
+    }
+    return (unsigned)std::min(cus * per_cu, EVICT_GRID);
+  }();
+  return (unsigned)std::min<uint64_t>(grid_for(max_items, (uint64_t)BLOCK, EVICT_GRID), resident);
+}
+
 // split_steps (phase timing of a 16-slot BitHash table): steps 3 and 4 in
-// two launches, the second timed as its own phase.
-static void launch_evict(hive_table *h, uint64_t max_items, hipStream_t st, bool split_steps = false) {
+// two launches, the second timed as its own phase.  refill: 16-slot
+// two-hash tables run evict_lanes_kernel (lanes refilled from the wave's
+// range); the re-placement after a split, a few thousand items that each
+// start a chain at once, keeps one item per lane (evict_kernel).
+static void launch_evict(hive_table *h, uint64_t max_items, hipStream_t st, bool split_steps = false,
+                         bool refill = true) {
   EvictArgs e{h->d_buckets, h->d_hint,       h->d_stash,   h->d_pending,   h->d_ctl,
               h->d_wl,      h->wl_seg_cap,   h->stash_cap, h->pending_cap, h->cfg.max_evictions};
   const dim3 grid(grid_for(max_items, (uint64_t)WAVES * evict_groups_per_wave(h->S), EVICT_GRID));
@@ -3695,14 +3871,24 @@ static void launch_evict(hive_table *h, uint64_t max_items, hipStream_t st, bool
   }
   switch (h->S) {
     case 16:
-      if (h->cfg.hash_pair == PAIR_CRC)
-        hipLaunchKernelGGL((evict_kernel<16, PAIR_CRC>), grid, dim3(BLOCK), 0, st, e);
+      if (!refill && h->cfg.hash_pair != PAIR_TRIPLE) {
+        if (h->cfg.hash_pair == PAIR_CRC)
+          hipLaunchKernelGGL((evict_kernel<16, PAIR_CRC>), grid, dim3(BLOCK), 0, st, e);
+        else if (h->cfg.hash_pair == PAIR_MURMUR)
+          hipLaunchKernelGGL((evict_kernel<16, PAIR_MURMUR>), grid, dim3(BLOCK), 0, st, e);
+        else
+          hipLaunchKernelGGL(evict_kernel<16>, grid, dim3(BLOCK), 0, st, e);
+      } else if (h->cfg.hash_pair == PAIR_CRC)
+        hipLaunchKernelGGL(evict_lanes_kernel<PAIR_CRC>, dim3(evict_lanes_grid<PAIR_CRC>(max_items)), dim3(BLOCK),
+                           0, st, e);
       else if (h->cfg.hash_pair == PAIR_MURMUR)
-        hipLaunchKernelGGL((evict_kernel<16, PAIR_MURMUR>), grid, dim3(BLOCK), 0, st, e);
+        hipLaunchKernelGGL(evict_lanes_kernel<PAIR_MURMUR>, dim3(evict_lanes_grid<PAIR_MURMUR>(max_items)),
+                           dim3(BLOCK), 0, st, e);
       else if (h->cfg.hash_pair == PAIR_TRIPLE)
         hipLaunchKernelGGL((evict_kernel<16, PAIR_TRIPLE>), grid, dim3(BLOCK), 0, st, e);
       else
-        hipLaunchKernelGGL(evict_kernel<16>, grid, dim3(BLOCK), 0, st, e);
+        hipLaunchKernelGGL(evict_lanes_kernel<PAIR_BITHASH>, dim3(evict_lanes_grid<PAIR_BITHASH>(max_items)),
+                           dim3(BLOCK), 0, st, e);
       break;
     case 32: hipLaunchKernelGGL(evict_kernel<32>, grid, dim3(BLOCK), 0, st, e); break;
     default: hipLaunchKernelGGL(evict_kernel<64>, grid, dim3(BLOCK), 0, st, e); break;
@@ -3779,7 +3965,7 @@ static hive_status resize_sequence(hive_table *h, uint32_t mode, uint64_t amount
   phase_mark(h, HIVE_PHASE_DRAIN, st);
   hipLaunchKernelGGL(drain_kernel, dim3(DRAIN_GRID), dim3(BLOCK), 0, st, h->d_stash, h->stash_cap, h->d_pending,
                      h->pending_cap, h->d_hint, hint_words(h->max_buckets), h->d_wl, h->wl_seg_cap, h->d_ctl);
-  launch_evict(h, h->stash_cap + h->pending_cap, st);  // live entries of a drain
+  launch_evict(h, h->stash_cap + h->pending_cap, st, false, false);  // live entries of a drain
   launch_finish(h, st);
   return launch_check();
 }
