@@ -363,8 +363,12 @@ __global__ __launch_bounds__(BLOCK) void ddp_collect_kernel(DdpArgs d) {
     if (ty[j] >= 0) d.win[base + (uint64_t)j * BLOCK + threadIdx.x] = 0;
   for (int j = threadIdx.x; j < DD_LDS; j += BLOCK) tab[j] = EMPTY;
   __syncthreads();
+  // slot[j]: the table slot whose key operation j's thread claimed (the
+  // key's first record in this chunk), DD_LDS when it claimed none
+  uint32_t slot[DD_PER_THREAD];
 #pragma unroll
   for (int j = 0; j < DD_PER_THREAD; ++j) {
+    slot[j] = DD_LDS;
     const uint32_t k = kk[j];
     if (ty[j] < 0 || !valid_key(k)) continue;
     const bool keep_last = ddp_op(d, (uint32_t)ty[j]) == OP_INSERT;
@@ -373,7 +377,10 @@ __global__ __launch_bounds__(BLOCK) void ddp_collect_kernel(DdpArgs d) {
       uint64_t cur = tab[s];
       if (cur == EMPTY) {
         cur = atomicCAS((unsigned long long *)&tab[s], (unsigned long long)EMPTY, (unsigned long long)e);
-        if (cur == EMPTY) break;
+        if (cur == EMPTY) {
+          slot[j] = s;
+          break;
+        }
       }
       if ((uint32_t)(cur >> 32) == k) {
         // only an update that can change the word (a hot key's later
@@ -388,61 +395,60 @@ __global__ __launch_bounds__(BLOCK) void ddp_collect_kernel(DdpArgs d) {
     }
   }
   __syncthreads();
-  // compact the chunk's distinct keys to the front of the table, type 0
-  // first, then type 1 (wave by wave, rows in order)
-  constexpr int ROWS = DD_LDS / BLOCK;
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  uint64_t row[ROWS];
-  uint32_t rank[ROWS];
-  uint32_t mine[2] = {0, 0};
+  // each distinct key's record, as the collapse left it, is staged by the
+  // thread that claimed its slot: the claimants' records are read, the
+  // table is then free, and block-wide offsets per type come from a scan of
+  // the per-thread counts (records of a type in thread order)
+  uint64_t rec[DD_PER_THREAD];
+  uint32_t mine0 = 0, mine1 = 0;
 #pragma unroll
-  for (int r = 0; r < ROWS; ++r) {
-    row[r] = tab[r * BLOCK + threadIdx.x];
-    const bool used = row[r] != EMPTY, t1 = ((uint32_t)row[r] >> 31) != 0;
-    const uint64_t m0 = ballot(used && !t1), m1 = ballot(used && t1);
-    rank[r] = t1 ? mine[1] + rank_below(m1) : mine[0] + rank_below(m0);
-    mine[0] += (uint32_t)__popcll(m0);
-    mine[1] += (uint32_t)__popcll(m1);
+  for (int j = 0; j < DD_PER_THREAD; ++j) {
+    rec[j] = slot[j] < DD_LDS ? tab[slot[j]] : EMPTY;
+    if (rec[j] != EMPTY) {
+      if (((uint32_t)rec[j] >> 31) != 0) ++mine1;
+      else ++mine0;
+    }
   }
-  __syncthreads();  // every wave holds its rows in registers: tab may be overwritten
-  // the waves' counts go to the table's last words (a chunk has at most
-  // DD_CHUNK = DD_LDS / 2 distinct keys, so the compacted lists stay clear
-  // of them), keeping the block's LDS at 32 KiB (five blocks per CU)
-  static_assert(DD_CHUNK + 2 * WAVES <= DD_LDS, "wave counts overlap the compacted lists");
-  if (lane == 0) {
-    tab[DD_LDS - 1 - wv] = mine[0];
-    tab[DD_LDS - 1 - WAVES - wv] = mine[1];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  uint32_t in0 = mine0, in1 = mine1;  // inclusive prefixes within the wave
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y0 = __shfl_up(in0, o, 64), y1 = __shfl_up(in1, o, 64);
+    if (lane >= o) {
+      in0 += y0;
+      in1 += y1;
+    }
   }
+  __syncthreads();  // every claimant holds its records: tab may be overwritten
+  // the waves' totals in the table's last words, the partition histograms
+  // (one per type) at its front
+  static_assert(2 * DDP_BINS + 2 * WAVES <= 2 * DD_LDS, "histogram room");
+  uint32_t *words = (uint32_t *)tab;
+  if (lane == 63) {
+    words[2 * DD_LDS - 1 - wv] = in0;
+    words[2 * DD_LDS - 1 - WAVES - wv] = in1;
+  }
+  uint32_t *bins = words;
+  for (int b = threadIdx.x; b < 2 * DDP_BINS; b += BLOCK) bins[b] = 0u;
   __syncthreads();
-  uint32_t off0 = 0, off1 = 0, cnt0 = 0, cnt1 = 0;
+  uint32_t off0 = in0 - mine0, off1 = in1 - mine1, cnt0 = 0, cnt1 = 0;
 #pragma unroll
   for (int w = 0; w < WAVES; ++w) {
-    const uint32_t c0w = (uint32_t)tab[DD_LDS - 1 - w], c1w = (uint32_t)tab[DD_LDS - 1 - WAVES - w];
+    const uint32_t c0w = words[2 * DD_LDS - 1 - w], c1w = words[2 * DD_LDS - 1 - WAVES - w];
     off0 += w < wv ? c0w : 0u;
     off1 += w < wv ? c1w : 0u;
     cnt0 += c0w;
     cnt1 += c1w;
   }
-#pragma unroll
-  for (int r = 0; r < ROWS; ++r)
-    if (row[r] != EMPTY) {
-      const bool t1 = ((uint32_t)row[r] >> 31) != 0;
-      tab[(t1 ? cnt0 + off1 : off0) + rank[r]] = row[r];
-    }
-  __syncthreads();
-  // histograms over the partitions, one per type, in the table's upper half
-  static_assert(DD_CHUNK * 2 >= DDP_BINS && DD_CHUNK + DDP_BINS <= DD_LDS - 2 * WAVES, "histogram room");
-  uint32_t *bins = (uint32_t *)(tab + DD_CHUNK);
-  for (int b = threadIdx.x; b < 2 * DDP_BINS; b += BLOCK) bins[b] = 0u;
-  __syncthreads();
   uint64_t *st0 = d.stage + c * DD_CHUNK, *st1 = d.stage + ((uint64_t)d.nch + c) * DD_CHUNK;
-  for (uint32_t q = threadIdx.x; q < cnt0 + cnt1; q += BLOCK) {
-    const uint64_t t = tab[q];
+#pragma unroll
+  for (int j = 0; j < DD_PER_THREAD; ++j) {
+    if (rec[j] == EMPTY) continue;
+    const uint64_t t = rec[j];
     const uint32_t k = (uint32_t)(t >> 32), i = (uint32_t)(base + ((uint32_t)t & (DD_CHUNK - 1)));
     const uint64_t e = ((uint64_t)k << 32) | i;
-    const bool t1 = q >= cnt0;
-    if (t1) st1[q - cnt0] = e;
-    else st0[q] = e;
+    const bool t1 = ((uint32_t)t >> 31) != 0;
+    if (t1) st1[off1++] = e;
+    else st0[off0++] = e;
     d.win[i] = 1;  // within this chunk's flags
     atomicAdd(&bins[(t1 ? DDP_BINS : 0) + ddp_bin(k)], 1u);
   }
