@@ -266,7 +266,8 @@ const char *hive_status_string(hive_status s);
  * array of HIVE_PHASE_KINDS doubles.  The events are ordered on each call's
  * own stream only.  HIVE_ERR_HIP if waiting for the events failed. */
 enum {
-  HIVE_PHASE_DEDUPE = 0,  /* dedupe set fill and build */
+  HIVE_PHASE_DEDUPE = 0,  /* dedupe of the batch's repeated keys (by hash
+                             partitions: collect, sums, scan, scatter, resolve) */
   HIVE_PHASE_PROBE = 1,   /* probe launch: replace, claim (steps 1-2), lookup, delete */
   HIVE_PHASE_EVICT = 2,   /* eviction chains (step 3); with 16-slot buckets and
                              the BitHash pair, step 4 is timed apart below,
