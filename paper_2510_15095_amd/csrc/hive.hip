@@ -175,6 +175,12 @@ __global__ __launch_bounds__(64) void finish_kernel(Ctl *c) {
   (void)fold_shards_wave(c, true);
 }
 
+// The counters folded with the worklist kept (one wave of 64 threads): the
+// key count of a batch whose worklist is placed after its load-factor rule.
+__global__ __launch_bounds__(64) void fold_kernel(Ctl *c) {
+  (void)fold_shards_wave(c, false);
+}
+
 struct OpsArgs {
   uint64_t *buckets;
   uint32_t *hint;
@@ -3757,6 +3763,16 @@ static uint64_t ddp_layout(uint64_t *base, uint64_t n, uint32_t nt, DdpArgs *d) 
 // plain launches (mixed batches: two types) or the executor's set.
 static uint64_t dd_words_for(uint64_t n) { return std::max(dd_set_words(n), ddp_layout(nullptr, n, 2, nullptr)); }
 
+// Worklist entries a stash drain may append: the whole stash table and the
+// pending list.
+static uint64_t drain_words(const hive_table *h) { return stash_slots_for(h->stash_cap) + h->pending_cap; }
+
+// Added to a worklist that holds a batch's entries and a drain: the probe
+// launch's and the drain's per-segment fills are each bounded by their own
+// rounding of whole tiles per segment, which can exceed the rounding of the
+// sum by up to 4 x NSHARD tiles in all.
+constexpr uint64_t WL_SLACK = 4ull * NSHARD * BLOCK;
+
 static hive_status ensure_scratch(hive_table *h, uint64_t n, uint64_t n_dd, hipStream_t st) {
   if (n > h->wl_cap) {
     HIP_OK(hipStreamSynchronize(st));
@@ -3947,8 +3963,11 @@ static void phase_mark(hive_table *h, int kind, hipStream_t st) {
   h->open_ev = e;
 }
 
+// batch_items > 0: the call follows a batch's probe launch whose eviction
+// worklist (at most batch_items entries) is still to be placed; the
+// drained stash joins it and one eviction launch places both.
 static hive_status resize_sequence(hive_table *h, uint32_t mode, uint64_t amount, const uint8_t *d_ops,
-                                   hipStream_t st) {
+                                   hipStream_t st, uint64_t batch_items = 0) {
   ResizeArgs ra{h->d_buckets, h->d_hint, h->d_ctl, h->S, h->cfg.resize_k, h->cfg.lf_expand_pct,
                 h->cfg.lf_contract_pct};
   phase_mark(h, HIVE_PHASE_RESIZE, st);
@@ -3971,7 +3990,8 @@ static hive_status resize_sequence(hive_table *h, uint32_t mode, uint64_t amount
   phase_mark(h, HIVE_PHASE_DRAIN, st);
   hipLaunchKernelGGL(drain_kernel, dim3(DRAIN_GRID), dim3(BLOCK), 0, st, h->d_stash, h->stash_cap, h->d_pending,
                      h->pending_cap, h->d_hint, hint_words(h->max_buckets), h->d_wl, h->wl_seg_cap, h->d_ctl);
-  launch_evict(h, h->stash_cap + h->pending_cap, st, false, false);  // live entries of a drain
+  // live entries of a drain (and the batch's worklist)
+  launch_evict(h, batch_items + h->stash_cap + h->pending_cap, st, false, batch_items > 0);
   launch_finish(h, st);
   return launch_check();
 }
@@ -4123,8 +4143,17 @@ static hive_status run_batch(hive_t h, uint32_t mode, const uint8_t *d_ops, cons
   if (flags & ~(uint32_t)HIVE_UNIQUE) return HIVE_ERR_ARG;
   hipStream_t st = (hipStream_t)stream;
   const bool dedupe = !(flags & HIVE_UNIQUE) && mode != OP_LOOKUP;
+  const bool linear = h->cfg.addressing == HIVE_LINEAR;
+  const bool inserts = mode == OP_INSERT || mode == OP_MIXED;
+  // A batch with inserts on a table with the post-batch rule places its
+  // eviction worklist after the rule: the splits' stash drain joins the
+  // worklist and one eviction launch places both (the re-placement launch
+  // goes).  The worklist then holds the batch's entries and a full drain.
+  const uint64_t wl_post = n + drain_words(h) + WL_SLACK;
+  const bool post_after = linear && h->cfg.post_policy && inserts && h->entry_bytes == 8 && !h->timing &&
+                          (!no_alloc || wl_post <= h->wl_cap);
   // only inserts reach the eviction worklist
-  const uint64_t wl_need = (mode == OP_INSERT || mode == OP_MIXED) ? n : 0;
+  const uint64_t wl_need = inserts ? (post_after ? wl_post : n) : 0;
   uint64_t *dd = nullptr;
   if (no_alloc) {
     if (wl_need > h->wl_cap) {
@@ -4203,7 +4232,6 @@ static hive_status run_batch(hive_t h, uint32_t mode, const uint8_t *d_ops, cons
     phase_mark(h, -1, st);
     return launch_check();
   }
-  const bool linear = h->cfg.addressing == HIVE_LINEAR;
   if (linear && h->cfg.pre_expand && (mode == OP_INSERT || mode == OP_MIXED)) {
     // grow before the batch so that live + (inserts of the batch) fits
     if ((s = resize_sequence(h, mode == OP_MIXED ? PLAN_PRE_MIXED : PLAN_PRE, n, d_ops, st)) != HIVE_OK) return s;
@@ -4226,6 +4254,12 @@ static hive_status run_batch(hive_t h, uint32_t mode, const uint8_t *d_ops, cons
     default: launch_ops_mode<64, false>(mode, a, h->cfg, st); break;
   }
   if ((s = launch_check()) != HIVE_OK) return s;
+  if (post_after) {
+    hipLaunchKernelGGL(fold_kernel, dim3(1), dim3(64), 0, st, h->d_ctl);
+    if ((s = resize_sequence(h, PLAN_POST, 0, nullptr, st, n)) != HIVE_OK) return s;
+    phase_mark(h, -1, st);
+    return HIVE_OK;
+  }
   if (mode == OP_INSERT || mode == OP_MIXED) {
     phase_mark(h, HIVE_PHASE_EVICT, st);
     launch_evict(h, n, st, h->timing);
@@ -4320,8 +4354,13 @@ hive_status hive_create(const hive_config *cfg_in, uint64_t initial_buckets, voi
   h->last = st;
   // the worklist must hold a full stash + pending drain (after a split);
   // the drain walks the whole stash table
-  const uint64_t min_wl = stash_slots_for(h->stash_cap) + h->pending_cap;
-  if ((s = ensure_scratch(h, std::max<uint64_t>(cfg.max_batch, min_wl), cfg.max_batch, st)) != HIVE_OK) {
+  const uint64_t min_wl = drain_words(h);
+  // a table with the post-batch rule places a batch's worklist after the
+  // rule, together with the drain (see run_batch)
+  const uint64_t batch_wl = cfg.addressing == HIVE_LINEAR && cfg.post_policy && cfg.max_batch
+                                ? cfg.max_batch + min_wl + WL_SLACK
+                                : cfg.max_batch;
+  if ((s = ensure_scratch(h, std::max<uint64_t>(batch_wl, min_wl), cfg.max_batch, st)) != HIVE_OK) {
     free_table(h);
     return s;
   }
