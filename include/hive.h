@@ -83,7 +83,11 @@ typedef struct {
   uint64_t max_buckets;       /* bucket arena reserved at create (LINEAR:
                                  growth headroom; 0 = initial buckets) */
   uint64_t max_batch;         /* scratch preallocated for batches of this many
-                                 operations (0 = grow on demand) */
+                                 operations (0 = grow on demand).  LINEAR
+                                 tables with post_policy also hold a full
+                                 stash drain beside a batch's eviction
+                                 worklist: a batch with inserts is evicted
+                                 once, after the post-batch rule */
   uint32_t probe_both;        /* S = 16: 1 = lookups and deletes load both
                                  candidate buckets in one round (one memory
                                  round trip fewer, more bytes); inserts always
